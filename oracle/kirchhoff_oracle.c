@@ -1,0 +1,275 @@
+/*
+ * Plain FP64 CPU evaluation of the Kirchhoff prestack migration integral.
+ *
+ * TEST INFRASTRUCTURE ONLY.  This file is the oracle that the GPU library is
+ * checked against.  It shares no code, header or table with the library:
+ * only tests, the smoke check and the benchmark's CPU-baseline leg load it.
+ *
+ * What it computes (Section 3, Eq. (1) of "Distributed computing of Seismic
+ * Imaging Algorithms"):
+ *
+ *   I(x, X) = sum over traces j with offset bin X of
+ *             W(x, x_s, x_r) * D_j(t = T(x, x_s) + T(x, x_r)),
+ *
+ * i.e. every trace whose offset |x_s - x_r| falls in bin X contributes, at
+ * every image point x that is close enough (the aperture of Eq. (2)), its
+ * sample at the total propagation time, weighted by W; the image is the sum
+ * of all such contributions (the Reduce step of Section 4 is a plain sum).
+ *
+ * Discretisation (the paper leaves these open; the readings are stated here):
+ *  - T(x, x_s) = sqrt(t0sq[iz] + s2[iz] * h_s^2), h_s the horizontal distance
+ *    between image column and source; t0sq, s2 are per-depth model tables.
+ *  - Aperture: both legs satisfy h^2 <= r2[iz].  The decision is taken in
+ *    float32 with the operation order dx = fl(x - sx), h2 = fl(fl(dx*dx) +
+ *    fl(dy*dy)), so that any float32 implementation can take the identical
+ *    decision; r2 is itself a float32 input.
+ *  - Everything continuous is FP64 (coordinates widened from float32).
+ *  - u = (T_s + T_r - t_first) / dt, i = floor(u), f = u - i and the data value
+ *    is (1 - f) * D[i] + f * D[i + 1] on the trace extended by zeros outside
+ *    [0, n_t).
+ *  - Weight kind 1: W = cos(th_s) cos(th_r) / (T_s T_r) with cos(th) = t0 / T,
+ *    i.e. W = t0sq / (a_s * a_r) where a = T^2; W = 0 when t0sq = 0.
+ *    Weight kind 0: W = 1.
+ *  - The adjoint (demigration) is the exact transpose: each in-aperture pair
+ *    adds (1 - f) W I to D[i] and f W I to D[i + 1] (samples outside [0, n_t)
+ *    are dropped).
+ *
+ * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
+ */
+#include <float.h>
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#include <omp.h>
+
+#if !defined(FLT_EVAL_METHOD) || FLT_EVAL_METHOD != 0
+#error "float arithmetic must be evaluated in float precision for the aperture decision"
+#endif
+
+typedef struct {
+    int64_t n_traces;
+    int32_t n_t;
+    double t_first, dt;
+    const double* data;    /* [n_traces][n_t]; may be NULL for count / adjoint */
+    const float* src;      /* [n_traces][2] (x, y) */
+    const float* rec;      /* [n_traces][2] */
+    const int32_t* bin;    /* [n_traces]; outside [0, n_bins) = trace unused */
+    int32_t nx, ny, nz, n_bins;
+    const float* x;        /* [nx] */
+    const float* y;        /* [ny] */
+    const double* t0sq;    /* [nz] */
+    const double* s2;      /* [nz] */
+    const float* r2;       /* [nz] */
+    int32_t weight;        /* 0: W = 1; 1: W = t0sq / (a_s a_r) */
+} ko_problem;
+
+/* Aperture decision in float32 (see header). */
+static int ko_in_aperture(float px, float py, float sx, float sy, float rx, float ry, float r2)
+{
+    float dxs = px - sx, dys = py - sy;
+    float dxr = px - rx, dyr = py - ry;
+    float hs2 = dxs * dxs + dys * dys;
+    float hr2 = dxr * dxr + dyr * dyr;
+    return hs2 <= r2 && hr2 <= r2;
+}
+
+/* One (trace, image point) pair.  Returns 0 when the pair is outside the
+ * aperture; otherwise sets *u (fractional sample index) and *w (weight). */
+static int ko_pair(const ko_problem* P, int64_t j, int ix, int iy, int iz, double* u, double* w)
+{
+    const float px = P->x[ix], py = P->y[iy];
+    const float sx = P->src[2 * j], sy = P->src[2 * j + 1];
+    const float rx = P->rec[2 * j], ry = P->rec[2 * j + 1];
+    if (!ko_in_aperture(px, py, sx, sy, rx, ry, P->r2[iz])) return 0;
+    double hs2 = ((double)px - sx) * ((double)px - sx) + ((double)py - sy) * ((double)py - sy);
+    double hr2 = ((double)px - rx) * ((double)px - rx) + ((double)py - ry) * ((double)py - ry);
+    double a_s = P->t0sq[iz] + P->s2[iz] * hs2;
+    double a_r = P->t0sq[iz] + P->s2[iz] * hr2;
+    double T = sqrt(a_s) + sqrt(a_r);
+    *u = (T - P->t_first) / P->dt;
+    if (P->weight == 1)
+        *w = P->t0sq[iz] > 0.0 ? P->t0sq[iz] / (a_s * a_r) : 0.0;
+    else
+        *w = 1.0;
+    return 1;
+}
+
+/* Zero-extended linear interpolation of trace row d at fractional index u. */
+static double ko_sample(const double* d, int32_t n_t, double u)
+{
+    if (!(u > -1.0 && u < (double)n_t)) return 0.0;
+    double fl = floor(u);
+    int64_t i = (int64_t)fl;
+    double f = u - fl;
+    double d0 = (i >= 0 && i < n_t) ? d[i] : 0.0;
+    double d1 = (i + 1 >= 0 && i + 1 < n_t) ? d[i + 1] : 0.0;
+    return (1.0 - f) * d0 + f * d1;
+}
+
+static int ko_check(const ko_problem* P)
+{
+    if (!P || P->n_traces < 0 || P->n_t < 0 || P->nx < 0 || P->ny < 0 || P->nz < 0 || P->n_bins < 0) return 1;
+    if (!(P->dt > 0.0)) return 1;
+    return 0;
+}
+
+/* Image columns (b, iy, ix) listed in cols[3*c .. 3*c+2]; out[c][iz], nz values each. */
+int oracle_migrate_columns(const ko_problem* P, int64_t n_cols, const int32_t* cols, double* out)
+{
+    if (ko_check(P) || !P->data) return 1;
+    const int32_t nz = P->nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < n_cols; ++c) {
+        const int b = cols[3 * c], iy = cols[3 * c + 1], ix = cols[3 * c + 2];
+        double* o = out + c * (int64_t)nz;
+        for (int iz = 0; iz < nz; ++iz) o[iz] = 0.0;
+        for (int64_t j = 0; j < P->n_traces; ++j) {
+            if (P->bin[j] != b) continue;
+            const double* d = P->data + j * (int64_t)P->n_t;
+            for (int iz = 0; iz < nz; ++iz) {
+                double u, w;
+                if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+                o[iz] += w * ko_sample(d, P->n_t, u);
+            }
+        }
+    }
+    return 0;
+}
+
+/* Full image I[n_bins][ny][nx][nz] (overwritten). */
+int oracle_migrate(const ko_problem* P, double* image)
+{
+    if (ko_check(P) || !P->data) return 1;
+    int64_t n_cols = (int64_t)P->n_bins * P->ny * P->nx;
+    int32_t* cols = (int32_t*)malloc(sizeof(int32_t) * 3 * (size_t)(n_cols > 0 ? n_cols : 1));
+    if (!cols) return 2;
+    int64_t c = 0;
+    for (int b = 0; b < P->n_bins; ++b)
+        for (int iy = 0; iy < P->ny; ++iy)
+            for (int ix = 0; ix < P->nx; ++ix) {
+                cols[3 * c] = b; cols[3 * c + 1] = iy; cols[3 * c + 2] = ix; ++c;
+            }
+    int rc = oracle_migrate_columns(P, n_cols, cols, image);
+    free(cols);
+    return rc;
+}
+
+/* Single image points pts[4*k .. 4*k+3] = (b, iy, ix, iz) -> out[k]. */
+int oracle_migrate_points(const ko_problem* P, int64_t n_pts, const int32_t* pts, double* out)
+{
+    if (ko_check(P) || !P->data) return 1;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n_pts; ++k) {
+        const int b = pts[4 * k], iy = pts[4 * k + 1], ix = pts[4 * k + 2], iz = pts[4 * k + 3];
+        double acc = 0.0;
+        for (int64_t j = 0; j < P->n_traces; ++j) {
+            if (P->bin[j] != b) continue;
+            double u, w;
+            if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+            acc += w * ko_sample(P->data + j * (int64_t)P->n_t, P->n_t, u);
+        }
+        out[k] = acc;
+    }
+    return 0;
+}
+
+/* Adjoint: data[n_traces][n_t] (overwritten) from image[n_bins][ny][nx][nz]. */
+int oracle_demigrate(const ko_problem* P, const double* image, double* data)
+{
+    if (ko_check(P)) return 1;
+    const int32_t nt = P->n_t, nz = P->nz;
+#pragma omp parallel for schedule(dynamic, 16)
+    for (int64_t j = 0; j < P->n_traces; ++j) {
+        double* d = data + j * (int64_t)nt;
+        for (int k = 0; k < nt; ++k) d[k] = 0.0;
+        const int b = P->bin[j];
+        if (b < 0 || b >= P->n_bins) continue;
+        for (int iy = 0; iy < P->ny; ++iy)
+            for (int ix = 0; ix < P->nx; ++ix) {
+                const double* m = image + (((int64_t)b * P->ny + iy) * P->nx + ix) * nz;
+                for (int iz = 0; iz < nz; ++iz) {
+                    double u, w;
+                    if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+                    if (!(u > -1.0 && u < (double)nt)) continue;
+                    double fl = floor(u);
+                    int64_t i = (int64_t)fl;
+                    double f = u - fl;
+                    double val = w * m[iz];
+                    if (i >= 0) d[i] += (1.0 - f) * val;
+                    if (i + 1 < nt) d[i + 1] += f * val;
+                }
+            }
+    }
+    return 0;
+}
+
+/* Adjoint at single samples smp[2*k], smp[2*k+1] = (trace j, sample n) -> out[k]. */
+int oracle_demigrate_samples(const ko_problem* P, const double* image, int64_t n_smp, const int64_t* smp,
+                             double* out)
+{
+    if (ko_check(P)) return 1;
+    const int32_t nt = P->n_t, nz = P->nz;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t k = 0; k < n_smp; ++k) {
+        const int64_t j = smp[2 * k];
+        const int64_t n = smp[2 * k + 1];
+        const int b = P->bin[j];
+        double acc = 0.0;
+        if (b >= 0 && b < P->n_bins)
+            for (int iy = 0; iy < P->ny; ++iy)
+                for (int ix = 0; ix < P->nx; ++ix) {
+                    const double* m = image + (((int64_t)b * P->ny + iy) * P->nx + ix) * nz;
+                    for (int iz = 0; iz < nz; ++iz) {
+                        double u, w;
+                        if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+                        if (!(u > -1.0 && u < (double)nt)) continue;
+                        double fl = floor(u);
+                        int64_t i = (int64_t)fl;
+                        double f = u - fl;
+                        if (i == n) acc += (1.0 - f) * w * m[iz];
+                        if (i + 1 == n) acc += f * w * m[iz];
+                    }
+                }
+        out[k] = acc;
+    }
+    return 0;
+}
+
+/* Pair counts of Eq. (2): n_aperture = pairs (trace, image point of the
+ * trace's bin) passing the aperture test; n_effective = those whose time
+ * also falls inside the zero-extended record, -1 < u < n_t. */
+int oracle_count(const ko_problem* P, int64_t* n_aperture, int64_t* n_effective)
+{
+    if (ko_check(P)) return 1;
+    int64_t na = 0, ne = 0;
+    const int32_t nt = P->n_t;
+#pragma omp parallel for schedule(dynamic, 16) reduction(+ : na, ne)
+    for (int64_t j = 0; j < P->n_traces; ++j) {
+        const int b = P->bin[j];
+        if (b < 0 || b >= P->n_bins) continue;
+        for (int iy = 0; iy < P->ny; ++iy)
+            for (int ix = 0; ix < P->nx; ++ix)
+                for (int iz = 0; iz < P->nz; ++iz) {
+                    double u, w;
+                    if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+                    ++na;
+                    if (u > -1.0 && u < (double)nt) ++ne;
+                }
+    }
+    *n_aperture = na;
+    *n_effective = ne;
+    return 0;
+}
+
+/* Number of OpenMP threads a parallel region would use. */
+int oracle_threads(void)
+{
+    int n = 1;
+#pragma omp parallel
+    {
+#pragma omp single
+        n = omp_get_num_threads();
+    }
+    return n;
+}
