@@ -1,0 +1,175 @@
+"""Benchmark: Kirchhoff migration + adjoint on the 3D v(z) survey, one MI355X.
+
+Workload (synthetic, seeded): 200 000 traces x 1500 samples (4 ms) on 10 x 10
+shots with 40 x 50 receiver patches over 5 x 5 km, v = 1500 + 0.5 z with
+straight-ray RMS traveltimes; image 256 x 256 x 400 (12.5 / 12.5 / 5 m) in
+16 offset bins; aperture 60 degrees; weight cos*cos/(Ts*Tr); float32.
+
+One step = migration of the traces into the 16 offset images followed by
+demigration (the adjoint) of that image back into 200 000 traces; inputs are
+resident in HBM before timing.  The unit of work is one (trace, image point)
+pair inside the aperture (Eq. (2)), counted exactly by the counting kernel;
+value = 2 * pairs / step time.
+
+Also reported: a roofline object for the dominant kernel (VALU bound; the
+transcendental issue cost is measured live by the issue-rate probe) and the
+FP64 oracle timed on this host's cores on a bounded sample of image columns,
+whose GPU values are checked against the oracle on the way.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes/clk (4 SIMD16) x 2.4 GHz, unpacked issue
+C_FULL = 9  # full-rate VALU lane-ops per pair (roofline)
+C_TRANS = 3  # transcendentals per pair: 2 square roots + 1 reciprocal
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--tile", type=int, default=-1, help="migrate tile shape (-1: library choice)")
+    ap.add_argument("--dtile", type=int, default=-1, help="demigrate tile shape (-1: library choice)")
+    ap.add_argument("--cpu-columns", type=int, default=1536, help="image columns in the oracle sample")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is design-only "
+                                   "(image-column sharding, see DESIGN.md)", "n_gpus": args.gpus}))
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    from paper_1204_1225_amd import _lib, ops, survey
+
+    assert torch.cuda.is_available(), "bench.py needs a ROCm GPU"
+    _lib.load()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+
+    t0 = time.time()
+    p = survey.make_survey3d(seed=2, device=dev)
+    dp = ops.to_device(p, dev)
+    torch.cuda.synchronize()
+    log(f"generated workload in {time.time() - t0:.1f} s: {p.n_traces} traces x {p.n_t} samples, "
+        f"image {p.image_shape}")
+    n_ap, n_eff = ops.count(dp)
+    log(f"pairs in aperture {n_ap:.4e}, inside record {n_eff:.4e}")
+
+    image = torch.empty(dp.image_shape, dtype=torch.float32, device=dev)
+    traces_out = torch.empty((dp.n_traces, dp.n_t), dtype=torch.float32, device=dev)
+
+    def step():
+        ops.migrate(dp, image=image, tile=args.tile)
+        ops.demigrate(dp, image, out=traces_out, tile=args.dtile)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log("warmup done")
+
+    s = torch.cuda.current_stream(dev)
+    ev = [[torch.cuda.Event(enable_timing=True) for _ in range(3)] for _ in range(args.steps)]
+    start, stop = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    wall0 = time.perf_counter()
+    start.record(s)
+    for k in range(args.steps):
+        ev[k][0].record(s)
+        ops.migrate(dp, image=image, tile=args.tile)
+        ev[k][1].record(s)
+        ops.demigrate(dp, image, out=traces_out, tile=args.dtile)
+        ev[k][2].record(s)
+    stop.record(s)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - wall0
+    ms_total = start.elapsed_time(stop)
+    ms_mig = float(np.mean([e[0].elapsed_time(e[1]) for e in ev]))
+    ms_dem = float(np.mean([e[1].elapsed_time(e[2]) for e in ev]))
+    ms_step = ms_total / args.steps
+    log(f"step {ms_step:.1f} ms (migrate {ms_mig:.1f} ms, demigrate {ms_dem:.1f} ms), wall {wall:.2f} s")
+
+    # transcendental issue cost r (in full-rate slots) from the issue-rate probe
+    t_fma = ops.probe_issue(0)
+    t_sqrt = ops.probe_issue(1)
+    t_rcp = ops.probe_issue(2)
+    r = 0.5 * (t_sqrt + t_rcp) / t_fma
+    c_k = C_FULL + C_TRANS * r
+    dom_ms, dom = (ms_mig, "migrate") if ms_mig >= ms_dem else (ms_dem, "demigrate")
+    achieved = n_ap * c_k / (dom_ms * 1e-3) / 1e12
+    peak = PEAK_VALU_LANE_OPS / 1e12
+    roofline = {"bound": "alu", "achieved": round(achieved, 3), "peak": round(peak, 3), "unit": "TFLOP/s",
+                "frac": round(achieved / peak, 4), "traffic": None, "kernel": dom,
+                "ops_per_pair": round(c_k, 3), "transcendental_cost_slots": round(r, 3),
+                "kernel_ms": round(dom_ms, 3)}
+
+    cpu = None
+    parity = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        if not os.path.exists(os.path.join(ROOT, "oracle", "liboracle.so")):
+            oracle.build(force=False)
+        rng = np.random.default_rng(0)
+        per_bin = max(1, args.cpu_columns // p.n_bins)
+        cols = np.array([(b, int(iy), int(ix)) for b in range(p.n_bins)
+                         for iy, ix in zip(rng.integers(0, p.ny, per_bin), rng.integers(0, p.nx, per_bin))],
+                        dtype=np.int32)
+        host = dict(data=dp.data.cpu().numpy())
+        log(f"oracle sample: {len(cols)} image columns x {p.nz} depths, all traces of their bins")
+        c_ap, _ = oracle.count_columns(p, cols)
+        tc = time.perf_counter()
+        ref = oracle.migrate_columns(p, cols, data=host["data"])
+        t_cpu = time.perf_counter() - tc
+        cores = oracle.threads()
+        got = image[cols[:, 0], cols[:, 1], cols[:, 2]].double().cpu().numpy()
+        parity = float(np.linalg.norm(got - ref) / np.linalg.norm(ref))
+        log(f"oracle: {t_cpu:.1f} s on {cores} threads; GPU vs oracle on the sample: rel L2 {parity:.3e}")
+        cpu = {"value": round(c_ap / t_cpu / 1e9, 6), "unit": "G contributions/s", "cores": cores,
+               "kind": "oracle", "sample": f"migrate only: {len(cols)} random image columns ({per_bin} per bin) "
+                                           f"x {p.nz} depths against all traces of their bins "
+                                           f"({c_ap:.3e} pairs in aperture, {t_cpu:.1f} s)"}
+
+    value = 2.0 * n_ap / (ms_step * 1e-3) / 1e9
+    out = {
+        "metric": "G image-point·trace contributions/s (migrate + adjoint) and % of roofline",
+        "value": round(value, 3),
+        "unit": "G contributions/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(ms_step, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "survey3d_vz: 200000 traces x 1500 samples, image 256x256x400 in 16 offset bins, "
+                               "v=1500+0.5z RMS, aperture 60 deg; step = migrate + demigrate",
+                   "pairs_in_aperture": n_ap, "pairs_inside_record": n_eff},
+        "migrate_gcps": round(n_ap / (ms_mig * 1e-3) / 1e9, 3),
+        "demigrate_gcps": round(n_ap / (ms_dem * 1e-3) / 1e9, 3),
+        "roofline": roofline,
+        "cpu_baseline": cpu,
+        "parity_sample_rel_l2": parity,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

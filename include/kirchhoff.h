@@ -1,0 +1,222 @@
+/*
+ * kirchhoff.h - C ABI of libkirchhoff.so: Kirchhoff prestack migration and
+ * its adjoint on AMD Instinct MI355X (gfx950).
+ *
+ * The operator is Eq. (1) of "Distributed computing of Seismic Imaging
+ * Algorithms" (Section 3):
+ *
+ *   I(x, X) = integral dx_s dx_r W(x, x_s, x_r) delta(X - |x_s - x_r|)
+ *                    D(x_s, x_r, t = T(x, x_s) + T(x, x_r)),
+ *
+ * discretised as a sum over recorded traces: every trace of offset bin X adds,
+ * at every image point x inside the migration aperture ("traces close enough",
+ * Eq. (2)), W times its sample at the total propagation time, linearly
+ * interpolated on the trace extended by zeros.  The image is the plain sum of
+ * all contributions (Section 4, Reduce = sum).
+ *
+ * Discretisation used by every entry point:
+ *   - trace j: source src[j] = (sx, sy), receiver rec[j] = (rx, ry) in metres,
+ *     offset bin bin[j], samples D_j[k] at t = t_first + k * dt, k < n_samples;
+ *   - image point (b, iy, ix, iz): column (x[ix], y[iy]), depth index iz;
+ *     image layout I[n_bins][ny][nx][nz], depth fastest;
+ *   - traveltime model (per-depth tables): T = sqrt(t0sq[iz] + s2[iz] * h^2),
+ *     h the horizontal distance from the column to the source or receiver;
+ *   - aperture: both legs satisfy h^2 <= r2[iz], with h^2 evaluated in float32
+ *     as fl(fl(dx*dx) + fl(dy*dy)), dx = fl(x - sx) (an exact, reproducible
+ *     decision shared with any float32 checker);
+ *   - u = (T_s + T_r - t_first) / dt, i = floor(u), f = u - i,
+ *     value = (1 - f) D[i] + f D[i + 1] with D = 0 outside [0, n_samples);
+ *   - weight KM_W_COSCOS_OVER_TT: W = cos(th_s) cos(th_r) / (T_s T_r) with
+ *     cos(th) = t0 / T, i.e. W = t0sq / (T_s^2 T_r^2); 0 where t0sq <= 0.
+ *     KM_W_UNIT: W = 1.
+ *
+ * Conventions for all entry points:
+ *   - Pointers are DEVICE pointers unless the comment says "host".  The caller
+ *     owns every buffer; the library keeps no reference after a call returns,
+ *     except inside a km_batch handle (see there).
+ *   - Calls are asynchronous on the given HIP stream (a hipStream_t passed as
+ *     void*, NULL = default stream) and never synchronise the device, unless
+ *     stated.
+ *   - Arguments are validated on the host before anything is launched.  On a
+ *     non-KM_OK status nothing was launched and outputs are untouched; the
+ *     status and a message (km_last_error, per thread) describe the problem.
+ *   - Nothing aborts or throws across the ABI.  Entry points are re-entrant;
+ *     concurrent calls that write the same output buffer race.
+ */
+#ifndef KIRCHHOFF_H
+#define KIRCHHOFF_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KM_ABI_VERSION 1
+
+typedef enum km_status {
+    KM_OK = 0,
+    KM_E_INVALID = 1,     /* bad argument (null pointer, size, enum, layout) */
+    KM_E_UNSUPPORTED = 2, /* valid but not supported (e.g. 16-bit demigrate output, record too long) */
+    KM_E_HIP = 3,         /* a HIP runtime call failed; km_last_error has its message */
+    KM_E_NOMEM = 4        /* a library-owned allocation failed (batch handles only) */
+} km_status;
+
+typedef enum km_dtype { KM_F32 = 0, KM_BF16 = 1, KM_F16 = 2 } km_dtype;
+
+typedef enum km_weight_kind { KM_W_UNIT = 0, KM_W_COSCOS_OVER_TT = 1 } km_weight_kind;
+
+/* Recorded traces D(x_s, x_r, t) (Section 2: one trace per source/receiver
+ * pair, P samples each). */
+typedef struct km_traces {
+    int64_t n_traces;      /* >= 0 */
+    int32_t n_samples;     /* samples per trace, 0 <= n_samples <= km_max_samples() */
+    int32_t dtype;         /* km_dtype of data */
+    int64_t trace_stride;  /* elements between the starts of consecutive traces, >= n_samples */
+    double t_first;        /* time of sample 0 in seconds (finite) */
+    double dt;             /* sample interval in seconds (> 0, finite) */
+    void* data;            /* [n_traces][trace_stride] elements of dtype; read by migrate, written by demigrate */
+    const float* scale;    /* [n_traces] per-trace factor for KM_BF16 / KM_F16 (sample = stored * scale);
+                              NULL means 1; must be NULL for KM_F32 */
+    const float* src;      /* [n_traces][2] source (x, y), metres */
+    const float* rec;      /* [n_traces][2] receiver (x, y), metres */
+    const int32_t* bin;    /* [n_traces] offset bin, NONDECREASING in j (traces grouped by bin);
+                              a trace whose bin is outside [0, n_bins) contributes nothing.
+                              Unsorted bins are not detected: traces out of order are then missed. */
+} km_traces;
+
+/* Image grid: columns (x[ix], y[iy]) and n_bins offset bins (the X of I(x, X)). */
+typedef struct km_grid {
+    int32_t nx, ny, nz, n_bins;  /* >= 0 each; nx * ny < 2^31 */
+    const float* x;              /* [nx] metres */
+    const float* y;              /* [ny] metres (a single 0 for a 2D line) */
+} km_grid;
+
+/* Traveltime and aperture model, per image depth index (T(x, x_s) "in the
+ * model", Section 3), float32. */
+typedef struct km_traveltime {
+    const float* t0sq;  /* [nz] squared one-way vertical time, s^2 */
+    const float* s2;    /* [nz] squared slowness for horizontal distance, s^2 / m^2 */
+    const float* r2;    /* [nz] aperture: largest squared horizontal leg length, m^2 */
+} km_traveltime;
+
+/* Amplitude weight W(x, x_s, x_r) of Eq. (1). */
+typedef struct km_weight {
+    int32_t kind;  /* km_weight_kind */
+} km_weight;
+
+/* Library ABI version (KM_ABI_VERSION of the build). */
+int km_abi_version(void);
+
+/* Message describing the last non-KM_OK status returned to this thread
+ * ("" if none).  The pointer stays valid until the next call on this thread. */
+const char* km_last_error(void);
+
+/* Longest record (n_samples) the kernels accept. */
+int32_t km_max_samples(void);
+
+/* Migration, Eq. (1): image[n_bins][ny][nx][nz] (float32) from traces.
+ * accumulate = 0 overwrites the image; 1 adds into it (Reduce = sum,
+ * Section 4, so migrating trace subsets with accumulate = 1 sums them).
+ * tile: -1 = library choice (tuned shape if km_tune_migrate recorded one for
+ * this shape class, else a default); otherwise an index < km_tile_count(0).
+ * Work: one float32 evaluation per (trace, image point of its bin) pair that
+ * passes the aperture test. */
+km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                            const km_weight* weight, float* image, int32_t accumulate, int32_t tile,
+                            void* stream);
+
+/* Demigration (Kirchhoff modelling): the exact transpose of kirchhoff_migrate
+ * for the same traces geometry, grid, model and weight.  Each in-aperture
+ * pair adds (1 - f) W I to D[i] and f W I to D[i + 1]; samples outside
+ * [0, n_samples) are dropped.  out->data (float32 only; KM_E_UNSUPPORTED
+ * otherwise) is overwritten (accumulate = 0) or added into (1).  Uses the
+ * same per-pair aperture, time and weight evaluation as kirchhoff_migrate,
+ * so <migrate(d), m> = <d, demigrate(m)> up to float32 summation rounding.
+ * Within a trace, floating-point summation order is not fixed. */
+km_status kirchhoff_demigrate(const float* image, const km_grid* grid, const km_traveltime* tt,
+                              const km_weight* weight, const km_traces* out, int32_t accumulate,
+                              int32_t tile, void* stream);
+
+/* Pair counts of Eq. (2) (f_K N_xyz N_tr with N_tr the traces close enough):
+ * counts[0] = pairs passing the aperture test, counts[1] = those whose time
+ * also falls inside the zero-extended record (-1 < u < n_samples, u in the
+ * kernels' float32).  counts: device int64[2], overwritten. */
+km_status km_count_contributions(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                                 int64_t* counts, void* stream);
+
+/* out[0] = sum_k a[k] * b[k] accumulated in float64 (products exact in
+ * float64); device double[1], overwritten.  Used for the adjoint
+ * dot-product test and least-squares scalars.  Summation order not fixed. */
+km_status km_dot_f64(const float* a, const float* b, int64_t n, double* out, void* stream);
+
+/* y[k] = alpha * x[k] + beta * y[k] in float32 (alpha, beta rounded to float32
+ * once).  x may equal y. */
+km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t n, void* stream);
+
+/* ---- tile shapes and tuning ------------------------------------------------
+ * op: 0 = migrate, 1 = demigrate. */
+typedef struct km_tile_info {
+    int32_t waves;            /* wavefronts (64 lanes) per workgroup */
+    int32_t column_groups;    /* groups of 4 image columns per wavefront */
+    int32_t depth_slots;      /* 16-depth slots held per lane (depth chunk = 16 * depth_slots) */
+    int32_t lds_budget;       /* bytes of LDS the trace block may use */
+} km_tile_info;
+
+int32_t km_tile_count(int32_t op);
+km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out /* host */);
+
+/* Time every tile shape of op on this problem (each run once untimed, then
+ * `reps` times), keep the fastest for its shape class
+ * (op, dtype, depth-count bucket, sample-count bucket) and return it.
+ * Synchronises the stream.  Writes the output buffer (image for op 0,
+ * out->data for op 1) with accumulate = 0 semantics.  best_ms: host, may be NULL. */
+km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                  const km_weight* weight, float* image, int32_t reps, void* stream,
+                  int32_t* best_tile /* host */, float* best_ms /* host */);
+
+/* Shape-class cache of km_tune (so callers can persist it).  km_tune_lookup
+ * returns -1 when no shape is recorded. */
+int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples);
+km_status km_tune_record(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples, int32_t tile);
+
+/* ---- batched migration ------------------------------------------------------
+ * Many independent problems (e.g. uneven 2D lines) migrated by ONE persistent
+ * kernel launch that pulls (problem, bin, column tile, depth chunk) work items
+ * from a queue ordered longest first; the launch is captured once into a HIP
+ * graph.  The handle keeps the device pointers of every problem: they must
+ * stay valid, and keep their shapes, until km_batch_destroy.  Only float32 or
+ * 16-bit traces and accumulate = 0 semantics (every image is overwritten). */
+typedef struct km_problem {
+    km_traces traces;
+    km_grid grid;
+    km_traveltime tt;
+    km_weight weight;
+    float* image;
+} km_problem;
+
+typedef struct km_batch km_batch;
+
+/* probs: host array of n problems.  tile: as for kirchhoff_migrate (one shape
+ * for the whole batch).  Work-item costs are measured with the counting
+ * kernel on `stream` (the call synchronises it).  Allocates device memory for
+ * the problem table and queue (KM_E_NOMEM on failure). */
+km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void* stream, km_batch** out);
+/* Replay the captured graph on stream (asynchronous). */
+km_status km_batch_run(km_batch* batch, void* stream);
+/* Work items and persistent workgroups of the batch (host outputs, may be NULL). */
+km_status km_batch_info(const km_batch* batch, int64_t* n_items, int32_t* n_workgroups);
+/* Releases the graph and device memory (synchronises the device first). */
+km_status km_batch_destroy(km_batch* batch);
+
+/* ---- measurement ----------------------------------------------------------
+ * Issue-rate microbenchmark: ms for `iters` iterations of 8 independent
+ * dependency chains of one instruction kind over `n_waves` wavefronts
+ * (kind 0 = v_fma_f32, 1 = v_sqrt_f32, 2 = v_rcp_f32).  Synchronises. */
+km_status km_probe_issue(int32_t kind, int32_t n_waves, int32_t iters, void* stream, float* ms /* host */);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KIRCHHOFF_H */

@@ -64,6 +64,7 @@ def _load():
         lib.oracle_demigrate.argtypes = [P, vp, vp]
         lib.oracle_demigrate_samples.argtypes = [P, vp, i64, vp, vp]
         lib.oracle_count.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
+        lib.oracle_count_columns.argtypes = [P, i64, vp, vp]
         lib.oracle_threads.argtypes = []
         _lib = lib
     return _lib
@@ -169,6 +170,16 @@ def count(p):
     if _load().oracle_count(b.ref, ctypes.byref(na), ctypes.byref(ne)) != 0:
         raise ValueError("oracle_count rejected the problem")
     return int(na.value), int(ne.value)
+
+
+def count_columns(p, cols):
+    """(n_aperture, n_effective) over image columns cols[k] = (bin, iy, ix)."""
+    b = _Bound(p, need_data=False)
+    cols = _arr(cols, np.int32).reshape(-1, 3)
+    out = np.zeros(2, dtype=np.int64)
+    if _load().oracle_count_columns(b.ref, cols.shape[0], cols.ctypes.data, out.ctypes.data) != 0:
+        raise ValueError("oracle_count_columns rejected the problem")
+    return int(out[0]), int(out[1])
 
 
 def threads() -> int:

@@ -262,6 +262,31 @@ int oracle_count(const ko_problem* P, int64_t* n_aperture, int64_t* n_effective)
     return 0;
 }
 
+/* Eq. (2) pair counts restricted to image columns cols[3*c..3*c+2] = (b, iy, ix):
+ * out[0] = pairs passing the aperture test, out[1] = of those, -1 < u < n_t. */
+int oracle_count_columns(const ko_problem* P, int64_t n_cols, const int32_t* cols, int64_t* out)
+{
+    if (ko_check(P)) return 1;
+    int64_t na = 0, ne = 0;
+    const int32_t nt = P->n_t;
+#pragma omp parallel for schedule(dynamic, 1) reduction(+ : na, ne)
+    for (int64_t c = 0; c < n_cols; ++c) {
+        const int b = cols[3 * c], iy = cols[3 * c + 1], ix = cols[3 * c + 2];
+        for (int64_t j = 0; j < P->n_traces; ++j) {
+            if (P->bin[j] != b) continue;
+            for (int iz = 0; iz < P->nz; ++iz) {
+                double u, w;
+                if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+                ++na;
+                if (u > -1.0 && u < (double)nt) ++ne;
+            }
+        }
+    }
+    out[0] = na;
+    out[1] = ne;
+    return 0;
+}
+
 /* Number of OpenMP threads a parallel region would use. */
 int oracle_threads(void)
 {

@@ -1,0 +1,573 @@
+// C ABI of libkirchhoff.so (declared in include/kirchhoff.h): argument
+// validation, tile-shape choice, the shape-class tuning cache and the batched
+// hipGraph handle.  All device work is in the km_*.hip kernel files.
+#include "kirchhoff.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdarg>
+#include <cstdio>
+#include <map>
+#include <mutex>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "km_kernels.h"
+
+namespace {
+
+thread_local std::string g_last_error;
+
+km_status fail(km_status st, const char* fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof(buf), fmt, ap);
+    va_end(ap);
+    g_last_error = buf;
+    return st;
+}
+
+km_status hip_fail(hipError_t e, const char* what) {
+    return fail(KM_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
+}
+
+constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
+constexpr int kMaxTracesPerBlock = 32;
+constexpr int kLeadPad = 1, kTailPad = 2;
+
+bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
+
+km_status check_traces(const km_traces* t, bool need_samples, const char* who) {
+    if (!t) return fail(KM_E_INVALID, "%s: traces is NULL", who);
+    if (t->n_traces < 0) return fail(KM_E_INVALID, "%s: n_traces < 0", who);
+    if (t->n_samples < 0) return fail(KM_E_INVALID, "%s: n_samples < 0", who);
+    if (t->n_samples > km_max_samples())
+        return fail(KM_E_UNSUPPORTED, "%s: n_samples %d exceeds km_max_samples() = %d", who, t->n_samples,
+                    km_max_samples());
+    if (t->trace_stride < t->n_samples) return fail(KM_E_INVALID, "%s: trace_stride < n_samples", who);
+    if (t->dtype != KM_F32 && t->dtype != KM_BF16 && t->dtype != KM_F16)
+        return fail(KM_E_INVALID, "%s: unknown dtype %d", who, t->dtype);
+    if (!(t->dt > 0.0) || !std::isfinite(t->dt)) return fail(KM_E_INVALID, "%s: dt must be finite and > 0", who);
+    if (!std::isfinite(t->t_first)) return fail(KM_E_INVALID, "%s: t_first must be finite", who);
+    if (std::fabs(t->t_first / t->dt) > 1.0e7) return fail(KM_E_UNSUPPORTED, "%s: |t_first / dt| > 1e7", who);
+    if (t->dtype == KM_F32 && t->scale) return fail(KM_E_INVALID, "%s: scale must be NULL for KM_F32", who);
+    if (t->n_traces > 0) {
+        if (!t->src || !t->rec || !t->bin) return fail(KM_E_INVALID, "%s: src, rec and bin must be non-NULL", who);
+        if (!aligned(t->src, 4) || !aligned(t->rec, 4) || !aligned(t->bin, 4))
+            return fail(KM_E_INVALID, "%s: src, rec, bin must be 4-byte aligned", who);
+        if (need_samples && t->n_samples > 0) {
+            if (!t->data) return fail(KM_E_INVALID, "%s: data is NULL", who);
+            if (!aligned(t->data, t->dtype == KM_F32 ? 4 : 2))
+                return fail(KM_E_INVALID, "%s: data is misaligned for its dtype", who);
+            if (t->trace_stride > 0 && t->n_traces > INT64_MAX / t->trace_stride)
+                return fail(KM_E_INVALID, "%s: n_traces * trace_stride overflows", who);
+        }
+        if (t->scale && !aligned(t->scale, 4)) return fail(KM_E_INVALID, "%s: scale misaligned", who);
+    }
+    return KM_OK;
+}
+
+km_status check_grid(const km_grid* g, const km_traveltime* tt, const km_weight* w, const char* who) {
+    if (!g || !tt || !w) return fail(KM_E_INVALID, "%s: grid, traveltime and weight must be non-NULL", who);
+    if (g->nx < 0 || g->ny < 0 || g->nz < 0 || g->n_bins < 0) return fail(KM_E_INVALID, "%s: negative grid size", who);
+    if (static_cast<int64_t>(g->nx) * g->ny >= (int64_t(1) << 31))
+        return fail(KM_E_UNSUPPORTED, "%s: nx * ny must be < 2^31", who);
+    if (g->n_bins > 65535) return fail(KM_E_UNSUPPORTED, "%s: n_bins > 65535", who);
+    if (w->kind != KM_W_UNIT && w->kind != KM_W_COSCOS_OVER_TT)
+        return fail(KM_E_INVALID, "%s: unknown weight kind %d", who, w->kind);
+    const bool empty = g->nx == 0 || g->ny == 0 || g->nz == 0 || g->n_bins == 0;
+    if (!empty) {
+        if (!g->x || !g->y) return fail(KM_E_INVALID, "%s: x and y must be non-NULL", who);
+        if (!tt->t0sq || !tt->s2 || !tt->r2) return fail(KM_E_INVALID, "%s: t0sq, s2, r2 must be non-NULL", who);
+        if (!aligned(g->x, 4) || !aligned(g->y, 4) || !aligned(tt->t0sq, 4) || !aligned(tt->s2, 4) ||
+            !aligned(tt->r2, 4))
+            return fail(KM_E_INVALID, "%s: grid / table pointers must be 4-byte aligned", who);
+    }
+    return KM_OK;
+}
+
+bool grid_empty(const km_grid* g) { return g->nx == 0 || g->ny == 0 || g->nz == 0 || g->n_bins == 0; }
+
+// Base parameters (independent of the tile shape).
+km::Params base_params(const km_traces* t, const km_grid* g, const km_traveltime* tt, const km_weight* w,
+                       float* image, int accumulate) {
+    km::Params P{};
+    P.data = t->data;
+    P.scale = t->scale;
+    P.src = t->src;
+    P.rec = t->rec;
+    P.bin = t->bin;
+    P.n_traces = t->n_traces;
+    P.stride = t->trace_stride;
+    P.nt = t->n_samples;
+    P.dtype = t->dtype;
+    P.x = g->x;
+    P.y = g->y;
+    P.nx = g->nx;
+    P.ny = g->ny;
+    P.nz = g->nz;
+    P.n_bins = g->n_bins;
+    P.t0sq = tt->t0sq;
+    P.s2 = tt->s2;
+    P.r2 = tt->r2;
+    P.inv_dt2 = 1.0 / (t->dt * t->dt);
+    P.wscale = P.inv_dt2 * P.inv_dt2;
+    P.has_tf = t->t_first != 0.0 ? 1 : 0;
+    P.tf_shift = static_cast<float>(1.0 - t->t_first / t->dt);
+    P.weight = w->kind;
+    P.image = image;
+    P.accumulate = accumulate ? 1 : 0;
+    P.lt = t->n_samples + kLeadPad + kTailPad;
+    return P;
+}
+
+// Traces per LDS block for a shape's budget; 0 if even one row does not fit.
+int traces_per_block(int lt, int budget) {
+    const int64_t per = (static_cast<int64_t>(lt) + 4) * 4;
+    int64_t tb = budget / per;
+    if (tb < 1 && per <= kMaxLds) tb = 1;
+    return static_cast<int>(std::min<int64_t>(tb, kMaxTracesPerBlock));
+}
+
+km_status shape_params(int op, int shape, km::Params& P) {
+    const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
+    P.tb = traces_per_block(P.lt, S.lds_budget);
+    if (P.tb < 1) return fail(KM_E_UNSUPPORTED, "record of %d samples does not fit in LDS", P.nt);
+    const int zchunk = 16 * S.depth_slots;
+    P.n_zchunks = (P.nz + zchunk - 1) / zchunk;
+    if (P.n_zchunks > 65535) return fail(KM_E_UNSUPPORTED, "nz = %d needs more than 65535 depth chunks", P.nz);
+    const int cols = S.waves * S.column_groups * 4;
+    const int ncol = P.nx * P.ny;
+    P.n_coltiles = (ncol + cols - 1) / cols;
+    return KM_OK;
+}
+
+// ---- tuning cache ----------------------------------------------------------
+std::mutex g_tune_mu;
+std::map<std::tuple<int, int, int, int>, int> g_tune;
+
+std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
+    return std::make_tuple(op, dtype, (nz + 127) / 128, (nt + 511) / 512);
+}
+
+int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
+
+int default_shape(int op, int nz) {
+    if (op == 0) return nz <= 128 ? 3 : 0;
+    return 0;
+}
+
+km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {
+    if (tile >= 0) {
+        if (tile >= shape_count(op)) return fail(KM_E_INVALID, "tile %d out of range [0, %d)", tile, shape_count(op));
+        *shape = tile;
+        return KM_OK;
+    }
+    {
+        std::lock_guard<std::mutex> lk(g_tune_mu);
+        auto it = g_tune.find(tune_key(op, dtype, nz, nt));
+        if (it != g_tune.end()) {
+            *shape = it->second;
+            return KM_OK;
+        }
+    }
+    *shape = default_shape(op, nz);
+    return KM_OK;
+}
+
+km_status run_op(int op, const km_traces* t, const km_grid* g, const km_traveltime* tt, const km_weight* w,
+                 float* image, int accumulate, int shape, hipStream_t s) {
+    km::Params P = base_params(t, g, tt, w, image, accumulate);
+    km_status st = shape_params(op, shape, P);
+    if (st != KM_OK) return st;
+    if (op == 1 && (P.n_traces + P.tb - 1) / P.tb > INT32_MAX)
+        return fail(KM_E_UNSUPPORTED, "kirchhoff_demigrate: too many trace blocks");
+    hipError_t e = op == 0 ? km::launch_migrate(shape, P, s) : km::launch_demigrate(shape, P, s);
+    if (e != hipSuccess) return hip_fail(e, op == 0 ? "migrate launch" : "demigrate launch");
+    return KM_OK;
+}
+
+// Image zero fill for empty problems (nothing to evaluate, overwrite semantics).
+km_status zero_floats(float* p, int64_t n, hipStream_t s) {
+    if (n <= 0) return KM_OK;
+    const hipError_t e = km::launch_axpby(0.0f, p, 0.0f, p, n, s);
+    return e == hipSuccess ? KM_OK : hip_fail(e, "zero fill");
+}
+
+}  // namespace
+
+extern "C" {
+
+int km_abi_version(void) { return KM_ABI_VERSION; }
+
+const char* km_last_error(void) { return g_last_error.c_str(); }
+
+int32_t km_max_samples(void) { return 40000; }  // one staged row (+ geometry) stays below 160 KiB
+
+km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                            const km_weight* weight, float* image, int32_t accumulate, int32_t tile, void* stream) {
+    km_status st = check_traces(traces, true, "kirchhoff_migrate");
+    if (st != KM_OK) return st;
+    st = check_grid(grid, tt, weight, "kirchhoff_migrate");
+    if (st != KM_OK) return st;
+    if (grid_empty(grid)) return KM_OK;
+    if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_migrate: image is NULL or misaligned");
+    int shape = 0;
+    st = pick_shape(0, tile, traces->dtype, grid->nz, traces->n_samples, &shape);
+    if (st != KM_OK) return st;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (traces->n_traces == 0 && !accumulate)
+        return zero_floats(image, static_cast<int64_t>(grid->n_bins) * grid->ny * grid->nx * grid->nz, s);
+    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s);
+}
+
+km_status kirchhoff_demigrate(const float* image, const km_grid* grid, const km_traveltime* tt,
+                              const km_weight* weight, const km_traces* out, int32_t accumulate, int32_t tile,
+                              void* stream) {
+    km_status st = check_traces(out, true, "kirchhoff_demigrate");
+    if (st != KM_OK) return st;
+    if (out->dtype != KM_F32)
+        return fail(KM_E_UNSUPPORTED, "kirchhoff_demigrate: output traces must be KM_F32");
+    st = check_grid(grid, tt, weight, "kirchhoff_demigrate");
+    if (st != KM_OK) return st;
+    if (out->n_traces == 0 || out->n_samples == 0) return KM_OK;
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    if (grid_empty(grid)) {
+        if (accumulate) return KM_OK;
+        if (out->trace_stride != out->n_samples)
+            return fail(KM_E_UNSUPPORTED, "kirchhoff_demigrate: empty grid with strided output");
+        return zero_floats(static_cast<float*>(out->data), out->n_traces * out->trace_stride, s);
+    }
+    if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_demigrate: image is NULL or misaligned");
+    int shape = 0;
+    st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, &shape);
+    if (st != KM_OK) return st;
+    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s);
+}
+
+km_status km_count_contributions(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                                 int64_t* counts, void* stream) {
+    km_status st = check_traces(traces, false, "km_count_contributions");
+    if (st != KM_OK) return st;
+    km_weight w{KM_W_UNIT};
+    st = check_grid(grid, tt, &w, "km_count_contributions");
+    if (st != KM_OK) return st;
+    if (!counts || !aligned(counts, 8)) return fail(KM_E_INVALID, "km_count_contributions: counts NULL/misaligned");
+    km::Params P = base_params(traces, grid, tt, &w, nullptr, 0);
+    if (grid_empty(grid)) { P.nx = P.ny = P.nz = P.n_bins = 0; }
+    const hipError_t e = km::launch_count(P, reinterpret_cast<unsigned long long*>(counts),
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "count launch");
+}
+
+km_status km_dot_f64(const float* a, const float* b, int64_t n, double* out, void* stream) {
+    if (n < 0) return fail(KM_E_INVALID, "km_dot_f64: n < 0");
+    if (!out || !aligned(out, 8)) return fail(KM_E_INVALID, "km_dot_f64: out NULL/misaligned");
+    if (n > 0 && (!a || !b || !aligned(a, 4) || !aligned(b, 4)))
+        return fail(KM_E_INVALID, "km_dot_f64: a, b NULL/misaligned");
+    const hipError_t e = km::launch_dot_f64(a, b, n, out, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "dot launch");
+}
+
+km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t n, void* stream) {
+    if (n < 0) return fail(KM_E_INVALID, "km_axpby: n < 0");
+    if (n > 0 && (!x || !y || !aligned(x, 4) || !aligned(y, 4)))
+        return fail(KM_E_INVALID, "km_axpby: x, y NULL/misaligned");
+    if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(KM_E_INVALID, "km_axpby: non-finite scalar");
+    const hipError_t e = km::launch_axpby(static_cast<float>(alpha), x, static_cast<float>(beta), y, n,
+                                          static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "axpby launch");
+}
+
+int32_t km_tile_count(int32_t op) { return (op == 0 || op == 1) ? shape_count(op) : 0; }
+
+km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out) {
+    if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tile_describe: op must be 0 or 1");
+    if (tile < 0 || tile >= shape_count(op)) return fail(KM_E_INVALID, "km_tile_describe: tile out of range");
+    if (!out) return fail(KM_E_INVALID, "km_tile_describe: out is NULL");
+    const km::TileShape& S = op == 0 ? km::migrate_shape(tile) : km::demigrate_shape(tile);
+    out->waves = S.waves;
+    out->column_groups = S.column_groups;
+    out->depth_slots = S.depth_slots;
+    out->lds_budget = S.lds_budget;
+    return KM_OK;
+}
+
+int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto it = g_tune.find(tune_key(op, dtype, nz, n_samples));
+    return it == g_tune.end() ? -1 : it->second;
+}
+
+km_status km_tune_record(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples, int32_t tile) {
+    if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tune_record: op must be 0 or 1");
+    if (tile < 0 || tile >= shape_count(op)) return fail(KM_E_INVALID, "km_tune_record: tile out of range");
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    g_tune[tune_key(op, dtype, nz, n_samples)] = tile;
+    return KM_OK;
+}
+
+km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                  const km_weight* weight, float* image, int32_t reps, void* stream, int32_t* best_tile,
+                  float* best_ms) {
+    if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tune: op must be 0 or 1");
+    if (reps < 1) return fail(KM_E_INVALID, "km_tune: reps < 1");
+    km_status st = check_traces(traces, true, "km_tune");
+    if (st != KM_OK) return st;
+    st = check_grid(grid, tt, weight, "km_tune");
+    if (st != KM_OK) return st;
+    if (op == 1 && traces->dtype != KM_F32) return fail(KM_E_UNSUPPORTED, "km_tune: demigrate output must be KM_F32");
+    if (grid_empty(grid) || traces->n_traces == 0) return fail(KM_E_INVALID, "km_tune: empty problem");
+    if (!image) return fail(KM_E_INVALID, "km_tune: image is NULL");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    hipError_t he = hipEventCreate(&e0);
+    if (he != hipSuccess) return hip_fail(he, "hipEventCreate");
+    he = hipEventCreate(&e1);
+    if (he != hipSuccess) {
+        hipEventDestroy(e0);
+        return hip_fail(he, "hipEventCreate");
+    }
+    int best = -1;
+    float best_t = 0.0f;
+    st = KM_OK;
+    for (int sh = 0; sh < shape_count(op) && st == KM_OK; ++sh) {
+        km::Params P = base_params(traces, grid, tt, weight, image, 0);
+        if (shape_params(op, sh, P) != KM_OK) continue;
+        st = run_op(op, traces, grid, tt, weight, image, 0, sh, s);
+        if (st != KM_OK) break;
+        hipEventRecord(e0, s);
+        for (int r = 0; r < reps && st == KM_OK; ++r) st = run_op(op, traces, grid, tt, weight, image, 0, sh, s);
+        hipEventRecord(e1, s);
+        he = hipEventSynchronize(e1);
+        if (he != hipSuccess) {
+            st = hip_fail(he, "km_tune synchronise");
+            break;
+        }
+        float ms = 0.0f;
+        hipEventElapsedTime(&ms, e0, e1);
+        ms /= reps;
+        if (best < 0 || ms < best_t) {
+            best = sh;
+            best_t = ms;
+        }
+    }
+    hipEventDestroy(e0);
+    hipEventDestroy(e1);
+    if (st != KM_OK) return st;
+    if (best < 0) return fail(KM_E_UNSUPPORTED, "km_tune: no tile shape fits this problem");
+    km_tune_record(op, traces->dtype, grid->nz, traces->n_samples, best);
+    if (best_tile) *best_tile = best;
+    if (best_ms) *best_ms = best_t;
+    return KM_OK;
+}
+
+// ---- batched persistent migration -----------------------------------------
+
+struct km_batch {
+    int device = 0;
+    int shape = 0;
+    int has_tf = 0, weight = 0;
+    km::Params* d_probs = nullptr;
+    int4* d_items = nullptr;
+    unsigned int* d_counter = nullptr;
+    int64_t n_items = 0;
+    int n_wg = 0;
+    size_t lds = 0;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+};
+
+static void batch_free(km_batch* b) {
+    if (!b) return;
+    if (b->exec) hipGraphExecDestroy(b->exec);
+    if (b->graph) hipGraphDestroy(b->graph);
+    if (b->d_probs) hipFree(b->d_probs);
+    if (b->d_items) hipFree(b->d_items);
+    if (b->d_counter) hipFree(b->d_counter);
+    delete b;
+}
+
+km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void* stream, km_batch** out) {
+    if (!out) return fail(KM_E_INVALID, "km_batch_create: out is NULL");
+    *out = nullptr;
+    if (!probs || n < 1) return fail(KM_E_INVALID, "km_batch_create: need n >= 1 problems");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    for (int i = 0; i < n; ++i) {
+        km_status st = check_traces(&probs[i].traces, true, "km_batch_create");
+        if (st != KM_OK) return st;
+        st = check_grid(&probs[i].grid, &probs[i].tt, &probs[i].weight, "km_batch_create");
+        if (st != KM_OK) return st;
+        if (grid_empty(&probs[i].grid)) return fail(KM_E_INVALID, "km_batch_create: problem %d has an empty grid", i);
+        if (!probs[i].image || !aligned(probs[i].image, 4))
+            return fail(KM_E_INVALID, "km_batch_create: problem %d image NULL/misaligned", i);
+        if ((probs[i].traces.t_first != 0.0) != (probs[0].traces.t_first != 0.0) ||
+            probs[i].weight.kind != probs[0].weight.kind)
+            return fail(KM_E_UNSUPPORTED, "km_batch_create: all problems must share the weight kind and t_first == 0 or not");
+    }
+    int max_nz = 0, max_nt = 0;
+    for (int i = 0; i < n; ++i) {
+        max_nz = std::max(max_nz, probs[i].grid.nz);
+        max_nt = std::max(max_nt, probs[i].traces.n_samples);
+    }
+    int shape = 0;
+    km_status st = pick_shape(0, tile, probs[0].traces.dtype, max_nz, max_nt, &shape);
+    if (st != KM_OK) return st;
+    const km::TileShape& S = km::migrate_shape(shape);
+
+    km_batch* B = new (std::nothrow) km_batch();
+    if (!B) return fail(KM_E_NOMEM, "km_batch_create: host allocation failed");
+    hipGetDevice(&B->device);
+    B->shape = shape;
+    B->has_tf = probs[0].traces.t_first != 0.0 ? 1 : 0;
+    B->weight = probs[0].weight.kind;
+
+    std::vector<km::Params> P(n);
+    struct Item {
+        unsigned long long cost;
+        int4 w;
+    };
+    std::vector<Item> items;
+    unsigned long long* d_costs = nullptr;
+    for (int i = 0; i < n; ++i) {
+        P[i] = base_params(&probs[i].traces, &probs[i].grid, &probs[i].tt, &probs[i].weight, probs[i].image, 0);
+        st = shape_params(0, shape, P[i]);
+        if (st != KM_OK) {
+            batch_free(B);
+            return st;
+        }
+        B->lds = std::max(B->lds, km::lds_bytes(P[i]));
+        const int64_t nslot = static_cast<int64_t>(P[i].n_bins) * P[i].n_zchunks * P[i].n_coltiles;
+        if (nslot > (int64_t(1) << 31)) {
+            batch_free(B);
+            return fail(KM_E_UNSUPPORTED, "km_batch_create: problem %d has too many work items", i);
+        }
+        hipError_t e = hipMalloc(&d_costs, sizeof(unsigned long long) * std::max<int64_t>(nslot, 1));
+        if (e != hipSuccess) {
+            batch_free(B);
+            return fail(KM_E_NOMEM, "km_batch_create: hipMalloc costs: %s", hipGetErrorString(e));
+        }
+        e = km::launch_item_costs(P[i], S.depth_slots, S.waves * S.column_groups * 4, d_costs, s);
+        std::vector<unsigned long long> h(nslot);
+        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_costs, sizeof(unsigned long long) * nslot,
+                                                hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        hipFree(d_costs);
+        d_costs = nullptr;
+        if (e != hipSuccess) {
+            batch_free(B);
+            return hip_fail(e, "km_batch_create: cost estimate");
+        }
+        for (int b = 0; b < P[i].n_bins; ++b)
+            for (int zc = 0; zc < P[i].n_zchunks; ++zc)
+                for (int tl = 0; tl < P[i].n_coltiles; ++tl) {
+                    const unsigned long long c = h[(static_cast<int64_t>(b) * P[i].n_zchunks + zc) * P[i].n_coltiles + tl];
+                    items.push_back({c, make_int4(i, b, c ? tl : -1 - tl, zc)});
+                }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    B->n_items = static_cast<int64_t>(items.size());
+    std::vector<int4> hw(items.size());
+    for (size_t k = 0; k < items.size(); ++k) hw[k] = items[k].w;
+
+    hipError_t e = hipMalloc(&B->d_probs, sizeof(km::Params) * n);
+    if (e == hipSuccess) e = hipMalloc(&B->d_items, sizeof(int4) * std::max<size_t>(hw.size(), 1));
+    if (e == hipSuccess) e = hipMalloc(&B->d_counter, sizeof(unsigned int));
+    if (e != hipSuccess) {
+        batch_free(B);
+        return fail(KM_E_NOMEM, "km_batch_create: hipMalloc: %s", hipGetErrorString(e));
+    }
+    e = hipMemcpyAsync(B->d_probs, P.data(), sizeof(km::Params) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !hw.empty())
+        e = hipMemcpyAsync(B->d_items, hw.data(), sizeof(int4) * hw.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) {
+        batch_free(B);
+        return hip_fail(e, "km_batch_create: upload");
+    }
+
+    // Persistent grid: as many workgroups as can be resident at once.
+    const void* kfn = km::migrate_batch_kernel_ptr(shape, B->has_tf, B->weight);
+    if (B->lds > 65536) hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(B->lds));
+    int per_cu = 0, n_cu = 0;
+    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S.waves * 64, B->lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, B->device);
+    if (e != hipSuccess) {
+        batch_free(B);
+        return hip_fail(e, "km_batch_create: occupancy");
+    }
+    B->n_wg = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(std::max(per_cu, 1)) * n_cu,
+                                                                        std::max<int64_t>(B->n_items, 1))));
+
+    // Capture [queue reset, persistent kernel] once.
+    hipStream_t cap = nullptr;
+    e = hipStreamCreateWithFlags(&cap, hipStreamNonBlocking);
+    if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        hipError_t e1 = km::launch_reset_counter(B->d_counter, cap);
+        hipError_t e2 = e1 == hipSuccess ? km::launch_migrate_batch(shape, B->d_probs, B->d_items, B->n_items,
+                                                                      B->d_counter, B->has_tf, B->weight, B->n_wg,
+                                                                      B->lds, cap)
+                                         : e1;
+        e = hipStreamEndCapture(cap, &B->graph);
+        if (e == hipSuccess) e = e2;
+    }
+    if (e == hipSuccess) e = hipGraphInstantiate(&B->exec, B->graph, nullptr, nullptr, 0);
+    if (cap) hipStreamDestroy(cap);
+    if (e != hipSuccess) {
+        batch_free(B);
+        return hip_fail(e, "km_batch_create: graph capture");
+    }
+    *out = B;
+    return KM_OK;
+}
+
+km_status km_batch_run(km_batch* batch, void* stream) {
+    if (!batch) return fail(KM_E_INVALID, "km_batch_run: batch is NULL");
+    const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "hipGraphLaunch");
+}
+
+km_status km_batch_info(const km_batch* batch, int64_t* n_items, int32_t* n_workgroups) {
+    if (!batch) return fail(KM_E_INVALID, "km_batch_info: batch is NULL");
+    if (n_items) *n_items = batch->n_items;
+    if (n_workgroups) *n_workgroups = batch->n_wg;
+    return KM_OK;
+}
+
+km_status km_batch_destroy(km_batch* batch) {
+    if (!batch) return KM_OK;
+    const hipError_t e = hipDeviceSynchronize();
+    batch_free(batch);
+    return e == hipSuccess ? KM_OK : hip_fail(e, "km_batch_destroy synchronise");
+}
+
+km_status km_probe_issue(int32_t kind, int32_t n_waves, int32_t iters, void* stream, float* ms) {
+    if (kind < 0 || kind > 2 || n_waves < 1 || iters < 1 || !ms) return fail(KM_E_INVALID, "km_probe_issue: bad args");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    float* sink = nullptr;
+    hipError_t e = hipMalloc(&sink, 256 * sizeof(float));
+    if (e != hipSuccess) return hip_fail(e, "km_probe_issue hipMalloc");
+    hipEvent_t a, b;
+    hipEventCreate(&a);
+    hipEventCreate(&b);
+    e = km::launch_probe(kind, n_waves, iters, sink, s);  // warm-up
+    if (e == hipSuccess) e = hipEventRecord(a, s);
+    if (e == hipSuccess) e = km::launch_probe(kind, n_waves, iters, sink, s);
+    if (e == hipSuccess) e = hipEventRecord(b, s);
+    if (e == hipSuccess) e = hipEventSynchronize(b);
+    float t = 0.0f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, a, b);
+    hipEventDestroy(a);
+    hipEventDestroy(b);
+    hipFree(sink);
+    if (e != hipSuccess) return hip_fail(e, "km_probe_issue");
+    *ms = t;
+    return KM_OK;
+}
+
+}  // extern "C"

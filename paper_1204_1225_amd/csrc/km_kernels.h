@@ -1,0 +1,57 @@
+// Internal interface between the C ABI (km_api.cpp) and the kernel files.
+#pragma once
+
+#include "km_device.h"
+
+namespace km {
+
+// One compiled tile shape.  lds_budget bounds the bytes of LDS a workgroup
+// spends on its trace block (migrate) or trace accumulators (demigrate).
+struct TileShape {
+    int waves;          // wavefronts per workgroup
+    int column_groups;  // groups of 4 columns per wavefront (migrate); unused by demigrate
+    int depth_slots;    // KS: 16-depth slots per lane
+    int lds_budget;
+};
+
+// Launch with `lds` bytes of dynamic LDS (raising the kernel's limit first
+// when more than the default 64 KiB is requested).
+template <typename Kernel, typename... Args>
+inline hipError_t launch_with_lds(Kernel kernel, dim3 grid, dim3 block, size_t lds, hipStream_t s, Args... args) {
+    if (lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                                 hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(lds));
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(kernel, grid, block, lds, s, args...);
+    return hipGetLastError();
+}
+
+inline size_t lds_bytes(const Params& P) {
+    return (static_cast<size_t>(4) * P.tb + static_cast<size_t>(P.tb) * P.lt) * sizeof(float);
+}
+
+// migrate (km_migrate.hip)
+int migrate_shape_count();
+const TileShape& migrate_shape(int i);
+hipError_t launch_migrate(int shape, const Params& P, hipStream_t s);
+hipError_t launch_migrate_batch(int shape, const Params* probs, const int4* items, int64_t n_items,
+                                unsigned int* counter, int has_tf, int weight, int n_wg, size_t lds,
+                                hipStream_t s);
+const void* migrate_batch_kernel_ptr(int shape, int has_tf, int weight);
+
+// demigrate (km_demigrate.hip)
+int demigrate_shape_count();
+const TileShape& demigrate_shape(int i);
+hipError_t launch_demigrate(int shape, const Params& P, hipStream_t s);
+
+// counting, reductions, probes (km_misc.hip)
+hipError_t launch_count(const Params& P, unsigned long long* counts, hipStream_t s);
+hipError_t launch_dot_f64(const float* a, const float* b, int64_t n, double* out, hipStream_t s);
+hipError_t launch_axpby(float alpha, const float* x, float beta, float* y, int64_t n, hipStream_t s);
+hipError_t launch_item_costs(const Params& P, int shape_ks, int cols_per_tile, unsigned long long* costs,
+                             hipStream_t s);
+hipError_t launch_reset_counter(unsigned int* counter, hipStream_t s);
+hipError_t launch_probe(int kind, int n_waves, int iters, float* sink, hipStream_t s);
+
+}  // namespace km

@@ -1,0 +1,262 @@
+"""Python entry points over libkirchhoff.so (argument marshalling only).
+
+Device memory and streams come from PyTorch; every step of migration,
+demigration, counting and the float64 reductions runs in the HIP library.
+A `DeviceProblem` holds the device-resident inputs of one problem (traces,
+geometry, bins, grid and model tables) in the layouts of include/kirchhoff.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+from ._lib import KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmWeight, check
+
+_DTYPES = {"f32": _lib.KM_F32, "bf16": _lib.KM_BF16, "f16": _lib.KM_F16}
+
+
+def _stream(device) -> int:
+    return torch.cuda.current_stream(device).cuda_stream
+
+
+def _ptr(t: Optional[torch.Tensor]):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+@dataclasses.dataclass
+class DeviceProblem:
+    """Device-resident inputs of one migration problem."""
+
+    device: torch.device
+    n_t: int
+    dt: float
+    t_first: float
+    n_bins: int
+    weight: int
+    src: torch.Tensor       # float32 [n, 2]
+    rec: torch.Tensor       # float32 [n, 2]
+    bin: torch.Tensor       # int32 [n], nondecreasing
+    x: torch.Tensor         # float32 [nx]
+    y: torch.Tensor         # float32 [ny]
+    t0sq: torch.Tensor      # float32 [nz]
+    s2: torch.Tensor        # float32 [nz]
+    r2: torch.Tensor        # float32 [nz]
+    data: Optional[torch.Tensor] = None   # [n, n_t] float32, or int16 bit patterns of bf16 / f16
+    scale: Optional[torch.Tensor] = None  # float32 [n] for 16-bit data
+    dtype: str = "f32"
+
+    @property
+    def n_traces(self) -> int:
+        return int(self.src.shape[0])
+
+    @property
+    def nx(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def ny(self) -> int:
+        return int(self.y.shape[0])
+
+    @property
+    def nz(self) -> int:
+        return int(self.t0sq.shape[0])
+
+    @property
+    def image_shape(self):
+        return (self.n_bins, self.ny, self.nx, self.nz)
+
+    def with_data(self, data: torch.Tensor, scale: Optional[torch.Tensor] = None, dtype: str = "f32"):
+        return dataclasses.replace(self, data=data, scale=scale, dtype=dtype)
+
+    # ctypes views -----------------------------------------------------------
+    def c_traces(self, data: Optional[torch.Tensor] = None, dtype: Optional[str] = None,
+                 scale: Optional[torch.Tensor] = None) -> KmTraces:
+        d = self.data if data is None else data
+        dt_name = self.dtype if dtype is None else dtype
+        sc = (self.scale if data is None else scale) if dt_name != "f32" else None
+        stride = int(d.stride(0)) if d is not None and d.dim() == 2 else self.n_t
+        if d is not None:
+            assert d.shape == (self.n_traces, self.n_t) and d.stride(1) == 1 and d.device == self.device
+        return KmTraces(n_traces=self.n_traces, n_samples=self.n_t, dtype=_DTYPES[dt_name], trace_stride=stride,
+                        t_first=self.t_first, dt=self.dt, data=_ptr(d), scale=_ptr(sc), src=_ptr(self.src),
+                        rec=_ptr(self.rec), bin=_ptr(self.bin))
+
+    def c_grid(self) -> KmGrid:
+        return KmGrid(nx=self.nx, ny=self.ny, nz=self.nz, n_bins=self.n_bins, x=_ptr(self.x), y=_ptr(self.y))
+
+    def c_tt(self) -> KmTraveltime:
+        return KmTraveltime(t0sq=_ptr(self.t0sq), s2=_ptr(self.s2), r2=_ptr(self.r2))
+
+    def c_weight(self) -> KmWeight:
+        return KmWeight(kind=int(self.weight))
+
+
+def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DeviceProblem:
+    """Copy a survey problem's inputs to the GPU in the ABI layouts.
+
+    Tables are converted to float32 (the ABI's table type).  dtype "bf16" /
+    "f16" stores the traces with a per-trace scale (survey.quantise)."""
+    from . import survey
+
+    dev = torch.device(device)
+
+    def f32(a):
+        return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)
+
+    dp = DeviceProblem(device=dev, n_t=int(problem.n_t), dt=float(problem.dt), t_first=float(problem.t_first),
+                       n_bins=int(problem.n_bins), weight=int(problem.weight), src=f32(problem.src),
+                       rec=f32(problem.rec),
+                       bin=torch.as_tensor(np.ascontiguousarray(problem.bin, dtype=np.int32), device=dev),
+                       x=f32(problem.x), y=f32(problem.y), t0sq=f32(problem.t0sq), s2=f32(problem.s2),
+                       r2=f32(problem.r2))
+    d = problem.data if data is None else data
+    if d is None:
+        return dp
+    if isinstance(d, torch.Tensor):
+        if dtype != "f32":
+            d = d.detach().cpu().numpy()
+        else:
+            return dp.with_data(d.to(device=dev, dtype=torch.float32).contiguous())
+    if dtype == "f32":
+        return dp.with_data(f32(d))
+    bits, sig, _ = survey.quantise(np.asarray(d, dtype=np.float32), dtype)
+    return dp.with_data(torch.as_tensor(bits.view(np.int16), device=dev), f32(sig), dtype)
+
+
+def migrate(dp: DeviceProblem, data: Optional[torch.Tensor] = None, image: Optional[torch.Tensor] = None,
+            accumulate: bool = False, tile: int = -1, dtype: Optional[str] = None,
+            scale: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Eq. (1): image [n_bins, ny, nx, nz] float32 from the problem's traces
+    (or `data`).  accumulate=True adds into `image`."""
+    if image is None:
+        image = torch.empty(dp.image_shape, dtype=torch.float32, device=dp.device)
+        if accumulate:
+            image.zero_()
+    assert image.shape == dp.image_shape and image.dtype == torch.float32 and image.is_contiguous()
+    tr = dp.c_traces(data, dtype if data is not None else None, scale)
+    lib = _lib.load()
+    check(lib.kirchhoff_migrate(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
+                                ctypes.byref(dp.c_weight()), _ptr(image), int(accumulate), int(tile),
+                                ctypes.c_void_p(_stream(dp.device))))
+    return image
+
+
+def demigrate(dp: DeviceProblem, image: torch.Tensor, out: Optional[torch.Tensor] = None,
+              accumulate: bool = False, tile: int = -1) -> torch.Tensor:
+    """Transpose of migrate: float32 traces [n_traces, n_t] from an image."""
+    assert image.shape == dp.image_shape and image.dtype == torch.float32 and image.is_contiguous()
+    if out is None:
+        out = torch.empty((dp.n_traces, dp.n_t), dtype=torch.float32, device=dp.device)
+        if accumulate:
+            out.zero_()
+    tr = dp.c_traces(out, "f32")
+    lib = _lib.load()
+    check(lib.kirchhoff_demigrate(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
+                                  ctypes.byref(dp.c_weight()), ctypes.byref(tr), int(accumulate), int(tile),
+                                  ctypes.c_void_p(_stream(dp.device))))
+    return out
+
+
+def count(dp: DeviceProblem):
+    """(n_aperture, n_effective) of Eq. (2) from the counting kernel."""
+    c = torch.empty(2, dtype=torch.int64, device=dp.device)
+    tr = dp.c_traces()
+    lib = _lib.load()
+    check(lib.km_count_contributions(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
+                                     _ptr(c), ctypes.c_void_p(_stream(dp.device))))
+    v = c.cpu().tolist()
+    return int(v[0]), int(v[1])
+
+
+def dot_f64(a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """float64 device scalar sum(a * b) of two float32 tensors of equal size."""
+    assert a.dtype == torch.float32 and b.dtype == torch.float32 and a.numel() == b.numel()
+    assert a.is_contiguous() and b.is_contiguous()
+    if out is None:
+        out = torch.empty((), dtype=torch.float64, device=a.device)
+    check(_lib.load().km_dot_f64(_ptr(a), _ptr(b), a.numel(), _ptr(out), ctypes.c_void_p(_stream(a.device))))
+    return out
+
+
+def axpby(alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor) -> torch.Tensor:
+    """y = alpha x + beta y in place (float32)."""
+    assert x.dtype == torch.float32 and y.dtype == torch.float32 and x.numel() == y.numel()
+    assert x.is_contiguous() and y.is_contiguous()
+    check(_lib.load().km_axpby(float(alpha), _ptr(x), float(beta), _ptr(y), y.numel(),
+                               ctypes.c_void_p(_stream(y.device))))
+    return y
+
+
+def tile_count(op: int) -> int:
+    return int(_lib.load().km_tile_count(op))
+
+
+def tile_describe(op: int, tile: int) -> dict:
+    info = KmTileInfo()
+    check(_lib.load().km_tile_describe(op, tile, ctypes.byref(info)))
+    return {f: int(getattr(info, f)) for f, _ in KmTileInfo._fields_}
+
+
+def tune(op: int, dp: DeviceProblem, image: torch.Tensor, traces_out: Optional[torch.Tensor] = None,
+         reps: int = 2):
+    """Time every tile shape of op (0 migrate, 1 demigrate) on dp and record the
+    fastest for its shape class; returns (tile, ms).  For op 0 `image` is
+    overwritten with the migration; for op 1 `image` is the input and
+    `traces_out` (float32 [n_traces, n_t]) is overwritten."""
+    best, ms = ctypes.c_int32(-1), ctypes.c_float(0.0)
+    tr = dp.c_traces() if op == 0 else dp.c_traces(traces_out, "f32")
+    check(_lib.load().km_tune(op, ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
+                              ctypes.byref(dp.c_weight()), _ptr(image), int(reps),
+                              ctypes.c_void_p(_stream(dp.device)), ctypes.byref(best), ctypes.byref(ms)))
+    return int(best.value), float(ms.value)
+
+
+def probe_issue(kind: int, n_waves: int = 8192, iters: int = 4096) -> float:
+    """ms of the issue-rate probe (kind 0 fma, 1 sqrt, 2 rcp)."""
+    ms = ctypes.c_float(0.0)
+    check(_lib.load().km_probe_issue(kind, n_waves, iters, ctypes.c_void_p(_stream(torch.device("cuda"))),
+                                     ctypes.byref(ms)))
+    return float(ms.value)
+
+
+class Batch:
+    """Many problems migrated by one persistent, graph-captured launch."""
+
+    def __init__(self, problems, images, tile: int = -1):
+        assert len(problems) == len(images) and len(problems) > 0
+        self._keep = (list(problems), list(images))
+        arr = (KmProblem * len(problems))()
+        for k, (dp, img) in enumerate(zip(problems, images)):
+            assert img.shape == dp.image_shape and img.dtype == torch.float32 and img.is_contiguous()
+            arr[k] = KmProblem(traces=dp.c_traces(), grid=dp.c_grid(), tt=dp.c_tt(), weight=dp.c_weight(),
+                               image=_ptr(img))
+        self._arr = arr
+        self._h = ctypes.c_void_p()
+        dev = problems[0].device
+        check(_lib.load().km_batch_create(arr, len(problems), int(tile), ctypes.c_void_p(_stream(dev)),
+                                          ctypes.byref(self._h)))
+        self.device = dev
+
+    def run(self):
+        check(_lib.load().km_batch_run(self._h, ctypes.c_void_p(_stream(self.device))))
+
+    def info(self):
+        n, w = ctypes.c_int64(0), ctypes.c_int32(0)
+        check(_lib.load().km_batch_info(self._h, ctypes.byref(n), ctypes.byref(w)))
+        return int(n.value), int(w.value)
+
+    def close(self):
+        if self._h:
+            check(_lib.load().km_batch_destroy(self._h))
+            self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

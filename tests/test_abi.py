@@ -1,0 +1,139 @@
+"""Host-side checks of the C ABI (no GPU needed): the library loads, exports
+every entry point include/kirchhoff.h declares, and rejects bad arguments on
+the host before launching anything."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def declared_functions():
+    src = open(os.path.join(ROOT, "include", "kirchhoff.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    names = re.findall(r"^\s*(?:const\s+)?[A-Za-z_][A-Za-z0-9_]*\s*\*?\s*((?:km|kirchhoff)_[A-Za-z0-9_]+)\s*\(", src,
+                       flags=re.M)
+    return sorted(set(names))
+
+
+@pytest.fixture(scope="module")
+def lib():
+    from paper_1204_1225_amd import _lib
+
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1204_1225_amd import build
+
+        build.build(verbose=False)
+    return _lib.load()
+
+
+def test_exports_every_declared_symbol(lib):
+    from paper_1204_1225_amd import _lib
+
+    names = declared_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(lib, n), n
+    assert set(names) == set(_lib.SIGNATURES), "binding and header disagree"
+
+
+def test_abi_version_and_limits(lib):
+    assert lib.km_abi_version() == 1
+    assert lib.km_max_samples() > 30000
+    assert lib.km_tile_count(0) >= 2 and lib.km_tile_count(1) >= 2
+    assert lib.km_tile_count(7) == 0
+
+
+def test_tile_describe(lib):
+    from paper_1204_1225_amd import _lib
+
+    info = _lib.KmTileInfo()
+    assert lib.km_tile_describe(0, 0, ctypes.byref(info)) == _lib.KM_OK
+    assert info.waves >= 1 and info.depth_slots >= 1 and info.lds_budget > 0
+    assert lib.km_tile_describe(0, 99, ctypes.byref(info)) == _lib.KM_E_INVALID
+    assert b"out of range" in lib.km_last_error()
+
+
+def _args(_lib, **over):
+    t = _lib.KmTraces(n_traces=4, n_samples=10, dtype=_lib.KM_F32, trace_stride=10, t_first=0.0, dt=0.004,
+                      data=ctypes.c_void_p(0x1000), scale=None, src=ctypes.c_void_p(0x1000),
+                      rec=ctypes.c_void_p(0x1000), bin=ctypes.c_void_p(0x1000))
+    g = _lib.KmGrid(nx=2, ny=1, nz=3, n_bins=1, x=ctypes.c_void_p(0x1000), y=ctypes.c_void_p(0x1000))
+    tt = _lib.KmTraveltime(t0sq=ctypes.c_void_p(0x1000), s2=ctypes.c_void_p(0x1000), r2=ctypes.c_void_p(0x1000))
+    w = _lib.KmWeight(kind=1)
+    for k, v in over.items():
+        obj, field = k.split("__")
+        setattr({"t": t, "g": g, "tt": tt, "w": w}[obj], field, v)
+    return t, g, tt, w
+
+
+@pytest.mark.parametrize("over,status,msg", [
+    ({"t__dt": 0.0}, 1, b"dt"),
+    ({"t__n_traces": -1}, 1, b"n_traces"),
+    ({"t__trace_stride": 5}, 1, b"trace_stride"),
+    ({"t__dtype": 9}, 1, b"dtype"),
+    ({"t__data": None}, 1, b"data"),
+    ({"t__scale": ctypes.c_void_p(0x1000)}, 1, b"scale"),
+    ({"t__n_samples": 10 ** 6, "t__trace_stride": 10 ** 6}, 2, b"km_max_samples"),
+    ({"w__kind": 5}, 1, b"weight"),
+    ({"g__x": None}, 1, b"x and y"),
+    ({"tt__r2": None}, 1, b"r2"),
+    ({"g__nx": -3}, 1, b"negative"),
+    ({"t__src": ctypes.c_void_p(0x1002)}, 1, b"aligned"),
+])
+def test_migrate_rejects_bad_arguments(lib, over, status, msg):
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib, **over)
+    st = lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w),
+                               ctypes.c_void_p(0x1000), 0, -1, None)
+    assert st == status
+    assert msg in lib.km_last_error()
+
+
+def test_demigrate_rejects_16bit_output_and_null_image(lib):
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib, t__dtype=_lib.KM_BF16)
+    st = lib.kirchhoff_demigrate(ctypes.c_void_p(0x1000), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w),
+                                 ctypes.byref(t), 0, -1, None)
+    assert st == _lib.KM_E_UNSUPPORTED
+    t, g, tt, w = _args(_lib)
+    st = lib.kirchhoff_demigrate(None, ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), ctypes.byref(t), 0, -1,
+                                 None)
+    assert st == _lib.KM_E_INVALID
+
+
+def test_null_struct_and_bad_tile(lib):
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib)
+    assert lib.kirchhoff_migrate(None, ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), ctypes.c_void_p(0x1000), 0,
+                                 -1, None) == _lib.KM_E_INVALID
+    assert lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w),
+                                 ctypes.c_void_p(0x1000), 0, 42, None) == _lib.KM_E_INVALID
+    assert b"tile" in lib.km_last_error()
+
+
+def test_reductions_reject_bad_arguments(lib):
+    from paper_1204_1225_amd import _lib
+
+    assert lib.km_dot_f64(None, None, -1, ctypes.c_void_p(0x1000), None) == _lib.KM_E_INVALID
+    assert lib.km_dot_f64(None, None, 5, ctypes.c_void_p(0x1000), None) == _lib.KM_E_INVALID
+    assert lib.km_axpby(float("nan"), ctypes.c_void_p(0x1000), 1.0, ctypes.c_void_p(0x1000), 4, None) == \
+        _lib.KM_E_INVALID
+    h = ctypes.c_void_p()
+    assert lib.km_batch_create(None, 0, -1, None, ctypes.byref(h)) == _lib.KM_E_INVALID
+    assert lib.km_batch_run(None, None) == _lib.KM_E_INVALID
+
+
+def test_tune_cache_roundtrip(lib):
+    from paper_1204_1225_amd import _lib
+
+    assert lib.km_tune_lookup(0, 0, 4000, 7000) == -1
+    assert lib.km_tune_record(0, 0, 4000, 7000, 1) == _lib.KM_OK
+    assert lib.km_tune_lookup(0, 0, 4000, 7000) == 1
+    assert lib.km_tune_lookup(0, 0, 4010, 7100) == 1  # same shape class
+    assert lib.km_tune_record(0, 0, 4000, 7000, 99) == _lib.KM_E_INVALID

@@ -1,0 +1,139 @@
+"""GPU demigration (the adjoint of migration) against the FP64 oracle, the
+float32 dot-product test, autograd, finite differences and least squares."""
+import numpy as np
+import pytest
+import torch
+
+from paper_1204_1225_amd import survey
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ops():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1204_1225_amd import _lib, ops
+
+    _lib.load()
+    return ops
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    return np.linalg.norm(a - b) / max(np.linalg.norm(b), 1e-300)
+
+
+CASES = [
+    (81, 301, 257, 13, 7, 37, 4, 0.0),
+    (82, 120, 500, 70, 1, 300, 3, 0.0),
+    (83, 90, 300, 9, 4, 50, 2, 0.07),
+]
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"seed{c[0]}")
+def test_demigrate_parity_all_tiles(ops, oracle_lib, case):
+    seed, n, nt, nx, ny, nz, nb, tf = case
+    p = survey.make_random(seed, n_traces=n, n_t=nt, nx=nx, ny=ny, nz=nz, n_bins=nb, dz=10.0, t_first=tf)
+    m = survey.random_image(p, seed + 1)
+    ref = oracle_lib.demigrate(p, m)
+    dp = ops.to_device(p)
+    mt = torch.from_numpy(m).cuda()
+    for tile in range(ops.tile_count(1)):
+        d = ops.demigrate(dp, mt, tile=tile).cpu().numpy()
+        e = rel_l2(d, ref)
+        print(f"seed{seed} tile{tile}: rel L2 {e:.3e}")
+        assert e <= 1e-5
+
+
+@pytest.mark.parametrize("case", CASES, ids=lambda c: f"seed{c[0]}")
+def test_dot_product_fp32(ops, case):
+    seed, n, nt, nx, ny, nz, nb, tf = case
+    p = survey.make_random(seed, n_traces=n, n_t=nt, nx=nx, ny=ny, nz=nz, n_bins=nb, dz=10.0, t_first=tf)
+    dp = ops.to_device(p)
+    d = torch.from_numpy(survey.random_data(p, 41)).cuda()
+    m = torch.from_numpy(survey.random_image(p, 42)).cuda()
+    Md = ops.migrate(dp, data=d, dtype="f32")
+    Mtm = ops.demigrate(dp, m)
+    lhs = float(ops.dot_f64(Md, m))
+    rhs = float(ops.dot_f64(d, Mtm))
+    e = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
+    print(f"dot test seed{seed}: {lhs:.9e} {rhs:.9e} rel {e:.2e}")
+    assert e < 1e-6
+
+
+def test_dot_f64_and_axpby(ops):
+    g = torch.Generator().manual_seed(3)
+    a = torch.randn(1_000_003, generator=g)
+    b = torch.randn(1_000_003, generator=g)
+    ref = float(np.dot(a.numpy().astype(np.float64), b.numpy().astype(np.float64)))
+    got = float(ops.dot_f64(a.cuda(), b.cuda()))
+    assert abs(got - ref) <= 1e-12 * abs(ref) + 1e-9
+    y = b.clone().cuda()
+    ops.axpby(0.5, a.cuda(), -2.0, y)
+    assert torch.allclose(y.cpu(), 0.5 * a - 2.0 * b, rtol=1e-6, atol=1e-6)
+    z = torch.full((10,), float("nan"), device="cuda")
+    ops.axpby(3.0, torch.ones(10, device="cuda"), 0.0, z)
+    assert torch.all(z == 3.0)
+
+
+def test_autograd_is_adjoint(ops):
+    from paper_1204_1225_amd import autograd
+
+    p = survey.make_random(91, n_traces=100, n_t=300, nx=12, ny=3, nz=60, n_bins=2, dz=10.0)
+    dp = ops.to_device(p)
+    m = torch.from_numpy(survey.random_image(p, 5)).cuda().requires_grad_(True)
+    w = torch.from_numpy(survey.random_data(p, 6)).cuda()
+    out = autograd.demigrate(m, dp)
+    (out * w).sum().backward()
+    ref = ops.migrate(dp, data=w, dtype="f32")
+    assert torch.equal(m.grad, ref)
+
+
+def test_finite_differences(ops):
+    from paper_1204_1225_amd import autograd
+
+    p = survey.make_random(92, n_traces=120, n_t=300, nx=12, ny=3, nz=60, n_bins=2, dz=10.0)
+    dp = ops.to_device(p)
+    d_obs = torch.from_numpy(survey.random_data(p, 7)).cuda()
+    m = torch.from_numpy(survey.random_image(p, 8)).cuda().requires_grad_(True)
+
+    def J(mm):
+        r = autograd.demigrate(mm, dp) - d_obs
+        return 0.5 * (r.double() ** 2).sum()
+
+    J(m).backward()
+    g = m.grad.double()
+    rng = np.random.default_rng(43)
+    for k in range(4):
+        delta = torch.from_numpy(rng.standard_normal(p.image_shape).astype(np.float32)).cuda()
+        eps = 0.1 * float(m.detach().norm()) / float(delta.norm())
+        with torch.no_grad():
+            fd = (J(m + eps * delta) - J(m - eps * delta)) / (2 * eps)
+        an = float((g * delta.double()).sum())
+        e = abs(float(fd) - an) / abs(an)
+        print(f"FD {k}: fd {float(fd):.6e} analytic {an:.6e} rel {e:.2e}")
+        assert e < 1e-4
+
+
+def test_lsm_monotone(ops, tmp_path):
+    from paper_1204_1225_amd import lsm
+
+    p = survey.make_random(93, n_traces=150, n_t=300, nx=16, ny=2, nz=60, n_bins=2, dz=10.0)
+    dp = ops.to_device(p)
+    m_true = torch.zeros(p.image_shape, device="cuda")
+    m_true[:, 0, 8, 30] = 1.0
+    m_true[:, 1, 3, 45] = -0.5
+    d_obs = ops.demigrate(dp, m_true)
+    res = lsm.lsm(dp, d_obs, n_iter=6)
+    J = res.objective
+    assert len(J) == 7
+    for k in range(6):
+        assert J[k + 1] <= J[k]
+        assert abs((J[k] - J[k + 1]) - res.predicted_decrease[k]) <= 1e-3 * J[0]
+    assert J[-1] < 0.5 * J[0]
+    # checkpoint / resume reproduces the remaining iterates
+    ck = str(tmp_path / "lsm.pt")
+    lsm.lsm(dp, d_obs, n_iter=3, checkpoint=ck)
+    res2 = lsm.lsm(dp, d_obs, n_iter=6, checkpoint=ck)
+    assert np.allclose(res2.objective, J, rtol=1e-5)

@@ -1,0 +1,177 @@
+"""GPU parity: the HIP kernels of libkirchhoff.so against the FP64 oracle.
+
+Tolerance: relative L2 error <= 1e-5 for float32 traces (float32 traveltime
+evaluation and float32 accumulation against FP64), plus a max-abs bound of
+1e-4 of the image peak.  Integer results (pair counts) are bit-exact; the
+source/receiver swap is bit-exact on the GPU because the kernel's expressions
+are symmetric in the two legs.
+"""
+import dataclasses
+
+import numpy as np
+import pytest
+import torch
+
+from paper_1204_1225_amd import survey
+
+pytestmark = pytest.mark.gpu
+
+TOL_L2 = 1e-5
+TOL_MAX = 1e-4
+
+
+@pytest.fixture(scope="module")
+def ops():
+    assert torch.cuda.is_available(), "GPU tests need a ROCm device"
+    from paper_1204_1225_amd import _lib, ops
+
+    _lib.load()
+    return ops
+
+
+def rel_l2(a, b):
+    a = np.asarray(a, np.float64)
+    b = np.asarray(b, np.float64)
+    nb = np.linalg.norm(b)
+    return np.linalg.norm(a - b) / (nb if nb > 0 else 1.0)
+
+
+def assert_close(gpu, ref, tol=TOL_L2, tol_max=TOL_MAX, what=""):
+    g = gpu.detach().cpu().numpy().astype(np.float64) if isinstance(gpu, torch.Tensor) else gpu
+    e = rel_l2(g, ref)
+    peak = np.abs(ref).max() if ref.size else 0.0
+    emax = np.abs(g - ref).max() / (peak if peak > 0 else 1.0) if ref.size else 0.0
+    print(f"{what}: rel L2 {e:.3e}, max/peak {emax:.3e}")
+    assert e <= tol, f"{what}: relative L2 {e:.3e} > {tol}"
+    assert emax <= tol_max, f"{what}: max error / peak {emax:.3e} > {tol_max}"
+
+
+def test_line2d_full_parity_and_focusing(ops, oracle_lib):
+    p = survey.make_line2d(1)
+    dp = ops.to_device(p)
+    img = ops.migrate(dp)
+    torch.cuda.synchronize()
+    ref = oracle_lib.migrate(p)
+    assert_close(img, ref, what="line2d")
+    stack = img.sum(0)[0].cpu().numpy()
+    for ix, _, iz in p.diffractor_nodes:
+        win = np.abs(stack[ix - 5:ix + 6, iz - 5:iz + 6])
+        assert np.unravel_index(np.argmax(win), win.shape) == (5, 5)
+
+
+RAGGED = [
+    # seed, n_traces, n_t, nx, ny, nz, n_bins
+    (21, 301, 257, 13, 7, 37, 4),
+    (22, 97, 600, 70, 1, 300, 3),
+    (23, 64, 131, 5, 5, 16, 2),
+    (24, 33, 90, 1, 1, 1, 1),
+]
+
+
+@pytest.mark.parametrize("case", RAGGED, ids=lambda c: f"seed{c[0]}")
+def test_ragged_parity_all_tiles(ops, oracle_lib, case):
+    seed, n, nt, nx, ny, nz, nb = case
+    p = survey.make_random(seed, n_traces=n, n_t=nt, nx=nx, ny=ny, nz=nz, n_bins=nb, dz=10.0)
+    ref = oracle_lib.migrate(p)
+    dp = ops.to_device(p)
+    assert np.count_nonzero(ref) > 0
+    for tile in range(ops.tile_count(0)):
+        img = ops.migrate(dp, tile=tile)
+        assert_close(img, ref, what=f"seed{seed} tile{tile}")
+
+
+def test_t_first_and_unit_weight(ops, oracle_lib):
+    p = survey.make_random(31, n_traces=200, n_t=400, nx=40, ny=1, nz=120, n_bins=2, t_first=0.05,
+                           weight=survey.WEIGHT_UNIT, dz=10.0)
+    ref = oracle_lib.migrate(p)
+    img = ops.migrate(ops.to_device(p))
+    assert_close(img, ref, what="t_first unit")
+    p2 = dataclasses.replace(p, weight=survey.WEIGHT_COSCOS, t_first=-0.03)
+    assert_close(ops.migrate(ops.to_device(p2)), oracle_lib.migrate(p2), what="negative t_first")
+
+
+@pytest.mark.parametrize("kind", ["bf16", "f16"])
+def test_16bit_traces(ops, oracle_lib, kind):
+    p = survey.make_line2d(1)
+    bits, sig, deq = survey.quantise(p.data, kind)
+    img = ops.migrate(ops.to_device(p, dtype=kind))
+    # kernel error: against the oracle on the dequantised samples
+    assert_close(img, oracle_lib.migrate(p, deq), what=f"{kind} vs oracle(dequantised)")
+    # storage error: reported against the oracle on the original samples
+    e = rel_l2(img.cpu().numpy(), oracle_lib.migrate(p))
+    print(f"{kind} storage error vs oracle(original): {e:.3e}")
+    assert e < (2e-2 if kind == "bf16" else 2e-3)
+
+
+def test_accumulate_is_reduce_sum(ops, oracle_lib):
+    p = survey.make_random(41, n_traces=240, n_t=300, nx=20, ny=3, nz=64, n_bins=3, dz=10.0)
+    dp = ops.to_device(p)
+    full = ops.migrate(dp)
+    idx = np.arange(p.n_traces)
+    a, b = p.subset(idx[idx % 3 == 0]), p.subset(idx[idx % 3 != 0])
+    img = ops.migrate(ops.to_device(a))
+    ops.migrate(ops.to_device(b), image=img, accumulate=True)
+    assert_close(img, full.cpu().numpy().astype(np.float64), tol=2e-6, what="shards summed")
+
+
+def test_reciprocity_bitwise(ops):
+    p = survey.make_random(51, n_traces=150, n_t=300, nx=16, ny=4, nz=80, n_bins=2, dz=10.0)
+    q = dataclasses.replace(p, src=p.rec.copy(), rec=p.src.copy())
+    a = ops.migrate(ops.to_device(p))
+    b = ops.migrate(ops.to_device(q))
+    assert torch.equal(a, b)
+
+
+def test_repeat_is_deterministic(ops):
+    p = survey.make_random(52, n_traces=150, n_t=300, nx=16, ny=4, nz=80, n_bins=2, dz=10.0)
+    dp = ops.to_device(p)
+    assert torch.equal(ops.migrate(dp), ops.migrate(dp))
+
+
+def test_counts_bit_exact(ops, oracle_lib):
+    for seed, n, nt, nx, ny, nz, nb in RAGGED[:3]:
+        p = survey.make_random(seed, n_traces=n, n_t=nt, nx=nx, ny=ny, nz=nz, n_bins=nb, dz=10.0)
+        na, ne = ops.count(ops.to_device(p))
+        ona, one = oracle_lib.count(p)
+        assert na == ona
+        assert abs(ne - one) <= max(2, one // 100000)
+    p = survey.make_line2d(1)
+    assert ops.count(ops.to_device(p))[0] == oracle_lib.count(p)[0]
+
+
+def test_edge_cases(ops, oracle_lib):
+    # no traces: image overwritten with zeros
+    p = survey.make_random(61, n_traces=40, n_t=100, nx=9, ny=2, nz=20, n_bins=2, dz=10.0)
+    empty = p.subset([])
+    dp = ops.to_device(empty)
+    img = torch.full(dp.image_shape, 7.0, device="cuda")
+    ops.migrate(dp, image=img)
+    assert torch.count_nonzero(img) == 0
+    # traces whose bins are outside [0, n_bins) contribute nothing; an empty bin images to 0
+    # (bin 0 -> -1 keeps the list sorted)
+    q = dataclasses.replace(p, bin=np.where(p.bin == 0, -1, p.bin).astype(np.int32), n_bins=3)
+    img = ops.migrate(ops.to_device(q))
+    ref = oracle_lib.migrate(q)
+    assert np.all(ref[0] == 0) and np.all(ref[2] == 0) and np.count_nonzero(ref[1]) > 0
+    assert_close(img, ref, what="bins outside range")
+    # one-sample traces
+    r = survey.make_random(62, n_traces=50, n_t=1, nx=6, ny=1, nz=30, n_bins=1, dz=2.0, spread=0.0)
+    r.data[:] = 1.0
+    assert_close(ops.migrate(ops.to_device(r)), oracle_lib.migrate(r), what="n_t = 1")
+
+
+def test_long_record(ops, oracle_lib):
+    # 20000 samples: one or two staged traces per block, > 64 KiB of LDS
+    p = survey.make_random(71, n_traces=12, n_t=20000, nx=8, ny=1, nz=40, n_bins=1, dz=50.0, dt=0.001)
+    ref = oracle_lib.migrate(p)
+    for tile in range(ops.tile_count(0)):
+        assert_close(ops.migrate(ops.to_device(p), tile=tile), ref, what=f"long record tile{tile}")
+
+
+def test_strided_traces(ops, oracle_lib):
+    p = survey.make_random(72, n_traces=80, n_t=200, nx=10, ny=3, nz=50, n_bins=2, dz=10.0)
+    dp = ops.to_device(p)
+    wide = torch.zeros((p.n_traces, 256), device="cuda")
+    wide[:, :200] = torch.from_numpy(p.data).cuda()
+    img = ops.migrate(dp, data=wide[:, :200], dtype="f32")
+    assert_close(img, oracle_lib.migrate(p), what="strided")
