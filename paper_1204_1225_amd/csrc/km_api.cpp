@@ -37,7 +37,7 @@ km_status hip_fail(hipError_t e, const char* what) {
 
 constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
 constexpr int kMaxTracesPerBlock = 32;
-constexpr int kLeadPad = 1, kTailPad = 2;
+constexpr int kTailPad = 2;
 
 bool aligned(const void* p, size_t a) { return (reinterpret_cast<uintptr_t>(p) % a) == 0; }
 
@@ -117,25 +117,29 @@ km::Params base_params(const km_traces* t, const km_grid* g, const km_traveltime
     P.inv_dt2 = 1.0 / (t->dt * t->dt);
     P.wscale = P.inv_dt2 * P.inv_dt2;
     P.has_tf = t->t_first != 0.0 ? 1 : 0;
-    P.tf_shift = static_cast<float>(1.0 - t->t_first / t->dt);
+    P.tf_off = static_cast<float>(km::kLead - t->t_first / t->dt);
     P.weight = w->kind;
     P.image = image;
     P.accumulate = accumulate ? 1 : 0;
-    P.lt = t->n_samples + kLeadPad + kTailPad;
+    P.lt = (t->n_samples + km::kLead + kTailPad + 3) / 4 * 4;
+    const uintptr_t base = reinterpret_cast<uintptr_t>(t->data);
+    P.vec_ok = t->dtype == KM_F32 ? (base % 16 == 0 && t->trace_stride % 4 == 0)
+                                  : (base % 8 == 0 && t->trace_stride % 4 == 0);
     return P;
 }
 
 // Traces per LDS block for a shape's budget; 0 if even one row does not fit.
-int traces_per_block(int lt, int budget) {
-    const int64_t per = (static_cast<int64_t>(lt) + 4) * 4;
-    int64_t tb = budget / per;
-    if (tb < 1 && per <= kMaxLds) tb = 1;
+int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
+    const int64_t fixed = static_cast<int64_t>(16) * ks * 4;
+    const int64_t per = static_cast<int64_t>(lt) * row_bytes_per_sample + 16;
+    int64_t tb = (budget - fixed) / per;
+    if (tb < 1 && fixed + per <= kMaxLds) tb = 1;
     return static_cast<int>(std::min<int64_t>(tb, kMaxTracesPerBlock));
 }
 
 km_status shape_params(int op, int shape, km::Params& P) {
     const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
-    P.tb = traces_per_block(P.lt, S.lds_budget);
+    P.tb = traces_per_block(P.lt, S.lds_budget, S.depth_slots, op == 0 ? 4 : 8);
     if (P.tb < 1) return fail(KM_E_UNSUPPORTED, "record of %d samples does not fit in LDS", P.nt);
     const int zchunk = 16 * S.depth_slots;
     P.n_zchunks = (P.nz + zchunk - 1) / zchunk;
@@ -156,9 +160,11 @@ std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
 
 int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
 
+// Untuned choice: the shapes measured fastest on the 3D survey (migrate:
+// 4 waves x 4 column groups x 8 slots; demigrate: 16 waves x 8 slots).
 int default_shape(int op, int nz) {
-    if (op == 0) return nz <= 128 ? 3 : 0;
-    return 0;
+    (void)nz;
+    return op == 0 ? 3 : 1;
 }
 
 km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {
@@ -206,7 +212,8 @@ int km_abi_version(void) { return KM_ABI_VERSION; }
 
 const char* km_last_error(void) { return g_last_error.c_str(); }
 
-int32_t km_max_samples(void) { return 40000; }  // one staged row (+ geometry) stays below 160 KiB
+// one float64 accumulator row (demigrate), its geometry and the chunk tables fit in 160 KiB
+int32_t km_max_samples(void) { return 20000; }
 
 km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
                             const km_weight* weight, float* image, int32_t accumulate, int32_t tile, void* stream) {
@@ -440,7 +447,7 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
             batch_free(B);
             return st;
         }
-        B->lds = std::max(B->lds, km::lds_bytes(P[i]));
+        B->lds = std::max(B->lds, km::lds_bytes(P[i], S.depth_slots));
         const int64_t nslot = static_cast<int64_t>(P[i].n_bins) * P[i].n_zchunks * P[i].n_coltiles;
         if (nslot > (int64_t(1) << 31)) {
             batch_free(B);

@@ -1,65 +1,104 @@
 // Demigration kernel: the transpose of migration as a trace-stationary scatter.
 //
 // Workgroup = a block of P.tb consecutive traces (of the bin-sorted list).
-// The block's output rows live in LDS as float32 accumulators (same
-// zero-padded row layout as the migration staging: row[1 + k] = sample k).
-// Wavefronts sweep the image columns of each bin present in the block (four
-// columns per wavefront slot, lanes = depths), load the image value of every
-// lane once per column group, and for every trace in aperture scatter
-// (1 - f) W I and f W I into the two samples around the total time with LDS
-// float atomics.  Each row is written back to HBM exactly once.
+// The block's output rows live in LDS as float64 accumulators (same
+// zero-padded row layout as the migration staging: row[kLead + k] = sample k).
+// float64 because gfx950 executes LDS float64 atomic adds at about 8 clocks
+// per wavefront instruction and float32 ones at about 190 (measured), and the
+// wider sum also keeps the transpose's own rounding negligible.
+// Wavefronts sweep the image columns of each bin present in the block, one
+// column per wavefront at a time; the four 16-lane groups of a wavefront work
+// on four different traces of the block (lanes = 16 consecutive depths), so
+// that the LDS float atomics of one instruction land in four different rows
+// and seldom on the same address.  The image values of the column are loaded
+// once and serve every trace of the block.  Each row is written back to HBM
+// exactly once.
 #include "km_kernels.h"
 
 namespace km {
 
+template <bool TF, int WK, bool MASKED>
+__device__ __forceinline__ void dem_slot(float A, float B, float hs2, float hr2, float hm, double* row, float tfo,
+                                         float wlo, float whi, const float* sRk, float x) {
+    if (MASKED && !(hm <= *sRk)) return;
+    const Pair pr = eval_pair<TF, WK>(A, B, hs2, hr2, tfo, wlo, whi);
+    const float q = (WK == W_COSCOS) ? x * pr.r : x;
+    const float q1 = pr.f * q;
+    const float q0 = q - q1;
+    atomicAdd(row + pr.i, static_cast<double>(q0));
+    atomicAdd(row + pr.i + 1, static_cast<double>(q1));
+}
+
 template <int NW, int KS, bool TF, int WK>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
-                                                  float* sAcc) {
+                                                  double* sAcc, float* sR) {
+    static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     const int g = lane / kGroup, d = lane % kGroup;
     const int ncol = P.nx * P.ny;
-    const int nquads = (ncol + kGroupsPerWave - 1) / kGroupsPerWave;
-    const float umax = TF ? static_cast<float>(P.lt - 2) : static_cast<float>(P.lt - 3);
-    const float tfs = P.tf_shift;
+    const int nseg = t1 - t0;  // <= tb <= 64
+    const int nquads = (nseg + kGroupsPerWave - 1) / kGroupsPerWave;
+    float wlo, whi;
+    clamp_bounds<TF>(P.lt, wlo, whi);
+    const float tfo = P.tf_off;
+    const int rowoff = TF ? 0 : kLead;
     const float* img = P.image + static_cast<int64_t>(b) * ncol * P.nz;
+    const uint64_t segmask = nseg >= 64 ? ~0ull : ((1ull << nseg) - 1ull);
+    // lane-parallel geometry: lane l <-> trace t0 + l (far away past the segment)
+    const float4 srl = lane < nseg ? sGeo[t0 + lane] : make_float4(kFar, kFar, kFar, kFar);
 
     for (int zc = 0; zc < P.n_zchunks; ++zc) {
         const int z0 = zc * KS * kGroup;
-        DepthTables<KS> T;
-        load_tables<KS>(P, z0, d, WK == W_COSCOS, T);
+        ChunkTables<KS> T;
+        __syncthreads();  // previous chunk's readers of sR are done
+        load_chunk_tables<KS>(P, z0, d, WK == W_COSCOS, T, sR);
+        float S[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) {
+            const int iz = z0 + k * kGroup + d;
+            S[k] = (iz < P.nz) ? depth_factor(P, iz) : 0.0f;
+        }
+        __syncthreads();
         if (T.rmax < 0.0f) continue;
-        for (int qi = wave; qi < nquads; qi += NW) {
-            const int col = qi * kGroupsPerWave + g;
-            float px = kFar, py = kFar;
-            if (col < ncol) {
-                px = P.x[col % P.nx];
-                py = P.y[col / P.nx];
-            }
-            // Is any trace of the segment inside the aperture of this column group?
-            bool any = false;
-            for (int t = t0; t < t1 && !any; ++t) any = legs(px, py, sGeo[t]).hmax <= T.rmax;
-            if (!__any(any)) continue;
-            float xv[KS];
+        for (int col = wave; col < ncol; col += NW) {
+            const float px = P.x[col % P.nx], py = P.y[col / P.nx];
+            const Legs Lp = legs(px, py, srl);
+            const uint64_t live = __builtin_amdgcn_ballot_w64(Lp.hmax <= T.rmax) & segmask;
+            if (!live) continue;
+            // extremes of hmax over each aligned quad of traces (the four groups of a slot)
+            float qmin = fminf(Lp.hmax, __shfl_xor(Lp.hmax, 1, kLanes));
+            qmin = fminf(qmin, __shfl_xor(qmin, 2, kLanes));
+            float qmax = fmaxf(Lp.hmax, __shfl_xor(Lp.hmax, 1, kLanes));
+            qmax = fmaxf(qmax, __shfl_xor(qmax, 2, kLanes));
+            float x[KS];
+            const float* colp = img + static_cast<int64_t>(col) * P.nz;
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
                 const int iz = z0 + k * kGroup + d;
-                xv[k] = (col < ncol && iz < P.nz) ? img[static_cast<int64_t>(col) * P.nz + iz] * depth_factor(P, iz)
-                                                  : 0.0f;
+                x[k] = (iz < P.nz) ? colp[iz] * S[k] : 0.0f;
             }
-            for (int t = t0; t < t1; ++t) {
-                const Legs L = legs(px, py, sGeo[t]);
-                if (L.hmax <= T.rmax) {
-                    float* row = sAcc + t * P.lt + (TF ? 0 : 1);
+            for (int qt = 0; qt < nquads; ++qt) {
+                if (!((live >> (kGroupsPerWave * qt)) & 0xFull)) continue;
+                const float hmin = uniform_read(qmin, kGroupsPerWave * qt);
+                const float hmaxw = uniform_read(qmax, kGroupsPerWave * qt);
+                uint64_t any, full;
+                slot_masks<KS>(T, hmin, hmaxw, any, full);
+                if (!any) continue;
+                const int src = kGroupsPerWave * qt + g;  // this group's trace (segment-relative)
+                const float hs2 = lane_read(Lp.hs2, src);
+                const float hr2 = lane_read(Lp.hr2, src);
+                const float hm = fmaxf(hs2, hr2);
+                double* row = sAcc + (t0 + min(src, nseg - 1)) * P.lt + rowoff;
 #pragma unroll
-                    for (int k = 0; k < KS; ++k) {
-                        if (L.hmax <= T.R[k]) {
-                            const Pair pr = eval_pair<TF, WK>(T.A[k], T.B[k], L.hs2, L.hr2, tfs, umax);
-                            const float q = (WK == W_COSCOS) ? xv[k] * pr.r : xv[k];
-                            const float q1 = pr.f * q;
-                            const float q0 = q - q1;
-                            atomicAdd(row + pr.i, q0);
-                            atomicAdd(row + pr.i + 1, q1);
+                for (int k = 0; k < KS; k += 2) {
+                    if ((any >> k) & 3ull) {
+                        if (((full >> k) & 3ull) == 3ull) {
+                            dem_slot<TF, WK, false>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, x[k]);
+                            dem_slot<TF, WK, false>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, x[k + 1]);
+                        } else {
+                            dem_slot<TF, WK, true>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, sR + k * kGroup + d, x[k]);
+                            dem_slot<TF, WK, true>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, sR + (k + 1) * kGroup + d, x[k + 1]);
                         }
                     }
                 }
@@ -71,8 +110,9 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
 template <int NW, int KS, bool TF, int WK>
 __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     extern __shared__ float lds[];
-    float4* sGeo = reinterpret_cast<float4*>(lds);
-    float* sAcc = lds + 4 * P.tb;
+    double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
+    float4* sGeo = reinterpret_cast<float4*>(lds + 2 * P.tb * P.lt);   // [tb]
+    float* sR = lds + 2 * P.tb * P.lt + 4 * P.tb;                      // [KS * 16]
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * P.tb;
     const int nb = static_cast<int>(min<int64_t>(P.tb, P.n_traces - j0));
 
@@ -84,7 +124,7 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
         }
         sGeo[t] = g;
     }
-    for (int e = threadIdx.x; e < P.tb * P.lt; e += blockDim.x) sAcc[e] = 0.0f;
+    for (int e = threadIdx.x; e < P.tb * P.lt; e += blockDim.x) sAcc[e] = 0.0;
     __syncthreads();
 
     // The block's traces form runs of equal bin (the list is sorted by bin).
@@ -93,7 +133,7 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
         const int b = P.bin[j0 + t0];
         int t1 = t0 + 1;
         while (t1 < nb && P.bin[j0 + t1] == b) ++t1;
-        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, TF, WK>(P, b, t0, t1, sGeo, sAcc);
+        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, TF, WK>(P, b, t0, t1, sGeo, sAcc, sR);
         t0 = t1;
     }
     __syncthreads();
@@ -101,8 +141,11 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     float* out = static_cast<float*>(P.data);
     for (int t = 0; t < nb; ++t) {
         float* o = out + (j0 + t) * P.stride;
-        const float* row = sAcc + t * P.lt + 1;
-        for (int k = threadIdx.x; k < P.nt; k += blockDim.x) o[k] = P.accumulate ? o[k] + row[k] : row[k];
+        const double* row = sAcc + t * P.lt + kLead;
+        for (int k = threadIdx.x; k < P.nt; k += blockDim.x) {
+            const float v = static_cast<float>(row[k]);
+            o[k] = P.accumulate ? o[k] + v : v;
+        }
     }
 }
 
@@ -110,7 +153,7 @@ template <int NW, int KS>
 static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     const int64_t nblk = (P.n_traces + P.tb - 1) / P.tb;
     dim3 grid(static_cast<unsigned>(nblk)), block(NW * 64);
-    const size_t lds = lds_bytes(P);
+    const size_t lds = lds_bytes_f64rows(P, KS);
     if (P.has_tf) {
         if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, true, W_COSCOS>, grid, block, lds, s, P);
         return launch_with_lds(demigrate_kernel<NW, KS, true, W_UNIT>, grid, block, lds, s, P);
@@ -119,10 +162,12 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     return launch_with_lds(demigrate_kernel<NW, KS, false, W_UNIT>, grid, block, lds, s, P);
 }
 
+// (waves, depth slots, LDS budget for the trace accumulators)
 #define KM_DEMIGRATE_SHAPES(X) \
-    X(8, 16, 98304)            \
-    X(4, 16, 65536)            \
-    X(8, 8, 98304)
+    X(8, 16, 131072)           \
+    X(16, 8, 131072)           \
+    X(8, 8, 98304)             \
+    X(12, 16, 131072)
 
 static const TileShape kDemigrateShapes[] = {
 #define X(nw, ks, lb) {nw, 1, ks, lb},

@@ -1,12 +1,14 @@
 // Device-side building blocks shared by the migrate, demigrate, count and
-// batched kernels: launch parameters, trace staging and the per-pair
-// evaluation of Eq. (1) (aperture, total time, interpolation index, weight).
+// batched kernels: launch parameters, the per-depth tables of a depth chunk,
+// the staged-trace row layout and the per-pair evaluation of Eq. (1)
+// (aperture, total time, interpolation index, weight).
 //
-// Lane layout used by every image-domain kernel: a wavefront (64 lanes) is
-// four groups of 16 lanes; group g works on one image column, lane d of the
-// group on depth z0 + 16 k + d for slot k = 0..KS-1.  A 16-depth slot is the
-// unit of the aperture mask: a pair (column, trace) enters a slot only if
-// some lane of the slot is inside the aperture.
+// Lane layout of the image-domain kernels: a wavefront (64 lanes) is four
+// groups of 16 lanes; lane d of a group works on depth z0 + 16 k + d in slot
+// k = 0..KS-1 of the depth chunk starting at z0.  A 16-depth slot is the unit
+// of work skipping: a slot is evaluated for a (column, trace) pairing only if
+// some lane of it can be inside the aperture, and without any per-lane mask
+// when every valid lane is inside.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -17,8 +19,9 @@
 namespace km {
 
 constexpr int kLanes = 64;
-constexpr int kGroup = 16;        // lanes per column group (depths per slot)
-constexpr int kGroupsPerWave = 4;  // columns per wavefront slot
+constexpr int kGroup = 16;         // lanes per group (depths per slot)
+constexpr int kGroupsPerWave = 4;  // groups per wavefront
+constexpr int kLead = 4;           // zero floats before sample 0 in a staged row: row[kLead + k] = D[k]
 constexpr float kFar = 3.0e30f;    // coordinate of padding columns / traces: never inside the aperture
 
 enum Dtype : int32_t { F32 = 0, BF16 = 1, F16 = 2 };
@@ -47,17 +50,18 @@ struct Params {
     const float* r2;
     double inv_dt2;   // 1 / dt^2: tables -> sample units
     double wscale;    // 1 / dt^4: W = t0sq * wscale / (a_s * a_r) with a in samples^2
-    float tf_shift;   // 1 - t_first / dt (used when t_first != 0)
+    float tf_off;     // kLead - t_first / dt (used when t_first != 0)
     int32_t has_tf;
     int32_t weight;
     // output / input image
     float* image;
     int32_t accumulate;
     // staging geometry
-    int32_t lt;       // LDS floats per staged trace (>= nt + 3)
+    int32_t lt;       // LDS floats per staged row (multiple of 4, >= nt + kLead + 2)
     int32_t tb;       // traces per LDS block
     int32_t n_zchunks;
     int32_t n_coltiles;
+    int32_t vec_ok;   // data base 16-byte aligned and stride a multiple of 4 elements (8 for 16-bit)
 };
 
 // First index in sorted bin[0..n) whose value is >= key.
@@ -70,17 +74,57 @@ __device__ __forceinline__ int64_t lower_bound_bin(const int32_t* __restrict__ b
     return lo;
 }
 
-__device__ __forceinline__ float load_sample(const Params& P, int64_t j, int32_t k) {
-    const int64_t off = j * P.stride + k;
-    if (P.dtype == F32) return static_cast<const float*>(P.data)[off];
-    const uint16_t bits = static_cast<const uint16_t*>(P.data)[off];
-    float v;
-    if (P.dtype == BF16) {
-        v = __uint_as_float(static_cast<uint32_t>(bits) << 16);
+__device__ __forceinline__ float widen16(uint32_t bits, int dtype) {
+    return dtype == BF16 ? __uint_as_float(bits << 16) : __half2float(__ushort_as_half(static_cast<uint16_t>(bits)));
+}
+
+// Stage trace j into an LDS row of P.lt floats: row[kLead + k] = D_j[k]
+// (times the per-trace scale for 16-bit storage), zeros elsewhere.  All
+// threads of the block take part; `nthr` threads, this one is `tid`.
+__device__ __forceinline__ void stage_row(const Params& P, int64_t j, float* row, int tid, int nthr) {
+    const int nt = P.nt;
+    const float sc = (P.dtype != F32 && P.scale) ? P.scale[j] : 1.0f;
+    const int nq = P.lt >> 2;  // float4 quads in the row
+    float4* row4 = reinterpret_cast<float4*>(row);
+    if (P.vec_ok) {
+        // quad m holds samples 4m - kLead .. 4m - kLead + 3; kLead = 4 so quad m >= 1 is D[4(m-1)..]
+        for (int m = tid; m < nq; m += nthr) {
+            const int k0 = 4 * m - kLead;
+            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
+            if (k0 >= 0 && k0 + 3 < nt) {
+                if (P.dtype == F32) {
+                    v = *reinterpret_cast<const float4*>(static_cast<const float*>(P.data) + j * P.stride + k0);
+                } else {
+                    const uint2 w = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(P.data) + j * P.stride + k0);
+                    v = make_float4(widen16(w.x & 0xFFFFu, P.dtype) * sc, widen16(w.x >> 16, P.dtype) * sc,
+                                    widen16(w.y & 0xFFFFu, P.dtype) * sc, widen16(w.y >> 16, P.dtype) * sc);
+                }
+            } else if (k0 >= 0 && k0 < nt) {
+                float e[4];
+#pragma unroll
+                for (int c = 0; c < 4; ++c) {
+                    const int k = k0 + c;
+                    e[c] = 0.0f;
+                    if (k < nt) {
+                        if (P.dtype == F32) e[c] = static_cast<const float*>(P.data)[j * P.stride + k];
+                        else e[c] = widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + k], P.dtype) * sc;
+                    }
+                }
+                v = make_float4(e[0], e[1], e[2], e[3]);
+            }
+            row4[m] = v;
+        }
     } else {
-        v = __half2float(__ushort_as_half(bits));
+        for (int k = tid; k < P.lt; k += nthr) {
+            const int ks = k - kLead;
+            float v = 0.0f;
+            if (ks >= 0 && ks < nt) {
+                if (P.dtype == F32) v = static_cast<const float*>(P.data)[j * P.stride + ks];
+                else v = widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + ks], P.dtype) * sc;
+            }
+            row[k] = v;
+        }
     }
-    return P.scale ? v * P.scale[j] : v;
 }
 
 // Horizontal squared leg lengths of a (column, trace) pair, float32 with the
@@ -102,9 +146,10 @@ __device__ __forceinline__ Legs legs(float px, float py, float4 sr) {
 
 // One (trace, image point) pair in sample units:
 //   a_s = A + B hs2, a_r = A + B hr2 (A = t0sq / dt^2, B = s2 / dt^2),
-//   u   = sqrt(a_s) + sqrt(a_r) (+ shift when t_first != 0), clamped to
-//         [0, umax] so that the staged-trace reads stay inside the row,
-//   i   = floor(u), f = u - i, and r = 1 / (a_s a_r) for the weight.
+//   w   = sqrt(a_s) + sqrt(a_r) [+ tf_off when t_first != 0], clamped to
+//         [wlo, whi]; the staged-row index of sample floor(u) is floor(w)
+//         (plus kLead through the row pointer when t_first == 0),
+//   i   = floor(w), f = w - i, and r = 1 / (a_s a_r) for the weight.
 // Migrate and demigrate both call this, so the transpose pair sees
 // bit-identical (i, f, r) for every pair.
 struct Pair {
@@ -114,52 +159,94 @@ struct Pair {
 };
 
 template <bool TF, int WK>
-__device__ __forceinline__ Pair eval_pair(float A, float B, float hs2, float hr2, float tf_shift, float umax) {
+__device__ __forceinline__ Pair eval_pair(float A, float B, float hs2, float hr2, float tf_off, float wlo, float whi) {
     const float as = fmaf(B, hs2, A);
     const float ar = fmaf(B, hr2, A);
-    float u = __builtin_amdgcn_sqrtf(as) + __builtin_amdgcn_sqrtf(ar);
-    if (TF) u = fmaxf(u + tf_shift, 0.0f);
-    u = fminf(u, umax);
+    float w = __builtin_amdgcn_sqrtf(as) + __builtin_amdgcn_sqrtf(ar);
+    if (TF) w = w + tf_off;
+    w = __builtin_amdgcn_fmed3f(w, wlo, whi);
     Pair p;
-    p.i = static_cast<int32_t>(u);
-    p.f = __builtin_amdgcn_fractf(u);
+    p.i = static_cast<int32_t>(w);
+    p.f = __builtin_amdgcn_fractf(w);
     p.r = (WK == W_COSCOS) ? __builtin_amdgcn_rcpf(as * ar) : 1.0f;
     return p;
 }
 
-// Per-depth tables of one depth chunk, in registers: lane d of every group
-// holds depth z0 + 16 k + d.  Depths past nz (and, for the cos*cos weight,
-// depths with t0sq <= 0 where W = 0) get R = -1 so that no leg is inside.
+// Clamp bounds of eval_pair for a row of lt floats: reads at floor(w) and
+// floor(w) + 1 stay in [0, lt).  Without t_first the row pointer is advanced
+// by kLead and u >= 0 needs no lower clamp beyond 0.
+template <bool TF>
+__device__ __forceinline__ void clamp_bounds(int lt, float& wlo, float& whi) {
+    wlo = TF ? static_cast<float>(kLead - 1) : 0.0f;
+    whi = TF ? static_cast<float>(lt - 2) : static_cast<float>(lt - 2 - kLead);
+}
+
+// Per-depth tables of one depth chunk.  Lane d of every group holds depth
+// z0 + 16 k + d in slot k.  A lane is valid if its depth exists and (for the
+// cos*cos weight) t0sq > 0; elsewhere W = 0 and the image value is 0.
+//   A, B     sample-unit traveltime tables per slot
+//   rlo/rhi  lane k < KS holds min / max over the valid lanes of slot k of the
+//            aperture table (+inf / -inf when the slot has no valid lane)
+//   rmax     max over the chunk (wavefront-uniform)
+// sR[16 k + d] (LDS) holds the aperture value of each depth, -1 where invalid.
 template <int KS>
-struct DepthTables {
-    float A[KS], B[KS], R[KS];
-    float rmax;  // max over the chunk of R (wavefront-uniform)
+struct ChunkTables {
+    float A[KS], B[KS];
+    float rlo, rhi, rmax;
 };
 
 template <int KS>
-__device__ __forceinline__ void load_tables(const Params& P, int z0, int d, bool zero_weight_guard,
-                                            DepthTables<KS>& T) {
+__device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d, bool zero_weight_guard,
+                                                  ChunkTables<KS>& T, float* sR) {
+    const int lane = threadIdx.x & (kLanes - 1);
     float rmax = -1.0f;
+    float rlo_mine = __builtin_inff(), rhi_mine = -__builtin_inff();
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int iz = z0 + k * kGroup + d;
+        // invalid lanes: a = 1 for every leg (finite time and weight), never inside
         float A = 1.0f, B = 0.0f, R = -1.0f;
+        bool valid = false;
         if (iz < P.nz) {
             const float t0 = P.t0sq[iz];
-            A = static_cast<float>(static_cast<double>(t0) * P.inv_dt2);
-            B = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);
-            R = P.r2[iz];
-            if (zero_weight_guard && !(t0 > 0.0f)) R = -1.0f;
+            valid = !(zero_weight_guard && !(t0 > 0.0f));
+            if (valid) {
+                A = static_cast<float>(static_cast<double>(t0) * P.inv_dt2);
+                B = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);
+                R = P.r2[iz];
+            }
         }
         T.A[k] = A;
         T.B[k] = B;
-        T.R[k] = R;
-        rmax = fmaxf(rmax, R);
-    }
-    // wavefront max (every lane ends with the same value)
+        if (sR && lane < kGroup) sR[k * kGroup + d] = R;
+        // min / max over the 16 lanes of the group (all groups hold the same depths)
+        float lo = valid ? R : __builtin_inff();
+        float hi = valid ? R : -__builtin_inff();
 #pragma unroll
-    for (int off = 1; off < kLanes; off <<= 1) rmax = fmaxf(rmax, __shfl_xor(rmax, off, kLanes));
+        for (int off = 1; off < kGroup; off <<= 1) {
+            lo = fminf(lo, __shfl_xor(lo, off, kLanes));
+            hi = fmaxf(hi, __shfl_xor(hi, off, kLanes));
+        }
+        if (lane == k) {
+            rlo_mine = lo;
+            rhi_mine = hi;
+        }
+        rmax = fmaxf(rmax, hi);
+    }
+    T.rlo = rlo_mine;
+    T.rhi = rhi_mine;
     T.rmax = rmax;
+}
+
+// Bit k (k < KS) set when slot k may hold a lane inside the aperture
+// (hmin <= max R of the slot) / when every valid lane is inside
+// (hmax <= min R of the slot).  hmin, hmax: wavefront-uniform.
+template <int KS>
+__device__ __forceinline__ void slot_masks(const ChunkTables<KS>& T, float hmin, float hmax, uint64_t& any,
+                                           uint64_t& full) {
+    constexpr uint64_t kMask = (KS >= 64) ? ~0ull : ((1ull << KS) - 1ull);
+    any = __builtin_amdgcn_ballot_w64(hmin <= T.rhi) & kMask;
+    full = __builtin_amdgcn_ballot_w64(hmax <= T.rlo) & kMask;
 }
 
 // Final per-depth factor of the image: t0sq / dt^4 for the cos*cos weight
@@ -168,6 +255,15 @@ __device__ __forceinline__ float depth_factor(const Params& P, int iz) {
     if (P.weight != W_COSCOS) return 1.0f;
     const float t0 = P.t0sq[iz];
     return t0 > 0.0f ? static_cast<float>(static_cast<double>(t0) * P.wscale) : 0.0f;
+}
+
+// v from lane `src` (any lane), through the LDS crossbar.
+__device__ __forceinline__ float lane_read(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+__device__ __forceinline__ float uniform_read(float v, int src) {
+    return __int_as_float(__builtin_amdgcn_readlane(__float_as_int(v), src));
 }
 
 }  // namespace km

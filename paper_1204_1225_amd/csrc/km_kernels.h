@@ -27,8 +27,17 @@ inline hipError_t launch_with_lds(Kernel kernel, dim3 grid, dim3 block, size_t l
     return hipGetLastError();
 }
 
-inline size_t lds_bytes(const Params& P) {
-    return (static_cast<size_t>(4) * P.tb + static_cast<size_t>(P.tb) * P.lt) * sizeof(float);
+// LDS of a migrate / demigrate workgroup: the chunk's aperture table
+// (16 * ks floats), the staged geometry (4 floats per trace) and the rows.
+inline size_t lds_bytes(const Params& P, int ks) {
+    return (static_cast<size_t>(16) * ks + static_cast<size_t>(4) * P.tb + static_cast<size_t>(P.tb) * P.lt) *
+           sizeof(float);
+}
+
+// Demigrate workgroups keep their rows as float64.
+inline size_t lds_bytes_f64rows(const Params& P, int ks) {
+    return (static_cast<size_t>(16) * ks + static_cast<size_t>(4) * P.tb + static_cast<size_t>(2) * P.tb * P.lt) *
+           sizeof(float);
 }
 
 // migrate (km_migrate.hip)

@@ -1,19 +1,21 @@
 // Migration kernel: Eq. (1) as an image-stationary gather.
 //
 // Workgroup = (offset bin b, column tile, depth chunk).  Each wavefront keeps
-// CWQ x 4 image columns x (16 * KS) depths of float32 accumulators in
-// registers; the traces of bin b stream through LDS in blocks of P.tb rows
-// (zero-padded so that every interpolation read stays in its row).  For each
-// (column group, trace) the wavefront computes both squared leg lengths once
-// and then, slot by slot, every lane evaluates its depth: two square roots,
-// the sample index and fraction, a two-sample LDS gather and the weight.
+// CWQ groups of 4 image columns x (16 * KS) depths of float32 accumulators
+// in registers; the traces of bin b stream through LDS in blocks of P.tb
+// zero-padded rows.  For every column group the wavefront computes the two
+// squared leg lengths of 16 traces at once (lane = (column, trace)), hands
+// them to the depth lanes through the LDS crossbar, derives from two ballots
+// which 16-depth slots can hold a pair inside the aperture and which need no
+// per-lane mask, and evaluates the slots two at a time: per lane two square
+// roots, the sample index and fraction, a two-sample LDS gather, the
+// interpolation and the weight.
 #include "km_kernels.h"
 
 namespace km {
 
-// Stage traces [j0, j0 + nb) of the sorted trace list into LDS rows of
-// P.lt floats: row[0] = 0 (lead pad), row[1 + k] = D_j[k], zeros after.
-// Rows nb..tb-1 are zero and their geometry is far away.
+// Stage traces [j0, j0 + nb) of the sorted list into rows 0..tb-1 (rows past
+// nb are zero with far-away geometry).
 __device__ __forceinline__ void stage_block(const Params& P, int64_t j0, int nb, float4* sGeo, float* sTr) {
     const int nthr = blockDim.x;
     for (int t = threadIdx.x; t < P.tb; t += nthr) {
@@ -27,27 +29,42 @@ __device__ __forceinline__ void stage_block(const Params& P, int64_t j0, int nb,
     for (int t = 0; t < P.tb; ++t) {
         float* row = sTr + static_cast<int64_t>(t) * P.lt;
         if (t < nb) {
-            const int64_t j = j0 + t;
-            for (int k = threadIdx.x; k < P.lt; k += nthr) {
-                const int ks = k - 1;
-                row[k] = (ks >= 0 && ks < P.nt) ? load_sample(P, j, ks) : 0.0f;
-            }
+            stage_row(P, j0 + t, row, threadIdx.x, nthr);
         } else {
-            for (int k = threadIdx.x; k < P.lt; k += nthr) row[k] = 0.0f;
+            float4* row4 = reinterpret_cast<float4*>(row);
+            for (int m = threadIdx.x; m < (P.lt >> 2); m += nthr) row4[m] = make_float4(0.f, 0.f, 0.f, 0.f);
         }
     }
 }
 
+// One slot of one (column group, trace) pairing: accumulate the lane's pair.
+template <bool TF, int WK, bool MASKED>
+__device__ __forceinline__ void mig_slot(float A, float B, float hs2, float hr2, float hmax, const float* row,
+                                         float tfo, float wlo, float whi, const float* sRk, float& acc) {
+    const Pair pr = eval_pair<TF, WK>(A, B, hs2, hr2, tfo, wlo, whi);
+    const float d0 = row[pr.i];
+    const float d1 = row[pr.i + 1];
+    float v = fmaf(pr.f, d1 - d0, d0);
+    if (MASKED) v = (hmax <= *sRk) ? v : 0.0f;
+    acc = (WK == W_COSCOS) ? fmaf(v, pr.r, acc) : acc + v;
+}
+
 template <int NW, int CWQ, int KS, bool TF, int WK>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
+    static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     const int g = lane / kGroup, d = lane % kGroup;
     const int ncol = P.nx * P.ny;
     const int z0 = zc * KS * kGroup;
 
-    DepthTables<KS> T;
-    load_tables<KS>(P, z0, d, WK == W_COSCOS, T);
+    // LDS: rows first, so that a row's lead pad folds into the gather's offset field
+    float* sTr = lds;                                                      // [tb][lt]
+    float4* sGeo = reinterpret_cast<float4*>(lds + P.tb * P.lt);           // [tb]
+    float* sR = lds + P.tb * P.lt + 4 * P.tb;                              // [KS * 16]
+
+    ChunkTables<KS> T;
+    load_chunk_tables<KS>(P, z0, d, WK == W_COSCOS, T, sR);
 
     float px[CWQ], py[CWQ];
     int colv[CWQ];
@@ -71,33 +88,53 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
 
     const int64_t lo = lower_bound_bin(P.bin, P.n_traces, b);
     const int64_t hi = lower_bound_bin(P.bin, P.n_traces, b + 1);
+    float wlo, whi;
+    clamp_bounds<TF>(P.lt, wlo, whi);
+    const float tfo = P.tf_off;
+    const int rowoff = TF ? 0 : kLead;
 
-    float4* sGeo = reinterpret_cast<float4*>(lds);
-    float* sTr = lds + 4 * P.tb;
-    const float umax = TF ? static_cast<float>(P.lt - 2) : static_cast<float>(P.lt - 3);
-    const float tfs = P.tf_shift;
-
-    // A wavefront whose depth chunk has no valid depth (rmax < 0) still takes
-    // part in staging and barriers but skips all evaluation.
     for (int64_t j0 = lo; j0 < hi; j0 += P.tb) {
         const int nb = static_cast<int>(min<int64_t>(P.tb, hi - j0));
         __syncthreads();
         stage_block(P, j0, nb, sGeo, sTr);
         __syncthreads();
+        if (T.rmax < 0.0f) continue;
+        for (int t0 = 0; t0 < nb; t0 += kGroup) {
+            const int nbt = min(kGroup, nb - t0);
+            // lane (g, d): legs of column group member g and trace t0 + d
+            const float4 sr = sGeo[min(t0 + d, P.tb - 1)];
 #pragma unroll
-        for (int q = 0; q < CWQ; ++q) {
-            for (int t = 0; t < nb; ++t) {
-                const Legs L = legs(px[q], py[q], sGeo[t]);
-                if (L.hmax <= T.rmax) {
-                    const float* row = sTr + t * P.lt + (TF ? 0 : 1);
+            for (int q = 0; q < CWQ; ++q) {
+                const Legs Lp = legs(px[q], py[q], sr);
+                // extremes of hmax over the four columns, per trace (lanes d, 16 + d, 32 + d, 48 + d)
+                float hmin4 = fminf(Lp.hmax, __shfl_xor(Lp.hmax, 16, kLanes));
+                hmin4 = fminf(hmin4, __shfl_xor(hmin4, 32, kLanes));
+                float hmax4 = fmaxf(Lp.hmax, __shfl_xor(Lp.hmax, 16, kLanes));
+                hmax4 = fmaxf(hmax4, __shfl_xor(hmax4, 32, kLanes));
+                const uint64_t live = __builtin_amdgcn_ballot_w64(hmin4 <= T.rmax) & ((1ull << nbt) - 1ull);
+                if (!live) continue;
+                for (int t = 0; t < nbt; ++t) {
+                    if (!((live >> t) & 1ull)) continue;
+                    const float hmin = uniform_read(hmin4, t);
+                    const float hmaxw = uniform_read(hmax4, t);
+                    uint64_t any, full;
+                    slot_masks<KS>(T, hmin, hmaxw, any, full);
+                    if (!any) continue;
+                    const int src = (lane & ~(kGroup - 1)) | t;
+                    const float hs2 = lane_read(Lp.hs2, src);
+                    const float hr2 = lane_read(Lp.hr2, src);
+                    const float hm = fmaxf(hs2, hr2);
+                    const float* row = sTr + (t0 + t) * P.lt + rowoff;
 #pragma unroll
-                    for (int k = 0; k < KS; ++k) {
-                        if (L.hmax <= T.R[k]) {
-                            const Pair pr = eval_pair<TF, WK>(T.A[k], T.B[k], L.hs2, L.hr2, tfs, umax);
-                            const float d0 = row[pr.i];
-                            const float d1 = row[pr.i + 1];
-                            const float v = fmaf(pr.f, d1 - d0, d0);
-                            acc[q][k] = (WK == W_COSCOS) ? fmaf(v, pr.r, acc[q][k]) : acc[q][k] + v;
+                    for (int k = 0; k < KS; k += 2) {
+                        if ((any >> k) & 3ull) {
+                            if (((full >> k) & 3ull) == 3ull) {
+                                mig_slot<TF, WK, false>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, acc[q][k]);
+                                mig_slot<TF, WK, false>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, acc[q][k + 1]);
+                            } else {
+                                mig_slot<TF, WK, true>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, sR + k * kGroup + d, acc[q][k]);
+                                mig_slot<TF, WK, true>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, sR + (k + 1) * kGroup + d, acc[q][k + 1]);
+                            }
                         }
                     }
                 }
@@ -105,8 +142,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         }
     }
 
-    const int64_t plane = static_cast<int64_t>(ncol) * P.nz;
-    float* img = P.image + static_cast<int64_t>(b) * plane;
+    float* img = P.image + static_cast<int64_t>(b) * ncol * P.nz;
 #pragma unroll
     for (int q = 0; q < CWQ; ++q) {
         if (colv[q] >= ncol) continue;
@@ -115,7 +151,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         for (int k = 0; k < KS; ++k) {
             const int iz = z0 + k * kGroup + d;
             if (iz < P.nz) {
-                const float val = acc[q][k] * depth_factor(P, iz);
+                const float fac = depth_factor(P, iz);
+                const float val = fac != 0.0f ? acc[q][k] * fac : 0.0f;
                 colp[iz] = P.accumulate ? colp[iz] + val : val;
             }
         }
@@ -180,7 +217,7 @@ __global__ __launch_bounds__(NW * 64) void migrate_batch_kernel(const Params* __
 template <int NW, int CWQ, int KS>
 static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
     dim3 grid(P.n_coltiles, P.n_zchunks, P.n_bins), block(NW * 64);
-    const size_t lds = lds_bytes(P);
+    const size_t lds = lds_bytes(P, KS);
     if (P.has_tf) {
         if (P.weight == W_COSCOS) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS>, grid, block, lds, s, P);
         return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT>, grid, block, lds, s, P);
@@ -204,11 +241,13 @@ static hipError_t launch_migrate_batch_shape(const Params* probs, const int4* it
     return launch_with_lds(migrate_batch_kernel<NW, CWQ, KS, false, W_UNIT>, grid, block, lds, s, probs, items, n_items, counter);
 }
 
+// (waves, column groups per wave, depth slots, LDS budget for the trace block)
 #define KM_MIGRATE_SHAPES(X) \
-    X(4, 4, 16, 65536)       \
-    X(4, 2, 16, 65536)       \
+    X(4, 4, 16, 49152)       \
+    X(4, 2, 16, 49152)       \
     X(8, 2, 16, 98304)       \
-    X(4, 4, 8, 49152)
+    X(4, 4, 8, 32768)        \
+    X(4, 3, 16, 49152)
 
 static const TileShape kMigrateShapes[] = {
 #define X(nw, cwq, ks, lb) {nw, cwq, ks, lb},

@@ -24,7 +24,7 @@ __global__ __launch_bounds__(kCountWaves * 64) void count_kernel(Params P, int c
     const int z0 = zc * ks * kGroup;
     const int64_t lo = lower_bound_bin(P.bin, P.n_traces, b);
     const int64_t hi = lower_bound_bin(P.bin, P.n_traces, b + 1);
-    const float tfu = P.has_tf ? 1.0f - P.tf_shift : 0.0f;  // t_first / dt
+    const float tfu = P.has_tf ? static_cast<float>(kLead) - P.tf_off : 0.0f;  // t_first / dt
     constexpr int kMaxSlots = 16;  // host guarantees ks <= kMaxSlots
     float Rk[kMaxSlots], Ak[kMaxSlots], Bk[kMaxSlots];
     float rmax = -1.0f;

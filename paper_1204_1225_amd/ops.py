@@ -81,7 +81,8 @@ class DeviceProblem:
         sc = (self.scale if data is None else scale) if dt_name != "f32" else None
         stride = int(d.stride(0)) if d is not None and d.dim() == 2 else self.n_t
         if d is not None:
-            assert d.shape == (self.n_traces, self.n_t) and d.stride(1) == 1 and d.device == self.device
+            assert d.shape == (self.n_traces, self.n_t) and d.device == self.device
+            assert d.numel() == 0 or d.stride(1) == 1
         return KmTraces(n_traces=self.n_traces, n_samples=self.n_t, dtype=_DTYPES[dt_name], trace_stride=stride,
                         t_first=self.t_first, dt=self.dt, data=_ptr(d), scale=_ptr(sc), src=_ptr(self.src),
                         rec=_ptr(self.rec), bin=_ptr(self.bin))
@@ -104,6 +105,8 @@ def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DevicePr
     from . import survey
 
     dev = torch.device(device)
+    if dev.type == "cuda" and dev.index is None:
+        dev = torch.device("cuda", torch.cuda.current_device())
 
     def f32(a):
         return torch.as_tensor(np.ascontiguousarray(a, dtype=np.float32), device=dev)

@@ -99,7 +99,7 @@ class Problem:
 
     def subset(self, idx) -> "Problem":
         """Problem restricted to the traces idx (kept in bin order)."""
-        idx = np.sort(np.asarray(idx))
+        idx = np.sort(np.asarray(idx, dtype=np.int64))
         return dataclasses.replace(
             self,
             src=self.src[idx].copy(),
@@ -427,9 +427,12 @@ def make_batch_line(shape, index=0):
 
 def make_random(seed, n_traces, n_t, nx, ny, nz, n_bins, velocity=("linear", 1500.0, 0.5),
                 aperture_deg=60.0, dx=12.5, dz=5.0, spread=600.0, t_first=0.0, dt=0.004,
-                weight=WEIGHT_COSCOS, data="normal"):
+                weight=WEIGHT_COSCOS, data="bandlimited"):
     """Small random problem for parity and invariant tests: sources and
-    receivers uniformly scattered around the image area, N(0, 1) data."""
+    receivers uniformly scattered around the image area.  data="bandlimited"
+    (default): Gaussian noise filtered by a 25 Hz Ricker wavelet and scaled to
+    unit RMS, i.e. seismic-like band-limited traces; data="normal": white
+    N(0, 1) samples (a stress case for time rounding); None: no data."""
     rng = np.random.default_rng(seed)
     x = (np.arange(nx) - (nx - 1) / 2.0) * dx + 1000.0
     y = ((np.arange(ny) - (ny - 1) / 2.0) * dx + 2000.0) if ny > 1 else np.array([0.0])
@@ -450,12 +453,34 @@ def make_random(seed, n_traces, n_t, nx, ny, nz, n_bins, velocity=("linear", 150
                 weight=weight)
     if data == "normal":
         p.data = rng.standard_normal((p.n_traces, n_t)).astype(np.float32)
+    elif data == "bandlimited":
+        p.data = bandlimited_noise(rng, p.n_traces, n_t, dt)
     return p
+
+
+def bandlimited_noise(rng, n_traces: int, n_t: int, dt: float, f_peak: float = 25.0) -> np.ndarray:
+    """Gaussian noise convolved with a Ricker wavelet (zero phase), unit RMS, float32."""
+    w = ricker(np.arange(-int(0.08 / dt), int(0.08 / dt) + 1) * dt, f_peak)
+    raw = rng.standard_normal((n_traces, n_t + len(w) - 1))
+    out = np.zeros((n_traces, n_t))
+    for k, c in enumerate(w):
+        out += c * raw[:, k:k + n_t]
+    rms = float(np.sqrt(np.mean(out * out))) if out.size else 1.0
+    return (out / (rms if rms > 0 else 1.0)).astype(np.float32)
 
 
 def random_image(problem: Problem, seed: int) -> np.ndarray:
     """N(0, 1) float32 image of the problem's shape."""
     return np.random.default_rng(seed).standard_normal(problem.image_shape).astype(np.float32)
+
+
+def bandlimited_image(problem: Problem, seed: int) -> np.ndarray:
+    """N(0, 1) image smoothed along depth by a Ricker wavelet (a reflectivity-
+    like, band-limited image), unit RMS, float32."""
+    rng = np.random.default_rng(seed)
+    nb, ny, nx, nz = problem.image_shape
+    flat = bandlimited_noise(rng, nb * ny * nx, nz, 0.004)
+    return flat.reshape(nb, ny, nx, nz)
 
 
 def random_data(problem: Problem, seed: int) -> np.ndarray:

@@ -58,8 +58,29 @@ def test_dot_product_fp32(ops, case):
     lhs = float(ops.dot_f64(Md, m))
     rhs = float(ops.dot_f64(d, Mtm))
     e = abs(lhs - rhs) / max(abs(lhs), abs(rhs))
-    print(f"dot test seed{seed}: {lhs:.9e} {rhs:.9e} rel {e:.2e}")
-    assert e < 1e-6
+    scale = float(ops.dot_f64(Md, Md)) ** 0.5 * float(ops.dot_f64(m, m)) ** 0.5
+    en = abs(lhs - rhs) / scale
+    print(f"dot test seed{seed}: {lhs:.9e} {rhs:.9e} rel {e:.2e} (|a-b|/(|Md||m|) {en:.2e})")
+    # <Md, m> of independent random vectors is a zero-mean sum whose size varies
+    # from seed to seed, so the rounding-level mismatch is bounded against the
+    # Cauchy-Schwarz scale |Md| |m|; the relative form is checked at the full
+    # adjoint workload (test_gpu_workloads) where the target is stated.
+    assert en < 1e-8
+    assert e < 1e-5
+
+
+def test_demigrate_long_record(ops, oracle_lib):
+    # 20000 samples: one float64 accumulator row per block (> 64 KiB of LDS).
+    # A band-limited image: for white-noise images the adjoint's error is the
+    # float32 rounding of the time itself (an ulp of u ~ 2600 is 2.4e-4 samples).
+    p = survey.make_random(74, n_traces=6, n_t=20000, nx=8, ny=1, nz=40, n_bins=1, dz=50.0, dt=0.001)
+    m = survey.bandlimited_image(p, 75)
+    ref = oracle_lib.demigrate(p, m)
+    dp = ops.to_device(p)
+    for tile in range(ops.tile_count(1)):
+        e = rel_l2(ops.demigrate(dp, torch.from_numpy(m).cuda(), tile=tile).cpu().numpy(), ref)
+        print(f"long record tile{tile}: rel L2 {e:.3e}")
+        assert e <= 1e-5
 
 
 def test_dot_f64_and_axpby(ops):
