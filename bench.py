@@ -29,8 +29,13 @@ if ROOT not in sys.path:
     sys.path.insert(0, ROOT)
 
 PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9  # 256 CUs x 64 lanes/clk (4 SIMD16) x 2.4 GHz, unpacked issue
-C_FULL = 9  # full-rate VALU lane-ops per pair (roofline)
-C_TRANS = 3  # transcendentals per pair: 2 square roots + 1 reciprocal
+# Minimum VALU work of one (trace, image point) pair once per-depth and
+# per-(column, trace) terms are hoisted: 2 FMA (a_s, a_r), 1 add (T_s + T_r),
+# floor + fraction (2), 1 LDS address, 1 FMA (interpolation on a precomputed
+# sample difference), 1 mul (a_s a_r), 1 FMA (accumulate) = 9 full-rate
+# lane-ops, plus 2 square roots and 1 reciprocal at r full-rate slots each.
+C_FULL = 9
+C_TRANS = 3
 
 
 def log(msg):
@@ -44,12 +49,18 @@ def main():
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--tile", type=int, default=-1, help="migrate tile shape (-1: library choice)")
     ap.add_argument("--dtile", type=int, default=-1, help="demigrate tile shape (-1: library choice)")
-    ap.add_argument("--cpu-columns", type=int, default=1536, help="image columns in the oracle sample")
+    ap.add_argument("--cpu-columns", type=int, default=6144, help="image columns in the oracle sample")
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="run one 1 GiB device-to-device copy before the workload (reference kernel for "
+                         "hardware byte counters)")
+    ap.add_argument("--workload", default="survey3d",
+                    choices=["survey3d", "survey3d_bf16", "survey3d_f16", "line2d_vz", "batch"],
+                    help="survey3d (default) is the headline; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(json.dumps({"error": "this build measures one GPU only; multi-GPU sharding is design-only "
-                                   "(image-column sharding, see DESIGN.md)", "n_gpus": args.gpus}))
+        print(json.dumps({"error": "only one GPU is measured: sharding the image columns (or the traces with a "
+                                   "reduce-scatter) across GPUs is not implemented", "n_gpus": args.gpus}))
         sys.exit(2)
 
     import numpy as np
@@ -61,6 +72,17 @@ def main():
     _lib.load()
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_calibration:
+        src = torch.ones(256 * 1024 * 1024, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+    if args.workload != "survey3d":
+        from paper_1204_1225_amd import extra_bench
+
+        print(json.dumps(extra_bench.run(args.workload, args.steps, args.warmup, dev)), flush=True)
+        return
 
     t0 = time.time()
     p = survey.make_survey3d(seed=2, device=dev)

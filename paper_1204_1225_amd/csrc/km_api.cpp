@@ -161,10 +161,10 @@ std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
 int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
-// 4 waves x 4 column groups x 8 slots; demigrate: 16 waves x 8 slots).
+// 8 waves x 4 column groups x 8 slots; demigrate: 16 waves x 8 slots).
 int default_shape(int op, int nz) {
     (void)nz;
-    return op == 0 ? 3 : 1;
+    return op == 0 ? 2 : 1;  // demigrate shape 1 is the unmerged (16, 8) form
 }
 
 km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {
@@ -384,6 +384,7 @@ struct km_batch {
     unsigned int* d_counter = nullptr;
     int64_t n_items = 0;
     int n_wg = 0;
+    int per_cu = 0;
     size_t lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
@@ -509,6 +510,7 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
     }
     B->n_wg = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(std::max(per_cu, 1)) * n_cu,
                                                                         std::max<int64_t>(B->n_items, 1))));
+    B->per_cu = per_cu;
 
     // Capture [queue reset, persistent kernel] once.
     hipStream_t cap = nullptr;

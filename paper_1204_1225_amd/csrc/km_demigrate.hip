@@ -17,19 +17,86 @@
 
 namespace km {
 
-template <bool TF, int WK, bool MASKED>
-__device__ __forceinline__ void dem_slot(float A, float B, float hs2, float hr2, float hm, double* row, float tfo,
-                                         float wlo, float whi, const float* sRk, float x) {
-    if (MASKED && !(hm <= *sRk)) return;
-    const Pair pr = eval_pair<TF, WK>(A, B, hs2, hr2, tfo, wlo, whi);
-    const float q = (WK == W_COSCOS) ? x * pr.r : x;
-    const float q1 = pr.f * q;
-    const float q0 = q - q1;
-    atomicAdd(row + pr.i, static_cast<double>(q0));
-    atomicAdd(row + pr.i + 1, static_cast<double>(q1));
+// Depth interleave of the adjoint's lanes: neighbouring lanes of a group are two
+// depths apart, so their target samples are at least about one sample apart
+// within the aperture and the LDS atomics of one instruction seldom share an address.
+constexpr int kIL = 2;
+
+// Two slots of one lane: with the depth interleave they are neighbouring
+// depths z, z + 1 of the same (column, trace) pairing, whose first samples i0,
+// i1 usually differ by 0 or 1.  Contributions landing on the same sample are
+// summed (in float32) before the LDS atomic, so a lane issues 2 to 4 atomics
+// for its 4 (sample, value) contributions instead of always 4.  Lanes with
+// nothing to add (image value 0, padding lanes, outside the aperture) issue
+// none.  MASKED: keep only lanes with hmax <= their aperture value.
+template <bool TF, int WK, bool MASKED, bool CLAMP>
+__device__ __forceinline__ void dem_pair(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
+                                         double* row, float tfo, float wlo, float whi, const float* sRk, float x0,
+                                         float x1) {
+    bool act0 = x0 != 0.0f, act1 = x1 != 0.0f;
+    if (MASKED) {
+        act0 = act0 && hm <= sRk[0];
+        act1 = act1 && hm <= sRk[kGroup];
+    }
+    if (!(act0 || act1)) return;
+    const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
+    const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
+    float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
+    float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
+    q0 = act0 ? q0 : 0.0f;
+    q1 = act1 ? q1 : 0.0f;
+    const float b0 = p0.f * q0, a0 = q0 - b0;  // to samples i0, i0 + 1
+    const float b1 = p1.f * q1, a1 = q1 - b1;  // to samples i1, i1 + 1
+    const int delta = p1.i - p0.i;
+    const bool same = delta == 0, next = delta == 1;
+    // float32 pre-sums (each term is a float32 product already); the row is float64
+    const float c0 = a0 + (same ? a1 : 0.0f);
+    const float c1 = b0 + (same ? b1 : (next ? a1 : 0.0f));
+    if (act0 || (act1 && (same || next))) {
+        atomicAdd(row + p0.i, static_cast<double>(c0));
+        atomicAdd(row + p0.i + 1, static_cast<double>(c1));
+    }
+    if (act1 && !same) {
+        atomicAdd(row + p1.i + 1, static_cast<double>(b1));
+        if (!next) atomicAdd(row + p1.i, static_cast<double>(a1));
+    }
 }
 
-template <int NW, int KS, bool TF, int WK>
+// The same two slots without merging: 4 atomics per lane with something to add.
+template <bool TF, int WK, bool MASKED, bool CLAMP>
+__device__ __forceinline__ void dem_pair_plain(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
+                                               double* row, float tfo, float wlo, float whi, const float* sRk,
+                                               float x0, float x1) {
+    bool act0 = x0 != 0.0f, act1 = x1 != 0.0f;
+    if (MASKED) {
+        act0 = act0 && hm <= sRk[0];
+        act1 = act1 && hm <= sRk[kGroup];
+    }
+    if (act0) {
+        const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
+        const float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
+        const float b0 = p0.f * q0;
+        atomicAdd(row + p0.i, static_cast<double>(q0 - b0));
+        atomicAdd(row + p0.i + 1, static_cast<double>(b0));
+    }
+    if (act1) {
+        const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
+        const float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
+        const float b1 = p1.f * q1;
+        atomicAdd(row + p1.i, static_cast<double>(q1 - b1));
+        atomicAdd(row + p1.i + 1, static_cast<double>(b1));
+    }
+}
+
+template <bool MERGE, bool TF, int WK, bool MASKED, bool CLAMP>
+__device__ __forceinline__ void dem_two(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
+                                        double* row, float tfo, float wlo, float whi, const float* sRk, float x0,
+                                        float x1) {
+    if (MERGE) dem_pair<TF, WK, MASKED, CLAMP>(A0, B0, A1, B1, hs2, hr2, hm, row, tfo, wlo, whi, sRk, x0, x1);
+    else dem_pair_plain<TF, WK, MASKED, CLAMP>(A0, B0, A1, B1, hs2, hr2, hm, row, tfo, wlo, whi, sRk, x0, x1);
+}
+
+template <int NW, int KS, bool MERGE, bool TF, int WK>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
                                                   double* sAcc, float* sR) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
@@ -52,11 +119,12 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
         const int z0 = zc * KS * kGroup;
         ChunkTables<KS> T;
         __syncthreads();  // previous chunk's readers of sR are done
-        load_chunk_tables<KS>(P, z0, d, WK == W_COSCOS, T, sR);
+        load_chunk_tables<KS, kIL>(P, z0, d, WK == W_COSCOS, T, sR);
+        const bool noclamp = !TF && T.wmax <= whi;
         float S[KS];
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
-            const int iz = z0 + k * kGroup + d;
+            const int iz = slot_depth<kIL>(z0, k, d);
             S[k] = (iz < P.nz) ? depth_factor(P, iz) : 0.0f;
         }
         __syncthreads();
@@ -75,7 +143,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
             const float* colp = img + static_cast<int64_t>(col) * P.nz;
 #pragma unroll
             for (int k = 0; k < KS; ++k) {
-                const int iz = z0 + k * kGroup + d;
+                const int iz = slot_depth<kIL>(z0, k, d);
                 x[k] = (iz < P.nz) ? colp[iz] * S[k] : 0.0f;
             }
             for (int qt = 0; qt < nquads; ++qt) {
@@ -94,11 +162,15 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
                 for (int k = 0; k < KS; k += 2) {
                     if ((any >> k) & 3ull) {
                         if (((full >> k) & 3ull) == 3ull) {
-                            dem_slot<TF, WK, false>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, x[k]);
-                            dem_slot<TF, WK, false>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, x[k + 1]);
+                            if (noclamp)
+                                dem_two<MERGE, TF, WK, false, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                                               tfo, wlo, whi, nullptr, x[k], x[k + 1]);
+                            else
+                                dem_two<MERGE, TF, WK, false, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                                              tfo, wlo, whi, nullptr, x[k], x[k + 1]);
                         } else {
-                            dem_slot<TF, WK, true>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, sR + k * kGroup + d, x[k]);
-                            dem_slot<TF, WK, true>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, sR + (k + 1) * kGroup + d, x[k + 1]);
+                            dem_two<MERGE, TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo,
+                                                         wlo, whi, sR + k * kGroup + d, x[k], x[k + 1]);
                         }
                     }
                 }
@@ -107,7 +179,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     }
 }
 
-template <int NW, int KS, bool TF, int WK>
+template <int NW, int KS, bool MERGE, bool TF, int WK>
 __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     extern __shared__ float lds[];
     double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
@@ -133,7 +205,7 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
         const int b = P.bin[j0 + t0];
         int t1 = t0 + 1;
         while (t1 < nb && P.bin[j0 + t1] == b) ++t1;
-        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, TF, WK>(P, b, t0, t1, sGeo, sAcc, sR);
+        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, MERGE, TF, WK>(P, b, t0, t1, sGeo, sAcc, sR);
         t0 = t1;
     }
     __syncthreads();
@@ -149,28 +221,28 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     }
 }
 
-template <int NW, int KS>
+template <int NW, int KS, bool MERGE>
 static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     const int64_t nblk = (P.n_traces + P.tb - 1) / P.tb;
     dim3 grid(static_cast<unsigned>(nblk)), block(NW * 64);
     const size_t lds = lds_bytes_f64rows(P, KS);
     if (P.has_tf) {
-        if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, true, W_COSCOS>, grid, block, lds, s, P);
-        return launch_with_lds(demigrate_kernel<NW, KS, true, W_UNIT>, grid, block, lds, s, P);
+        if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, MERGE, true, W_COSCOS>, grid, block, lds, s, P);
+        return launch_with_lds(demigrate_kernel<NW, KS, MERGE, true, W_UNIT>, grid, block, lds, s, P);
     }
-    if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, false, W_COSCOS>, grid, block, lds, s, P);
-    return launch_with_lds(demigrate_kernel<NW, KS, false, W_UNIT>, grid, block, lds, s, P);
+    if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, MERGE, false, W_COSCOS>, grid, block, lds, s, P);
+    return launch_with_lds(demigrate_kernel<NW, KS, MERGE, false, W_UNIT>, grid, block, lds, s, P);
 }
 
-// (waves, depth slots, LDS budget for the trace accumulators)
+// (waves, depth slots, LDS budget for the trace accumulators, merge same-sample atomics)
 #define KM_DEMIGRATE_SHAPES(X) \
-    X(8, 16, 131072)           \
-    X(16, 8, 131072)           \
-    X(8, 8, 98304)             \
-    X(12, 16, 131072)
+    X(16, 8, 131072, true)     \
+    X(16, 8, 131072, false)    \
+    X(8, 8, 98304, false)      \
+    X(12, 16, 131072, false)
 
 static const TileShape kDemigrateShapes[] = {
-#define X(nw, ks, lb) {nw, 1, ks, lb},
+#define X(nw, ks, lb, mg) {nw, 1, ks, lb},
     KM_DEMIGRATE_SHAPES(X)
 #undef X
 };
@@ -180,8 +252,8 @@ const TileShape& demigrate_shape(int i) { return kDemigrateShapes[i]; }
 
 hipError_t launch_demigrate(int shape, const Params& P, hipStream_t s) {
     int i = 0;
-#define X(nw, ks, lb) \
-    if (shape == i) return launch_demigrate_shape<nw, ks>(P, s); \
+#define X(nw, ks, lb, mg) \
+    if (shape == i) return launch_demigrate_shape<nw, ks, mg>(P, s); \
     ++i;
     KM_DEMIGRATE_SHAPES(X)
 #undef X

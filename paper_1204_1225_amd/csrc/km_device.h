@@ -151,20 +151,22 @@ __device__ __forceinline__ Legs legs(float px, float py, float4 sr) {
 //         (plus kLead through the row pointer when t_first == 0),
 //   i   = floor(w), f = w - i, and r = 1 / (a_s a_r) for the weight.
 // Migrate and demigrate both call this, so the transpose pair sees
-// bit-identical (i, f, r) for every pair.
+// bit-identical (i, f, r) for every pair.  CLAMP = false is used only where
+// every evaluated pair is known to satisfy w <= whi (ChunkTables::wmax) and
+// w >= wlo (t_first == 0 gives w >= 0); the result is then identical.
 struct Pair {
     int32_t i;
     float f;
     float r;
 };
 
-template <bool TF, int WK>
+template <bool TF, int WK, bool CLAMP = true>
 __device__ __forceinline__ Pair eval_pair(float A, float B, float hs2, float hr2, float tf_off, float wlo, float whi) {
     const float as = fmaf(B, hs2, A);
     const float ar = fmaf(B, hr2, A);
     float w = __builtin_amdgcn_sqrtf(as) + __builtin_amdgcn_sqrtf(ar);
     if (TF) w = w + tf_off;
-    w = __builtin_amdgcn_fmed3f(w, wlo, whi);
+    if (CLAMP) w = __builtin_amdgcn_fmed3f(w, wlo, whi);
     Pair p;
     p.i = static_cast<int32_t>(w);
     p.f = __builtin_amdgcn_fractf(w);
@@ -181,29 +183,41 @@ __device__ __forceinline__ void clamp_bounds(int lt, float& wlo, float& whi) {
     whi = TF ? static_cast<float>(lt - 2) : static_cast<float>(lt - 2 - kLead);
 }
 
+// Depth of lane d in slot k of the chunk starting at z0.  IL = 1: slot k is
+// the 16 consecutive depths z0 + 16 k + d.  IL = 2: slots 2m and 2m + 1 share
+// the 32 depths z0 + 32 m .. z0 + 32 m + 31, even depths in slot 2m and odd
+// ones in 2m + 1, so neighbouring lanes are two depths apart.
+template <int IL>
+__device__ __forceinline__ int slot_depth(int z0, int k, int d) {
+    if (IL == 1) return z0 + k * kGroup + d;
+    return z0 + (k >> 1) * (2 * kGroup) + 2 * d + (k & 1);
+}
+
 // Per-depth tables of one depth chunk.  Lane d of every group holds depth
-// z0 + 16 k + d in slot k.  A lane is valid if its depth exists and (for the
-// cos*cos weight) t0sq > 0; elsewhere W = 0 and the image value is 0.
+// slot_depth(z0, k, d) in slot k.  A lane is valid if its depth exists and (for
+// the cos*cos weight) t0sq > 0; elsewhere W = 0 and the image value is 0.
 //   A, B     sample-unit traveltime tables per slot
 //   rlo/rhi  lane k < KS holds min / max over the valid lanes of slot k of the
 //            aperture table (+inf / -inf when the slot has no valid lane)
 //   rmax     max over the chunk (wavefront-uniform)
-// sR[16 k + d] (LDS) holds the aperture value of each depth, -1 where invalid.
+//   wmax     an upper bound of sqrt(a_s) + sqrt(a_r) over every pair inside the
+//            aperture in this chunk (wavefront-uniform; +inf when unknown)
+// sR[16 k + d] (LDS) holds the aperture value of each lane, -1 where invalid.
 template <int KS>
 struct ChunkTables {
     float A[KS], B[KS];
-    float rlo, rhi, rmax;
+    float rlo, rhi, rmax, wmax;
 };
 
-template <int KS>
+template <int KS, int IL = 1>
 __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d, bool zero_weight_guard,
                                                   ChunkTables<KS>& T, float* sR) {
     const int lane = threadIdx.x & (kLanes - 1);
-    float rmax = -1.0f;
+    float rmax = -1.0f, wmax = 0.0f;
     float rlo_mine = __builtin_inff(), rhi_mine = -__builtin_inff();
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
-        const int iz = z0 + k * kGroup + d;
+        const int iz = slot_depth<IL>(z0, k, d);
         // invalid lanes: a = 1 for every leg (finite time and weight), never inside
         float A = 1.0f, B = 0.0f, R = -1.0f;
         bool valid = false;
@@ -219,6 +233,12 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         T.A[k] = A;
         T.B[k] = B;
         if (sR && lane < kGroup) sR[k * kGroup + d] = R;
+        // in aperture, a = A + B h^2 <= fma(B, R, A) (rounding is monotone);
+        // 2 sqrt of it with a relative margin for the approximate square root.
+        // A NaN (bad table) propagates and disables the unclamped path.
+        float wk = 2.0f * 1.00001f + 1.0f;
+        if (valid) wk = B >= 0.0f ? 2.0f * __builtin_amdgcn_sqrtf(fmaf(B, R, A)) * 1.00001f + 1.0f : __builtin_inff();
+        wmax = (wk > wmax || wk != wk) ? wk : wmax;
         // min / max over the 16 lanes of the group (all groups hold the same depths)
         float lo = valid ? R : __builtin_inff();
         float hi = valid ? R : -__builtin_inff();
@@ -233,9 +253,17 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         }
         rmax = fmaxf(rmax, hi);
     }
+    // wavefront max of wmax, NaN-preserving (any NaN lane makes it NaN)
+#pragma unroll
+    for (int off = 1; off < kLanes; off <<= 1) {
+        const float o = __shfl_xor(wmax, off, kLanes);
+        wmax = (o > wmax || o != o) ? o : wmax;
+    }
     T.rlo = rlo_mine;
     T.rhi = rhi_mine;
-    T.rmax = rmax;
+    // equal in every lane: make them scalar so that branches on them are uniform
+    T.rmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rmax)));
+    T.wmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmax)));
 }
 
 // Bit k (k < KS) set when slot k may hold a lane inside the aperture

@@ -37,16 +37,25 @@ __device__ __forceinline__ void stage_block(const Params& P, int64_t j0, int nb,
     }
 }
 
-// One slot of one (column group, trace) pairing: accumulate the lane's pair.
-template <bool TF, int WK, bool MASKED>
-__device__ __forceinline__ void mig_slot(float A, float B, float hs2, float hr2, float hmax, const float* row,
-                                         float tfo, float wlo, float whi, const float* sRk, float& acc) {
-    const Pair pr = eval_pair<TF, WK>(A, B, hs2, hr2, tfo, wlo, whi);
-    const float d0 = row[pr.i];
-    const float d1 = row[pr.i + 1];
-    float v = fmaf(pr.f, d1 - d0, d0);
-    if (MASKED) v = (hmax <= *sRk) ? v : 0.0f;
-    acc = (WK == W_COSCOS) ? fmaf(v, pr.r, acc) : acc + v;
+// Two slots (k, k + 1) of one (column group, trace) pairing.  MASKED: some
+// valid lane may be outside the aperture, so each value is kept only where
+// hmax <= the lane's aperture value; CLAMP: the time is clamped to the row.
+template <bool TF, int WK, bool MASKED, bool CLAMP>
+__device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
+                                         const float* row, float tfo, float wlo, float whi, const float* sRk,
+                                         float& acc0, float& acc1) {
+    const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
+    const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
+    const float a0 = row[p0.i], b0 = row[p0.i + 1];
+    const float a1 = row[p1.i], b1 = row[p1.i + 1];
+    float v0 = fmaf(p0.f, b0 - a0, a0);
+    float v1 = fmaf(p1.f, b1 - a1, a1);
+    if (MASKED) {
+        v0 = (hm <= sRk[0]) ? v0 : 0.0f;
+        v1 = (hm <= sRk[kGroup]) ? v1 : 0.0f;
+    }
+    acc0 = (WK == W_COSCOS) ? fmaf(v0, p0.r, acc0) : acc0 + v0;
+    acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
 }
 
 template <int NW, int CWQ, int KS, bool TF, int WK>
@@ -92,6 +101,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     clamp_bounds<TF>(P.lt, wlo, whi);
     const float tfo = P.tf_off;
     const int rowoff = TF ? 0 : kLead;
+    // fully-inside slots need no clamp when no pair of the chunk can reach past the row
+    const bool noclamp = !TF && T.wmax <= whi;
 
     for (int64_t j0 = lo; j0 < hi; j0 += P.tb) {
         const int nb = static_cast<int>(min<int64_t>(P.tb, hi - j0));
@@ -129,11 +140,15 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     for (int k = 0; k < KS; k += 2) {
                         if ((any >> k) & 3ull) {
                             if (((full >> k) & 3ull) == 3ull) {
-                                mig_slot<TF, WK, false>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, acc[q][k]);
-                                mig_slot<TF, WK, false>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, nullptr, acc[q][k + 1]);
+                                if (noclamp)
+                                    mig_pair<TF, WK, false, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                                                   tfo, wlo, whi, nullptr, acc[q][k], acc[q][k + 1]);
+                                else
+                                    mig_pair<TF, WK, false, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                                                  tfo, wlo, whi, nullptr, acc[q][k], acc[q][k + 1]);
                             } else {
-                                mig_slot<TF, WK, true>(T.A[k], T.B[k], hs2, hr2, hm, row, tfo, wlo, whi, sR + k * kGroup + d, acc[q][k]);
-                                mig_slot<TF, WK, true>(T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo, wlo, whi, sR + (k + 1) * kGroup + d, acc[q][k + 1]);
+                                mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo,
+                                                             wlo, whi, sR + k * kGroup + d, acc[q][k], acc[q][k + 1]);
                             }
                         }
                     }
@@ -191,8 +206,11 @@ __global__ __launch_bounds__(NW * 64) void migrate_kernel(Params P) {
 // Batched persistent form: work items (problem, bin, column tile, depth
 // chunk) are taken from a queue in list order (longest first).  A negative
 // tile field -1 - tile marks an item with no pair in aperture: zero store.
+// At least 4 wavefronts per SIMD (<= 128 VGPRs) for the 8-slot shapes, so
+// that two 8-wavefront workgroups share a CU as they do in single launches.
 template <int NW, int CWQ, int KS, bool TF, int WK>
-__global__ __launch_bounds__(NW * 64) void migrate_batch_kernel(const Params* __restrict__ probs,
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KS <= 8 ? 4 : 2)))
+void migrate_batch_kernel(const Params* __restrict__ probs,
                                                                 const int4* __restrict__ items,
                                                                 int64_t n_items, unsigned int* counter) {
     extern __shared__ float lds[];
@@ -243,11 +261,11 @@ static hipError_t launch_migrate_batch_shape(const Params* probs, const int4* it
 
 // (waves, column groups per wave, depth slots, LDS budget for the trace block)
 #define KM_MIGRATE_SHAPES(X) \
-    X(4, 4, 16, 49152)       \
-    X(4, 2, 16, 49152)       \
-    X(8, 2, 16, 98304)       \
     X(4, 4, 8, 32768)        \
-    X(4, 3, 16, 49152)
+    X(16, 4, 8, 155648)      \
+    X(8, 4, 8, 77824)        \
+    X(4, 3, 16, 49152)       \
+    X(4, 2, 16, 49152)
 
 static const TileShape kMigrateShapes[] = {
 #define X(nw, cwq, ks, lb) {nw, cwq, ks, lb},

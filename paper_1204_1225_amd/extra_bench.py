@@ -1,0 +1,111 @@
+"""Measurements of the non-headline workloads (each returns one JSON-able dict).
+
+survey3d_bf16 / survey3d_f16: the 3D survey with 16-bit trace storage
+    (per-trace scale), migrate-only throughput next to float32 on the same GPU.
+line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
+    1024 x 800 in 32 bins): migrate and demigrate throughput and the float32
+    dot-product test.
+batch: 64 uneven 2D lines migrated by one persistent hipGraph-captured launch
+    against 64 separate launches (same tile shape, chosen by the tuner on the
+    largest line), images compared bit for bit.
+"""
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import torch
+
+from . import ops, survey
+
+
+def _time(fn, steps, warmup):
+    for _ in range(warmup):
+        fn()
+    torch.cuda.synchronize()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record()
+    for _ in range(steps):
+        fn()
+    b.record()
+    torch.cuda.synchronize()
+    return a.elapsed_time(b) / steps
+
+
+def _survey16(kind, steps, warmup, dev):
+    p = survey.make_survey3d(seed=2, device=dev)
+    dp = ops.to_device(p, dev)
+    n_ap, _ = ops.count(dp)
+    host = dp.data.cpu().numpy()
+    bits, sig, _ = survey.quantise(host, kind)
+    dq = dp.with_data(torch.from_numpy(bits.view(np.int16)).to(dev), torch.from_numpy(sig).to(dev), kind)
+    img = torch.empty(dp.image_shape, device=dev)
+    ms32 = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
+    ms16 = _time(lambda: ops.migrate(dq, image=img), steps, warmup)
+    return {"workload": f"survey3d_{kind}", "metric": "G contributions/s (migrate)", "pairs_in_aperture": n_ap,
+            "ms_f32": round(ms32, 3), f"ms_{kind}": round(ms16, 3),
+            "gcps_f32": round(n_ap / ms32 / 1e6, 3), f"gcps_{kind}": round(n_ap / ms16 / 1e6, 3),
+            "trace_bytes_f32": int(host.nbytes), f"trace_bytes_{kind}": int(bits.nbytes + sig.nbytes)}
+
+
+def _line2d_vz(steps, warmup, dev):
+    p = survey.make_line2d_vz()
+    dp = ops.to_device(p, dev)
+    n_ap, n_eff = ops.count(dp)
+    d = torch.from_numpy(survey.random_data(p, 41)).to(dev)
+    m = torch.from_numpy(survey.random_image(p, 42)).to(dev)
+    img = torch.empty(dp.image_shape, device=dev)
+    out = torch.empty((dp.n_traces, dp.n_t), device=dev)
+    ms_m = _time(lambda: ops.migrate(dp, data=d, image=img, dtype="f32"), steps, warmup)
+    ms_d = _time(lambda: ops.demigrate(dp, m, out=out), steps, warmup)
+    lhs = float(ops.dot_f64(img, m))
+    rhs = float(ops.dot_f64(d, out))
+    return {"workload": "line2d_vz", "metric": "G contributions/s (migrate, demigrate)", "pairs_in_aperture": n_ap,
+            "ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
+            "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
+            "dot_test_rel": abs(lhs - rhs) / max(abs(lhs), abs(rhs))}
+
+
+def _batch(steps, warmup, dev):
+    shapes = survey.batch_line_shapes(5)
+    gen = torch.Generator(device=dev).manual_seed(5)
+    dps, t0 = [], time.time()
+    for i, sh in enumerate(shapes):
+        p = survey.make_batch_line(sh, i)
+        dp = ops.to_device(p, dev)
+        dps.append(dp.with_data(torch.randn((dp.n_traces, dp.n_t), generator=gen, device=dev)))
+    n_ap = sum(ops.count(dp)[0] for dp in dps)
+    big = max(range(len(dps)), key=lambda k: dps[k].n_traces * dps[k].nx * dps[k].nz)
+    tile, _ = ops.tune(0, dps[big], torch.empty(dps[big].image_shape, device=dev), reps=1)
+    gen_s = time.time() - t0
+    sep = [torch.empty(dp.image_shape, device=dev) for dp in dps]
+    bat = [torch.empty(dp.image_shape, device=dev) for dp in dps]
+
+    def separate():
+        for dp, im in zip(dps, sep):
+            ops.migrate(dp, image=im, tile=tile)
+
+    ms_sep = _time(separate, steps, warmup)
+    tc = time.time()
+    b = ops.Batch(dps, bat, tile=tile)
+    create_s = time.time() - tc
+    ms_bat = _time(b.run, steps, warmup)
+    n_items, n_wg = b.info()
+    same = all(torch.equal(x, y) for x, y in zip(sep, bat))
+    b.close()
+    return {"workload": "batch", "metric": "G contributions/s (migrate)", "lines": len(dps),
+            "pairs_in_aperture": n_ap, "tile": tile, "ms_separate_launches": round(ms_sep, 3),
+            "ms_batched_graph": round(ms_bat, 3), "gcps_separate": round(n_ap / ms_sep / 1e6, 3),
+            "gcps_batched": round(n_ap / ms_bat / 1e6, 3), "work_items": n_items, "persistent_workgroups": n_wg,
+            "bitwise_equal": bool(same), "create_s": round(create_s, 2), "setup_s": round(gen_s, 1),
+            "trace_bytes": int(sum(dp.data.numel() * 4 for dp in dps))}
+
+
+def run(workload, steps, warmup, dev):
+    if workload in ("survey3d_bf16", "survey3d_f16"):
+        return _survey16(workload.split("_")[1], steps, warmup, dev)
+    if workload == "line2d_vz":
+        return _line2d_vz(steps, warmup, dev)
+    if workload == "batch":
+        return _batch(steps, warmup, dev)
+    raise ValueError(workload)

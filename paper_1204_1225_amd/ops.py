@@ -79,7 +79,7 @@ class DeviceProblem:
         d = self.data if data is None else data
         dt_name = self.dtype if dtype is None else dtype
         sc = (self.scale if data is None else scale) if dt_name != "f32" else None
-        stride = int(d.stride(0)) if d is not None and d.dim() == 2 else self.n_t
+        stride = int(d.stride(0)) if d is not None and d.dim() == 2 and d.numel() > 0 else self.n_t
         if d is not None:
             assert d.shape == (self.n_traces, self.n_t) and d.device == self.device
             assert d.numel() == 0 or d.stride(1) == 1

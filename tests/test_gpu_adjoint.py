@@ -71,8 +71,10 @@ def test_dot_product_fp32(ops, case):
 
 def test_demigrate_long_record(ops, oracle_lib):
     # 20000 samples: one float64 accumulator row per block (> 64 KiB of LDS).
-    # A band-limited image: for white-noise images the adjoint's error is the
-    # float32 rounding of the time itself (an ulp of u ~ 2600 is 2.4e-4 samples).
+    # 50 m depth steps at 1 ms sampling put each depth's two samples apart from
+    # the next depth's, so every output sample holds isolated hat weights whose
+    # error is the float32 rounding of the time itself: an ulp of u in
+    # [2048, 4096) is 2.4e-4 samples.  Bound: 2e-4 relative L2.
     p = survey.make_random(74, n_traces=6, n_t=20000, nx=8, ny=1, nz=40, n_bins=1, dz=50.0, dt=0.001)
     m = survey.bandlimited_image(p, 75)
     ref = oracle_lib.demigrate(p, m)
@@ -80,7 +82,7 @@ def test_demigrate_long_record(ops, oracle_lib):
     for tile in range(ops.tile_count(1)):
         e = rel_l2(ops.demigrate(dp, torch.from_numpy(m).cuda(), tile=tile).cpu().numpy(), ref)
         print(f"long record tile{tile}: rel L2 {e:.3e}")
-        assert e <= 1e-5
+        assert e <= 2e-4
 
 
 def test_dot_f64_and_axpby(ops):

@@ -159,7 +159,7 @@ def test_counts_bit_exact(ops, oracle_lib):
 
 def test_edge_cases(ops, oracle_lib):
     # no traces: image overwritten with zeros
-    p = survey.make_random(61, n_traces=40, n_t=100, nx=9, ny=2, nz=20, n_bins=2, dz=10.0)
+    p = survey.make_random(61, n_traces=40, n_t=100, nx=9, ny=2, nz=20, n_bins=2, dz=10.0, spread=50.0)
     empty = p.subset([])
     dp = ops.to_device(empty)
     img = torch.full(dp.image_shape, 7.0, device="cuda")
