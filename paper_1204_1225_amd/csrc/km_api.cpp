@@ -139,7 +139,15 @@ int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
 
 km_status shape_params(int op, int shape, km::Params& P) {
     const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
-    P.tb = traces_per_block(P.lt, S.lds_budget, S.depth_slots, op == 0 ? 4 : 8);
+    if (op == 0) {
+        P.tb = traces_per_block(P.lt, S.lds_budget, S.depth_slots, 4);
+    } else {
+        // float64 rows; the four groups of a wavefront take four traces, so
+        // whole quads of traces keep every group busy
+        P.tb = traces_per_block(P.lt, S.lds_budget, 0, 8);
+        if (S.max_quads > 0) P.tb = std::min(P.tb, 4 * S.max_quads);
+        if (P.tb >= 4) P.tb &= ~3;
+    }
     if (P.tb < 1) return fail(KM_E_UNSUPPORTED, "record of %d samples does not fit in LDS", P.nt);
     const int zchunk = 16 * S.depth_slots;
     P.n_zchunks = (P.nz + zchunk - 1) / zchunk;
@@ -161,10 +169,11 @@ std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
 int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
-// 8 waves x 4 column groups x 8 slots; demigrate: 16 waves x 8 slots).
+// 8 waves x 4 column groups x 8 slots; demigrate: 16 waves x 8 slots x 3
+// trace quads).
 int default_shape(int op, int nz) {
     (void)nz;
-    return op == 0 ? 2 : 1;  // demigrate shape 1 is the unmerged (16, 8) form
+    return op == 0 ? 2 : 0;
 }
 
 km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {

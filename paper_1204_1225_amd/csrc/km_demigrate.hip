@@ -6,13 +6,16 @@
 // float64 because gfx950 executes LDS float64 atomic adds at about 8 clocks
 // per wavefront instruction and float32 ones at about 190 (measured), and the
 // wider sum also keeps the transpose's own rounding negligible.
-// Wavefronts sweep the image columns of each bin present in the block, one
-// column per wavefront at a time; the four 16-lane groups of a wavefront work
-// on four different traces of the block (lanes = 16 consecutive depths), so
-// that the LDS float atomics of one instruction land in four different rows
-// and seldom on the same address.  The image values of the column are loaded
-// once and serve every trace of the block.  Each row is written back to HBM
-// exactly once.
+//
+// Wavefronts sweep the image columns that can be inside the aperture of some
+// trace of the block (a box computed per depth chunk), one column per
+// wavefront at a time; the four 16-lane groups of a wavefront work on four
+// different traces of the block (lanes = 16 depths), so the LDS atomics of one
+// instruction land in four different rows.  The next column's image values
+// are loaded while the current one is evaluated, and the inner loop reads
+// nothing from LDS (tables, aperture values and trace geometry are in
+// registers), so no wait on a read ever waits behind the queued atomics.
+// Each row is written back to HBM exactly once.
 #include "km_kernels.h"
 
 namespace km {
@@ -22,65 +25,75 @@ namespace km {
 // within the aperture and the LDS atomics of one instruction seldom share an address.
 constexpr int kIL = 2;
 
-// Two slots of one lane: with the depth interleave they are neighbouring
-// depths z, z + 1 of the same (column, trace) pairing, whose first samples i0,
-// i1 usually differ by 0 or 1.  Contributions landing on the same sample are
-// summed (in float32) before the LDS atomic, so a lane issues 2 to 4 atomics
-// for its 4 (sample, value) contributions instead of always 4.  Lanes with
-// nothing to add (image value 0, padding lanes, outside the aperture) issue
-// none.  MASKED: keep only lanes with hmax <= their aperture value.
-template <bool TF, int WK, bool MASKED, bool CLAMP>
-__device__ __forceinline__ void dem_pair(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
-                                         double* row, float tfo, float wlo, float whi, const float* sRk, float x0,
-                                         float x1) {
-    bool act0 = x0 != 0.0f, act1 = x1 != 0.0f;
-    if (MASKED) {
-        act0 = act0 && hm <= sRk[0];
-        act1 = act1 && hm <= sRk[kGroup];
-    }
-    if (!(act0 || act1)) return;
-    const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
-    const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
-    float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
-    float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
-    q0 = act0 ? q0 : 0.0f;
-    q1 = act1 ? q1 : 0.0f;
-    const float b0 = p0.f * q0, a0 = q0 - b0;  // to samples i0, i0 + 1
-    const float b1 = p1.f * q1, a1 = q1 - b1;  // to samples i1, i1 + 1
-    const int delta = p1.i - p0.i;
-    const bool same = delta == 0, next = delta == 1;
-    // float32 pre-sums (each term is a float32 product already); the row is float64
-    const float c0 = a0 + (same ? a1 : 0.0f);
-    const float c1 = b0 + (same ? b1 : (next ? a1 : 0.0f));
-    if (act0 || (act1 && (same || next))) {
-        atomicAdd(row + p0.i, static_cast<double>(c0));
-        atomicAdd(row + p0.i + 1, static_cast<double>(c1));
-    }
-    if (act1 && !same) {
-        atomicAdd(row + p1.i + 1, static_cast<double>(b1));
-        if (!next) atomicAdd(row + p1.i, static_cast<double>(a1));
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 1; off < kLanes; off <<= 1) v = fminf(v, __shfl_xor(v, off, kLanes));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 1; off < kLanes; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, kLanes));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// First and last index of v[0..n) with a <= v[i] <= b (compared in float64);
+// lo > hi when there is none.  Wavefront-uniform.
+__device__ __forceinline__ void index_range(const float* __restrict__ v, int n, double a, double b, int& lo, int& hi) {
+    const int lane = threadIdx.x & (kLanes - 1);
+    lo = n;
+    hi = -1;
+    for (int base = 0; base < n; base += kLanes) {
+        const int i = base + lane;
+        bool in = false;
+        if (i < n) {
+            const double c = v[i];
+            in = c >= a && c <= b;
+        }
+        const uint64_t m = __builtin_amdgcn_ballot_w64(in);
+        if (m) {
+            if (lo == n) lo = base + __builtin_ctzll(m);
+            hi = base + 63 - __builtin_clzll(m);
+        }
     }
 }
 
-// The same two slots without merging: 4 atomics per lane with something to add.
-template <bool TF, int WK, bool MASKED, bool CLAMP>
-__device__ __forceinline__ void dem_pair_plain(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
-                                               double* row, float tfo, float wlo, float whi, const float* sRk,
-                                               float x0, float x1) {
-    bool act0 = x0 != 0.0f, act1 = x1 != 0.0f;
-    if (MASKED) {
-        act0 = act0 && hm <= sRk[0];
-        act1 = act1 && hm <= sRk[kGroup];
-    }
+// Bits of the four 16-lane groups of a ballot, OR-ed / AND-ed into 16 bits.
+__device__ __forceinline__ uint32_t fold_or(uint64_t m) {
+    return static_cast<uint32_t>((m | (m >> 16) | (m >> 32) | (m >> 48)) & 0xFFFFull);
+}
+__device__ __forceinline__ uint32_t fold_and(uint64_t m) {
+    return static_cast<uint32_t>((m & (m >> 16) & (m >> 32) & (m >> 48)) & 0xFFFFull);
+}
+
+// Two slots whose every lane is inside the aperture: 4 atomics per lane, no mask.
+template <bool TF, int WK, bool CLAMP>
+__device__ __forceinline__ void dem_full(float A0, float B0, float A1, float B1, float hs2, float hr2, double* row,
+                                         float tfo, float wlo, float whi, float x0, float x1) {
+    const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
+    const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
+    const float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
+    const float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
+    const float b0 = p0.f * q0, b1 = p1.f * q1;
+    atomicAdd(row + p0.i, static_cast<double>(q0 - b0));
+    atomicAdd(row + p0.i + 1, static_cast<double>(b0));
+    atomicAdd(row + p1.i, static_cast<double>(q1 - b1));
+    atomicAdd(row + p1.i + 1, static_cast<double>(b1));
+}
+
+// Two slots with a per-lane aperture mask.
+template <bool TF, int WK>
+__device__ __forceinline__ void dem_masked(float A0, float B0, float A1, float B1, float hs2, float hr2, double* row,
+                                           float tfo, float wlo, float whi, float x0, float x1, bool act0, bool act1) {
     if (act0) {
-        const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
+        const Pair p0 = eval_pair<TF, WK, true>(A0, B0, hs2, hr2, tfo, wlo, whi);
         const float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
         const float b0 = p0.f * q0;
         atomicAdd(row + p0.i, static_cast<double>(q0 - b0));
         atomicAdd(row + p0.i + 1, static_cast<double>(b0));
     }
     if (act1) {
-        const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
+        const Pair p1 = eval_pair<TF, WK, true>(A1, B1, hs2, hr2, tfo, wlo, whi);
         const float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
         const float b1 = p1.f * q1;
         atomicAdd(row + p1.i, static_cast<double>(q1 - b1));
@@ -88,38 +101,66 @@ __device__ __forceinline__ void dem_pair_plain(float A0, float B0, float A1, flo
     }
 }
 
-template <bool MERGE, bool TF, int WK, bool MASKED, bool CLAMP>
-__device__ __forceinline__ void dem_two(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
-                                        double* row, float tfo, float wlo, float whi, const float* sRk, float x0,
-                                        float x1) {
-    if (MERGE) dem_pair<TF, WK, MASKED, CLAMP>(A0, B0, A1, B1, hs2, hr2, hm, row, tfo, wlo, whi, sRk, x0, x1);
-    else dem_pair_plain<TF, WK, MASKED, CLAMP>(A0, B0, A1, B1, hs2, hr2, hm, row, tfo, wlo, whi, sRk, x0, x1);
+// Coordinates and image values (depth slots of this lane) of box column m.
+template <int KS>
+__device__ __forceinline__ void fetch_column(const Params& P, const float* img, int z0, int d, int m, int nbx, int ix0,
+                                             int iy0, float* xv, float& px, float& py) {
+    const int ix = ix0 + m % nbx, iy = iy0 + m / nbx;
+    px = P.x[ix];
+    py = P.y[iy];
+    const float* colp = img + (static_cast<int64_t>(iy) * P.nx + ix) * P.nz;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int iz = slot_depth<kIL>(z0, k, d);
+        xv[k] = iz < P.nz ? colp[iz] : 0.0f;
+    }
 }
 
-template <int NW, int KS, bool MERGE, bool TF, int WK>
+// Traces t0..t1-1 of the block (one bin b, at most 4 NQ traces).
+template <int NW, int KS, int NQ, bool TF, int WK>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
-                                                  double* sAcc, float* sR) {
+                                                  double* sAcc) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
+    constexpr uint32_t kMask = (KS >= 32) ? ~0u : ((1u << KS) - 1u);
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     const int g = lane / kGroup, d = lane % kGroup;
-    const int ncol = P.nx * P.ny;
-    const int nseg = t1 - t0;  // <= tb <= 64
-    const int nquads = (nseg + kGroupsPerWave - 1) / kGroupsPerWave;
+    const int nseg = t1 - t0;
+    const int nq = (nseg + kGroupsPerWave - 1) / kGroupsPerWave;
     float wlo, whi;
     clamp_bounds<TF>(P.lt, wlo, whi);
     const float tfo = P.tf_off;
     const int rowoff = TF ? 0 : kLead;
-    const float* img = P.image + static_cast<int64_t>(b) * ncol * P.nz;
-    const uint64_t segmask = nseg >= 64 ? ~0ull : ((1ull << nseg) - 1ull);
-    // lane-parallel geometry: lane l <-> trace t0 + l (far away past the segment)
-    const float4 srl = lane < nseg ? sGeo[t0 + lane] : make_float4(kFar, kFar, kFar, kFar);
+    const float* img = P.image + static_cast<int64_t>(b) * P.nx * P.ny * P.nz;
+
+    // group g of quad q works on trace 4 q + g of the segment (far away past its end)
+    float4 G[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) {
+        const int t = kGroupsPerWave * q + g;
+        G[q] = t < nseg ? sGeo[t0 + t] : make_float4(kFar, kFar, kFar, kFar);
+    }
+    // A column can be inside the aperture of trace j only if both its legs are
+    // at most sqrt(r2) long, so in x it lies in [max(sx, rx) - rho, min(sx, rx) + rho]
+    // (likewise in y); the union over the segment's traces bounds the columns.
+    float ax = __builtin_inff(), bx = -__builtin_inff(), ay = __builtin_inff(), by = -__builtin_inff();
+    if (lane < nseg) {
+        const float4 s = sGeo[t0 + lane];
+        ax = fmaxf(s.x, s.z);
+        bx = fminf(s.x, s.z);
+        ay = fmaxf(s.y, s.w);
+        by = fminf(s.y, s.w);
+    }
+    ax = wave_min(ax);
+    bx = wave_max(bx);
+    ay = wave_min(ay);
+    by = wave_max(by);
 
     for (int zc = 0; zc < P.n_zchunks; ++zc) {
         const int z0 = zc * KS * kGroup;
         ChunkTables<KS> T;
-        __syncthreads();  // previous chunk's readers of sR are done
-        load_chunk_tables<KS, kIL>(P, z0, d, WK == W_COSCOS, T, sR);
+        load_chunk_tables<KS, kIL>(P, z0, d, WK == W_COSCOS, T, nullptr);
+        if (!(T.rmax >= 0.0f)) continue;
         const bool noclamp = !TF && T.wmax <= whi;
         float S[KS];
 #pragma unroll
@@ -127,51 +168,49 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
             const int iz = slot_depth<kIL>(z0, k, d);
             S[k] = (iz < P.nz) ? depth_factor(P, iz) : 0.0f;
         }
-        __syncthreads();
-        if (T.rmax < 0.0f) continue;
-        for (int col = wave; col < ncol; col += NW) {
-            const float px = P.x[col % P.nx], py = P.y[col / P.nx];
-            const Legs Lp = legs(px, py, srl);
-            const uint64_t live = __builtin_amdgcn_ballot_w64(Lp.hmax <= T.rmax) & segmask;
-            if (!live) continue;
-            // extremes of hmax over each aligned quad of traces (the four groups of a slot)
-            float qmin = fminf(Lp.hmax, __shfl_xor(Lp.hmax, 1, kLanes));
-            qmin = fminf(qmin, __shfl_xor(qmin, 2, kLanes));
-            float qmax = fmaxf(Lp.hmax, __shfl_xor(Lp.hmax, 1, kLanes));
-            qmax = fmaxf(qmax, __shfl_xor(qmax, 2, kLanes));
+        // a float32 leg with |dx| > sqrt(r2) (1 + 2^-22) cannot pass the
+        // float32 aperture test, so this radius keeps every column that can
+        const double rho = sqrt(static_cast<double>(T.rmax)) * (1.0 + 1.0e-6);
+        int ix0, ix1, iy0, iy1;
+        index_range(P.x, P.nx, static_cast<double>(ax) - rho, static_cast<double>(bx) + rho, ix0, ix1);
+        if (ix0 > ix1) continue;
+        index_range(P.y, P.ny, static_cast<double>(ay) - rho, static_cast<double>(by) + rho, iy0, iy1);
+        if (iy0 > iy1) continue;
+        const int nbx = ix1 - ix0 + 1;
+        const int ncb = nbx * (iy1 - iy0 + 1);
+
+        float xv[KS], pxv = 0.0f, pyv = 0.0f;
+        int m = wave;
+        if (m < ncb) fetch_column<KS>(P, img, z0, d, m, nbx, ix0, iy0, xv, pxv, pyv);
+        for (; m < ncb; m += NW) {
             float x[KS];
-            const float* colp = img + static_cast<int64_t>(col) * P.nz;
 #pragma unroll
-            for (int k = 0; k < KS; ++k) {
-                const int iz = slot_depth<kIL>(z0, k, d);
-                x[k] = (iz < P.nz) ? colp[iz] * S[k] : 0.0f;
-            }
-            for (int qt = 0; qt < nquads; ++qt) {
-                if (!((live >> (kGroupsPerWave * qt)) & 0xFull)) continue;
-                const float hmin = uniform_read(qmin, kGroupsPerWave * qt);
-                const float hmaxw = uniform_read(qmax, kGroupsPerWave * qt);
-                uint64_t any, full;
-                slot_masks<KS>(T, hmin, hmaxw, any, full);
+            for (int k = 0; k < KS; ++k) x[k] = xv[k];
+            const float px = pxv, py = pyv;
+            if (m + NW < ncb) fetch_column<KS>(P, img, z0, d, m + NW, nbx, ix0, iy0, xv, pxv, pyv);
+#pragma unroll
+            for (int k = 0; k < KS; ++k) x[k] *= S[k];
+#pragma unroll
+            for (int q = 0; q < NQ; ++q) {
+                if (q >= nq) break;
+                const Legs L = legs(px, py, G[q]);
+                const uint32_t any = fold_or(__builtin_amdgcn_ballot_w64(d < KS && L.hmax <= T.rhi)) & kMask;
                 if (!any) continue;
-                const int src = kGroupsPerWave * qt + g;  // this group's trace (segment-relative)
-                const float hs2 = lane_read(Lp.hs2, src);
-                const float hr2 = lane_read(Lp.hr2, src);
-                const float hm = fmaxf(hs2, hr2);
-                double* row = sAcc + (t0 + min(src, nseg - 1)) * P.lt + rowoff;
+                const uint32_t full = fold_and(__builtin_amdgcn_ballot_w64(d < KS && L.hmax <= T.rlo)) & T.clean;
+                double* row = sAcc + (t0 + min(kGroupsPerWave * q + g, nseg - 1)) * P.lt + rowoff;
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
-                    if ((any >> k) & 3ull) {
-                        if (((full >> k) & 3ull) == 3ull) {
-                            if (noclamp)
-                                dem_two<MERGE, TF, WK, false, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
-                                                               tfo, wlo, whi, nullptr, x[k], x[k + 1]);
-                            else
-                                dem_two<MERGE, TF, WK, false, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
-                                                              tfo, wlo, whi, nullptr, x[k], x[k + 1]);
-                        } else {
-                            dem_two<MERGE, TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo,
-                                                         wlo, whi, sR + k * kGroup + d, x[k], x[k + 1]);
-                        }
+                    if (!((any >> k) & 3u)) continue;
+                    if (((full >> k) & 3u) == 3u) {
+                        if (noclamp)
+                            dem_full<TF, WK, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo,
+                                                    wlo, whi, x[k], x[k + 1]);
+                        else
+                            dem_full<TF, WK, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo,
+                                                   wlo, whi, x[k], x[k + 1]);
+                    } else {
+                        dem_masked<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo, wlo, whi,
+                                           x[k], x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
                     }
                 }
             }
@@ -179,12 +218,11 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     }
 }
 
-template <int NW, int KS, bool MERGE, bool TF, int WK>
+template <int NW, int KS, int NQ, bool TF, int WK>
 __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     extern __shared__ float lds[];
     double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
     float4* sGeo = reinterpret_cast<float4*>(lds + 2 * P.tb * P.lt);   // [tb]
-    float* sR = lds + 2 * P.tb * P.lt + 4 * P.tb;                      // [KS * 16]
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * P.tb;
     const int nb = static_cast<int>(min<int64_t>(P.tb, P.n_traces - j0));
 
@@ -205,7 +243,7 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
         const int b = P.bin[j0 + t0];
         int t1 = t0 + 1;
         while (t1 < nb && P.bin[j0 + t1] == b) ++t1;
-        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, MERGE, TF, WK>(P, b, t0, t1, sGeo, sAcc, sR);
+        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK>(P, b, t0, t1, sGeo, sAcc);
         t0 = t1;
     }
     __syncthreads();
@@ -221,28 +259,29 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     }
 }
 
-template <int NW, int KS, bool MERGE>
+template <int NW, int KS, int NQ>
 static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
+    if (P.tb < 1 || P.tb > kGroupsPerWave * NQ) return hipErrorInvalidValue;
     const int64_t nblk = (P.n_traces + P.tb - 1) / P.tb;
     dim3 grid(static_cast<unsigned>(nblk)), block(NW * 64);
-    const size_t lds = lds_bytes_f64rows(P, KS);
+    const size_t lds = lds_bytes_f64rows(P);
     if (P.has_tf) {
-        if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, MERGE, true, W_COSCOS>, grid, block, lds, s, P);
-        return launch_with_lds(demigrate_kernel<NW, KS, MERGE, true, W_UNIT>, grid, block, lds, s, P);
+        if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_COSCOS>, grid, block, lds, s, P);
+        return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT>, grid, block, lds, s, P);
     }
-    if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, MERGE, false, W_COSCOS>, grid, block, lds, s, P);
-    return launch_with_lds(demigrate_kernel<NW, KS, MERGE, false, W_UNIT>, grid, block, lds, s, P);
+    if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_COSCOS>, grid, block, lds, s, P);
+    return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT>, grid, block, lds, s, P);
 }
 
-// (waves, depth slots, LDS budget for the trace accumulators, merge same-sample atomics)
+// (waves, depth slots, trace quads per workgroup, LDS budget for the trace accumulators)
 #define KM_DEMIGRATE_SHAPES(X) \
-    X(16, 8, 131072, true)     \
-    X(16, 8, 131072, false)    \
-    X(8, 8, 98304, false)      \
-    X(12, 16, 131072, false)
+    X(16, 8, 3, 147456)        \
+    X(16, 8, 2, 98304)         \
+    X(12, 8, 3, 147456)        \
+    X(8, 8, 3, 147456)
 
 static const TileShape kDemigrateShapes[] = {
-#define X(nw, ks, lb, mg) {nw, 1, ks, lb},
+#define X(nw, ks, nq, lb) {nw, 1, ks, lb, nq},
     KM_DEMIGRATE_SHAPES(X)
 #undef X
 };
@@ -252,8 +291,8 @@ const TileShape& demigrate_shape(int i) { return kDemigrateShapes[i]; }
 
 hipError_t launch_demigrate(int shape, const Params& P, hipStream_t s) {
     int i = 0;
-#define X(nw, ks, lb, mg) \
-    if (shape == i) return launch_demigrate_shape<nw, ks, mg>(P, s); \
+#define X(nw, ks, nq, lb) \
+    if (shape == i) return launch_demigrate_shape<nw, ks, nq>(P, s); \
     ++i;
     KM_DEMIGRATE_SHAPES(X)
 #undef X

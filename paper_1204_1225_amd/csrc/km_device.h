@@ -197,16 +197,19 @@ __device__ __forceinline__ int slot_depth(int z0, int k, int d) {
 // slot_depth(z0, k, d) in slot k.  A lane is valid if its depth exists and (for
 // the cos*cos weight) t0sq > 0; elsewhere W = 0 and the image value is 0.
 //   A, B     sample-unit traveltime tables per slot
-//   rlo/rhi  lane k < KS holds min / max over the valid lanes of slot k of the
-//            aperture table (+inf / -inf when the slot has no valid lane)
+//   R        the aperture table per slot (-1 where the lane is invalid)
+//   rlo/rhi  lane d == k < KS of every group holds min / max over the valid
+//            lanes of slot k of the aperture table (+inf / -inf when the slot
+//            has no valid lane)
 //   rmax     max over the chunk (wavefront-uniform)
 //   wmax     an upper bound of sqrt(a_s) + sqrt(a_r) over every pair inside the
 //            aperture in this chunk (wavefront-uniform; +inf when unknown)
 // sR[16 k + d] (LDS) holds the aperture value of each lane, -1 where invalid.
 template <int KS>
 struct ChunkTables {
-    float A[KS], B[KS];
+    float A[KS], B[KS], R[KS];
     float rlo, rhi, rmax, wmax;
+    uint32_t clean;  // bit k: every lane of slot k is valid (wavefront-uniform)
 };
 
 template <int KS, int IL = 1>
@@ -215,6 +218,7 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
     const int lane = threadIdx.x & (kLanes - 1);
     float rmax = -1.0f, wmax = 0.0f;
     float rlo_mine = __builtin_inff(), rhi_mine = -__builtin_inff();
+    uint32_t clean = 0;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int iz = slot_depth<IL>(z0, k, d);
@@ -232,7 +236,9 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         }
         T.A[k] = A;
         T.B[k] = B;
+        T.R[k] = R;
         if (sR && lane < kGroup) sR[k * kGroup + d] = R;
+        if ((__builtin_amdgcn_ballot_w64(valid) & 0xFFFFull) == 0xFFFFull) clean |= 1u << k;
         // in aperture, a = A + B h^2 <= fma(B, R, A) (rounding is monotone);
         // 2 sqrt of it with a relative margin for the approximate square root.
         // A NaN (bad table) propagates and disables the unclamped path.
@@ -247,7 +253,7 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
             lo = fminf(lo, __shfl_xor(lo, off, kLanes));
             hi = fmaxf(hi, __shfl_xor(hi, off, kLanes));
         }
-        if (lane == k) {
+        if (d == k) {
             rlo_mine = lo;
             rhi_mine = hi;
         }
@@ -261,6 +267,7 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
     }
     T.rlo = rlo_mine;
     T.rhi = rhi_mine;
+    T.clean = clean;
     // equal in every lane: make them scalar so that branches on them are uniform
     T.rmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rmax)));
     T.wmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmax)));

@@ -12,6 +12,7 @@ struct TileShape {
     int column_groups;  // groups of 4 columns per wavefront (migrate); unused by demigrate
     int depth_slots;    // KS: 16-depth slots per lane
     int lds_budget;
+    int max_quads;      // demigrate: at most 4 * max_quads traces per workgroup (0: no cap)
 };
 
 // Launch with `lds` bytes of dynamic LDS (raising the kernel's limit first
@@ -34,10 +35,9 @@ inline size_t lds_bytes(const Params& P, int ks) {
            sizeof(float);
 }
 
-// Demigrate workgroups keep their rows as float64.
-inline size_t lds_bytes_f64rows(const Params& P, int ks) {
-    return (static_cast<size_t>(16) * ks + static_cast<size_t>(4) * P.tb + static_cast<size_t>(2) * P.tb * P.lt) *
-           sizeof(float);
+// Demigrate workgroups keep their rows as float64 next to the staged geometry.
+inline size_t lds_bytes_f64rows(const Params& P) {
+    return (static_cast<size_t>(4) * P.tb + static_cast<size_t>(2) * P.tb * P.lt) * sizeof(float);
 }
 
 // migrate (km_migrate.hip)
