@@ -101,18 +101,83 @@ __device__ __forceinline__ void dem_masked(float A0, float B0, float A1, float B
     }
 }
 
-// Coordinates and image values (depth slots of this lane) of box column m.
-template <int KS>
-__device__ __forceinline__ void fetch_column(const Params& P, const float* img, int z0, int d, int m, int nbx, int ix0,
-                                             int iy0, float* xv, float& px, float& py) {
-    const int ix = ix0 + m % nbx, iy = iy0 + m / nbx;
-    px = P.x[ix];
-    py = P.y[iy];
+// Coordinates and image values (depth slots of this lane) of column (ix, iy).
+// Lanes past the last depth (only in the last chunk, TAIL) read the last
+// depth instead; they are never inside the aperture, so the value is unused.
+template <int KS, bool TAIL>
+__device__ __forceinline__ void fetch_column(const Params& P, const float* img, int z0, int d, int ix, int iy,
+                                             float* xv, float& px, float& py) {
+    // Vector (not scalar) loads for the coordinates: a scalar load's wait also
+    // waits for every LDS atomic the wavefront has queued, which would drain
+    // the atomics once per column.
+    int ixv = ix, iyv = iy;
+    asm volatile("" : "+v"(ixv), "+v"(iyv));
+    px = P.x[ixv];
+    py = P.y[iyv];
     const float* colp = img + (static_cast<int64_t>(iy) * P.nx + ix) * P.nz;
 #pragma unroll
     for (int k = 0; k < KS; ++k) {
         const int iz = slot_depth<kIL>(z0, k, d);
-        xv[k] = iz < P.nz ? colp[iz] : 0.0f;
+        xv[k] = colp[TAIL ? min(iz, P.nz - 1) : iz];
+    }
+}
+
+// One depth chunk of the segment: wavefront `wave` takes the box columns
+// wave, wave + NW, ... in row-major order and scatters every pairing of a
+// column with the segment's traces into their rows.
+template <int NW, int KS, int NQ, bool TF, int WK, bool CLAMP, bool TAIL>
+__device__ __forceinline__ void sweep_columns(const Params& P, const float* img, int z0, int d, int g, int wave, int t0,
+                                              int nseg, int nq, int ix0, int ix1, int iy0, int iy1,
+                                              const ChunkTables<KS>& T, const float* S, const float4* G, double* sAcc) {
+    constexpr uint32_t kMask = (KS >= 32) ? ~0u : ((1u << KS) - 1u);
+    float wlo, whi;
+    clamp_bounds<TF>(P.lt, wlo, whi);
+    const float tfo = P.tf_off;
+    const int rowoff = TF ? 0 : kLead;
+    double* rows[NQ];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) rows[q] = sAcc + (t0 + min(kGroupsPerWave * q + g, nseg - 1)) * P.lt + rowoff;
+    const int nbx = ix1 - ix0 + 1;
+    int ix = ix0 + wave, iy = iy0;
+    while (ix > ix1) {
+        ix -= nbx;
+        ++iy;
+    }
+    float xv[KS], pxv = 0.0f, pyv = 0.0f;
+    if (iy <= iy1) fetch_column<KS, TAIL>(P, img, z0, d, ix, iy, xv, pxv, pyv);
+    while (iy <= iy1) {
+        float x[KS];
+#pragma unroll
+        for (int k = 0; k < KS; ++k) x[k] = xv[k];
+        const float px = pxv, py = pyv;
+        ix += NW;
+        while (ix > ix1) {
+            ix -= nbx;
+            ++iy;
+        }
+        if (iy <= iy1) fetch_column<KS, TAIL>(P, img, z0, d, ix, iy, xv, pxv, pyv);
+#pragma unroll
+        for (int k = 0; k < KS; ++k) x[k] *= S[k];
+#pragma unroll
+        for (int q = 0; q < NQ; ++q) {
+            if (q >= nq) break;
+            const Legs L = legs(px, py, G[q]);
+            // lanes d >= KS hold rhi = -inf and rlo = +inf; kMask drops their bits
+            const uint32_t any = fold_or(__builtin_amdgcn_ballot_w64(L.hmax <= T.rhi)) & kMask;
+            if (!any) continue;
+            const uint32_t full = fold_and(__builtin_amdgcn_ballot_w64(L.hmax <= T.rlo)) & T.clean;
+            double* row = rows[q];
+#pragma unroll
+            for (int k = 0; k < KS; k += 2) {
+                if (!((any >> k) & 3u)) continue;
+                if (((full >> k) & 3u) == 3u)
+                    dem_full<TF, WK, CLAMP>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo, wlo, whi,
+                                            x[k], x[k + 1]);
+                else
+                    dem_masked<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo, wlo, whi,
+                                       x[k], x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
+            }
+        }
     }
 }
 
@@ -121,16 +186,13 @@ template <int NW, int KS, int NQ, bool TF, int WK>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
                                                   double* sAcc) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
-    constexpr uint32_t kMask = (KS >= 32) ? ~0u : ((1u << KS) - 1u);
     const int lane = threadIdx.x & (kLanes - 1);
-    const int wave = threadIdx.x / kLanes;
+    const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
     const int g = lane / kGroup, d = lane % kGroup;
     const int nseg = t1 - t0;
     const int nq = (nseg + kGroupsPerWave - 1) / kGroupsPerWave;
     float wlo, whi;
     clamp_bounds<TF>(P.lt, wlo, whi);
-    const float tfo = P.tf_off;
-    const int rowoff = TF ? 0 : kLead;
     const float* img = P.image + static_cast<int64_t>(b) * P.nx * P.ny * P.nz;
 
     // group g of quad q works on trace 4 q + g of the segment (far away past its end)
@@ -176,45 +238,18 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
         if (ix0 > ix1) continue;
         index_range(P.y, P.ny, static_cast<double>(ay) - rho, static_cast<double>(by) + rho, iy0, iy1);
         if (iy0 > iy1) continue;
-        const int nbx = ix1 - ix0 + 1;
-        const int ncb = nbx * (iy1 - iy0 + 1);
-
-        float xv[KS], pxv = 0.0f, pyv = 0.0f;
-        int m = wave;
-        if (m < ncb) fetch_column<KS>(P, img, z0, d, m, nbx, ix0, iy0, xv, pxv, pyv);
-        for (; m < ncb; m += NW) {
-            float x[KS];
-#pragma unroll
-            for (int k = 0; k < KS; ++k) x[k] = xv[k];
-            const float px = pxv, py = pyv;
-            if (m + NW < ncb) fetch_column<KS>(P, img, z0, d, m + NW, nbx, ix0, iy0, xv, pxv, pyv);
-#pragma unroll
-            for (int k = 0; k < KS; ++k) x[k] *= S[k];
-#pragma unroll
-            for (int q = 0; q < NQ; ++q) {
-                if (q >= nq) break;
-                const Legs L = legs(px, py, G[q]);
-                const uint32_t any = fold_or(__builtin_amdgcn_ballot_w64(d < KS && L.hmax <= T.rhi)) & kMask;
-                if (!any) continue;
-                const uint32_t full = fold_and(__builtin_amdgcn_ballot_w64(d < KS && L.hmax <= T.rlo)) & T.clean;
-                double* row = sAcc + (t0 + min(kGroupsPerWave * q + g, nseg - 1)) * P.lt + rowoff;
-#pragma unroll
-                for (int k = 0; k < KS; k += 2) {
-                    if (!((any >> k) & 3u)) continue;
-                    if (((full >> k) & 3u) == 3u) {
-                        if (noclamp)
-                            dem_full<TF, WK, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo,
-                                                    wlo, whi, x[k], x[k + 1]);
-                        else
-                            dem_full<TF, WK, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo,
-                                                   wlo, whi, x[k], x[k + 1]);
-                    } else {
-                        dem_masked<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo, wlo, whi,
-                                           x[k], x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
-                    }
-                }
-            }
+        const bool tail = z0 + KS * kGroup > P.nz;
+#define KM_SWEEP(CLAMP, TAIL)                                                                                 \
+    sweep_columns<NW, KS, NQ, TF, WK, CLAMP, TAIL>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S, \
+                                                   G, sAcc)
+        if (noclamp) {
+            if (tail) KM_SWEEP(false, true);
+            else KM_SWEEP(false, false);
+        } else {
+            if (tail) KM_SWEEP(true, true);
+            else KM_SWEEP(true, false);
         }
+#undef KM_SWEEP
     }
 }
 
