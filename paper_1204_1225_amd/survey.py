@@ -396,6 +396,47 @@ def make_line2d_vz(seed=4, n_shots=256, n_rec=240, n_t=2000, nx=1024, nz=800, n_
                    ("linear", 1500.0, 0.5), 60.0)
 
 
+def bin_offsets(problem: Problem) -> np.ndarray:
+    """Mean absolute offset |x_s - x_r| of the traces of each bin (FP64; the
+    bin's lower edge midpoint when it holds no trace)."""
+    h = np.hypot(problem.src[:, 0].astype(np.float64) - problem.rec[:, 0],
+                 problem.src[:, 1].astype(np.float64) - problem.rec[:, 1])
+    out = np.zeros(problem.n_bins)
+    width = problem.offset_bin_width or 1.0
+    for b in range(problem.n_bins):
+        sel = problem.bin == b
+        out[b] = h[sel].mean() if sel.any() else (b + 0.5) * width
+    return out
+
+
+def make_flat_line(v_true=2000.0, v_mig=2000.0, z_reflector=800.0, n_t=400, nz=240, nx=5, n_bins=10,
+                   bin_width=100.0, f_peak=25.0):
+    """2D line over one flat reflector in a constant-velocity earth, for the
+    moveout measure of the offset images.
+
+    Shots every 50 m over 0 .. 4000 m, split-spread receivers every 50 m with
+    offsets -1000 .. 1000 m; 400 samples at 4 ms.  Each trace holds the
+    reflection of the flat interface at z_reflector computed with v_true: a
+    25 Hz Ricker at t = 2 sqrt(z^2 + (h/2)^2) / v_true, unit amplitude.  The
+    traveltime tables are those of v_mig (so v_mig != v_true is a velocity
+    error).  Image: nx columns at 50 m around x = 2000 m, z = 5 (k + 1) m,
+    n_bins bins of |h| of bin_width m, aperture 60 degrees."""
+    s = 50.0 * np.arange(81)
+    h = 50.0 * (np.arange(41) - 20)
+    S, H = np.meshgrid(s, h, indexing="ij")
+    src = np.stack([S.ravel(), np.zeros(S.size)], 1)
+    rec = np.stack([(S + H).ravel(), np.zeros(S.size)], 1)
+    x = 2000.0 + 50.0 * (np.arange(nx) - (nx - 1) / 2.0)
+    z = 5.0 * (np.arange(nz) + 1)
+    p = _finish("flat_line", src, rec, n_t, 0.004, 0.0, x, [0.0], z, n_bins, bin_width, ("const", v_mig), 60.0)
+    hh = np.abs(p.src[:, 0].astype(np.float64) - p.rec[:, 0])
+    t_ref = 2.0 * np.sqrt(z_reflector ** 2 + 0.25 * hh * hh) / v_true
+    t = np.arange(n_t) * p.dt
+    p.data = ricker(t[None, :] - t_ref[:, None], f_peak).astype(np.float32)
+    p.meta = dict(v_true=v_true, v_mig=v_mig, z_reflector=z_reflector)
+    return p
+
+
 def batch_line_shapes(seed=5, n_lines=64):
     """Shapes of the uneven batch: (n_shots, n_rec, n_t, nx, nz) per line,
     drawn inclusive from U{16..512}, U{48..480}, U{1000..3000}, U{256..2048},
