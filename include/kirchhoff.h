@@ -154,6 +154,42 @@ km_status km_dot_f64(const float* a, const float* b, int64_t n, double* out, voi
  * once).  x may equal y. */
 km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t n, void* stream);
 
+/* ---- offset stack and moveout of the offset images --------------------------
+ * The migration gives one image per offset bin: redundant images of the same
+ * subsurface.  The depth at which a reflector appears in the different offset
+ * images measures the error of the velocity model; once they agree they are
+ * added into one stacked image (Introduction). */
+
+/* stack[p] = sum over b = 0..n_bins-1 of image[b * n_points + p] (float32
+ * sums in bin order), p < n_points.  image: device float[n_bins][n_points];
+ * stack: device float[n_points], overwritten, must not overlap image.
+ * KM_E_INVALID for n_bins < 1, n_points < 0, NULL or misaligned pointers. */
+km_status km_stack_offsets(const float* image, int32_t n_bins, int64_t n_points, float* stack, void* stream);
+
+/* Moveout of every common-image gather (the n_bins depth vectors of one image
+ * column) against its stack S = sum_b I_b (formed in float64):
+ *   C_b(l) = sum_{z_lo <= z < z_hi} S[z] I_b[z + l],  l = -max_lag..max_lag,
+ * with I_b = 0 outside [0, nz), in float64.  The best lag l* maximises C_b
+ * (ties to the smaller |l|, then to the negative l); when |l*| < max_lag and
+ * the parabola through C_b(l* - 1), C_b(l*), C_b(l* + 1) opens downwards its
+ * vertex refines it:
+ *   shift = l* + (C(l*-1) - C(l*+1)) / (2 (C(l*-1) - 2 C(l*) + C(l*+1))),
+ * else shift = l*.  shift > 0: the bin images the event deeper than the stack
+ * (depth samples).  peak = C_b(l*).  curvature = least-squares slope of the
+ * shifts against offsets[b]^2 over the bins with peak > 0 (0 when fewer than
+ * two such bins or equal offsets), in depth samples per (offset unit)^2.
+ * image: device float[n_bins][ny][nx][nz] (grid->n_bins etc.; grid->x, y are
+ * not read).  offsets: device float[n_bins] (bin-centre offsets; read only when
+ * curvature is non-NULL).  Outputs (device, overwritten; NULL to skip except
+ * shift): stack float[ny][nx][nz], shift float[n_bins][ny][nx], peak
+ * float[n_bins][ny][nx], curvature float[ny][nx].
+ * KM_E_INVALID: max_lag < 0, window outside [0, nz] or empty, NULL image or
+ * shift, misaligned pointers.  KM_E_UNSUPPORTED: max_lag > 256 or one column's
+ * rows do not fit in the 160 KiB of LDS of a workgroup. */
+km_status km_cig_moveout(const float* image, const km_grid* grid, const float* offsets, int32_t max_lag,
+                         int32_t z_lo, int32_t z_hi, float* stack, float* shift, float* peak, float* curvature,
+                         void* stream);
+
 /* ---- tile shapes and tuning ------------------------------------------------
  * op: 0 = migrate, 1 = demigrate. */
 typedef struct km_tile_info {

@@ -299,6 +299,45 @@ km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t 
     return e == hipSuccess ? KM_OK : hip_fail(e, "axpby launch");
 }
 
+km_status km_stack_offsets(const float* image, int32_t n_bins, int64_t n_points, float* stack, void* stream) {
+    if (n_bins < 1) return fail(KM_E_INVALID, "km_stack_offsets: n_bins < 1");
+    if (n_points < 0) return fail(KM_E_INVALID, "km_stack_offsets: n_points < 0");
+    if (n_points == 0) return KM_OK;
+    if (!image || !stack || !aligned(image, 4) || !aligned(stack, 4))
+        return fail(KM_E_INVALID, "km_stack_offsets: image, stack NULL/misaligned");
+    const hipError_t e = km::launch_stack(image, n_bins, n_points, stack, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "stack launch");
+}
+
+km_status km_cig_moveout(const float* image, const km_grid* grid, const float* offsets, int32_t max_lag,
+                         int32_t z_lo, int32_t z_hi, float* stack, float* shift, float* peak, float* curvature,
+                         void* stream) {
+    if (!grid) return fail(KM_E_INVALID, "km_cig_moveout: grid is NULL");
+    if (grid->nx < 0 || grid->ny < 0 || grid->nz < 0 || grid->n_bins < 0)
+        return fail(KM_E_INVALID, "km_cig_moveout: negative grid size");
+    if (static_cast<int64_t>(grid->nx) * grid->ny >= (int64_t(1) << 31))
+        return fail(KM_E_UNSUPPORTED, "km_cig_moveout: nx * ny must be < 2^31");
+    if (max_lag < 0) return fail(KM_E_INVALID, "km_cig_moveout: max_lag < 0");
+    if (max_lag > 256) return fail(KM_E_UNSUPPORTED, "km_cig_moveout: max_lag > 256");
+    if (z_lo < 0 || z_hi > grid->nz || z_lo >= z_hi)
+        return fail(KM_E_INVALID, "km_cig_moveout: depth window [%d, %d) not inside [0, %d) or empty", z_lo, z_hi,
+                    grid->nz);
+    if (grid->n_bins < 1) return fail(KM_E_INVALID, "km_cig_moveout: n_bins < 1");
+    if (!image || !shift) return fail(KM_E_INVALID, "km_cig_moveout: image and shift must be non-NULL");
+    if (!aligned(image, 4) || !aligned(shift, 4) || (stack && !aligned(stack, 4)) || (peak && !aligned(peak, 4)) ||
+        (curvature && !aligned(curvature, 4)))
+        return fail(KM_E_INVALID, "km_cig_moveout: misaligned pointer");
+    if (curvature && (!offsets || !aligned(offsets, 4)))
+        return fail(KM_E_INVALID, "km_cig_moveout: offsets NULL/misaligned with curvature requested");
+    if (km::cig_lds_bytes(grid->n_bins, grid->nz, max_lag) > static_cast<size_t>(kMaxLds))
+        return fail(KM_E_UNSUPPORTED, "km_cig_moveout: %d bins x %d depths do not fit in LDS", grid->n_bins,
+                    grid->nz);
+    if (grid->nx == 0 || grid->ny == 0) return KM_OK;
+    const hipError_t e = km::launch_cig(image, grid->n_bins, grid->ny, grid->nx, grid->nz, max_lag, z_lo, z_hi,
+                                        offsets, stack, shift, peak, curvature, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "moveout launch");
+}
+
 int32_t km_tile_count(int32_t op) { return (op == 0 || op == 1) ? shape_count(op) : 0; }
 
 km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out) {

@@ -54,6 +54,13 @@ int demigrate_shape_count();
 const TileShape& demigrate_shape(int i);
 hipError_t launch_demigrate(int shape, const Params& P, hipStream_t s);
 
+// offset stack and moveout (km_cig.hip)
+size_t cig_lds_bytes(int n_bins, int nz, int max_lag);
+hipError_t launch_stack(const float* img, int n_bins, int64_t n_points, float* out, hipStream_t s);
+hipError_t launch_cig(const float* img, int n_bins, int ny, int nx, int nz, int max_lag, int z_lo, int z_hi,
+                      const float* offsets, float* stack, float* shift, float* peak, float* curvature,
+                      hipStream_t s);
+
 // counting, reductions, probes (km_misc.hip)
 hipError_t launch_count(const Params& P, unsigned long long* counts, hipStream_t s);
 hipError_t launch_dot_f64(const float* a, const float* b, int64_t n, double* out, hipStream_t s);

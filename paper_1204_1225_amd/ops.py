@@ -195,6 +195,41 @@ def axpby(alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor) -> torch.
     return y
 
 
+def stack_offsets(image: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Sum of the offset images image[n_bins, ...] over the bins (float32)."""
+    assert image.dtype == torch.float32 and image.is_contiguous() and image.dim() >= 1
+    if out is None:
+        out = torch.empty(image.shape[1:], dtype=torch.float32, device=image.device)
+    assert out.is_contiguous() and out.numel() * image.shape[0] == image.numel()
+    check(_lib.load().km_stack_offsets(_ptr(image), image.shape[0], out.numel(), _ptr(out),
+                                       ctypes.c_void_p(_stream(image.device))))
+    return out
+
+
+def cig_moveout(image: torch.Tensor, offsets: Optional[torch.Tensor] = None, max_lag: int = 12, z_lo: int = 0,
+                z_hi: Optional[int] = None, want_stack: bool = True, want_peak: bool = True):
+    """Moveout of the common-image gathers of image[n_bins, ny, nx, nz] against
+    their stack: returns (stack, shift, peak, curvature); stack / peak are
+    None when not wanted, curvature is None without offsets (float32 [n_bins]
+    bin-centre offsets on the image's device)."""
+    assert image.dtype == torch.float32 and image.is_contiguous() and image.dim() == 4
+    nb, ny, nx, nz = image.shape
+    dev = image.device
+    z_hi = nz if z_hi is None else z_hi
+    stack = torch.empty((ny, nx, nz), dtype=torch.float32, device=dev) if want_stack else None
+    shift = torch.empty((nb, ny, nx), dtype=torch.float32, device=dev)
+    peak = torch.empty((nb, ny, nx), dtype=torch.float32, device=dev) if want_peak else None
+    curv = None
+    if offsets is not None:
+        assert offsets.dtype == torch.float32 and offsets.numel() == nb and offsets.device == dev
+        offsets = offsets.contiguous()
+        curv = torch.empty((ny, nx), dtype=torch.float32, device=dev)
+    g = KmGrid(nx=nx, ny=ny, nz=nz, n_bins=nb, x=None, y=None)
+    check(_lib.load().km_cig_moveout(_ptr(image), ctypes.byref(g), _ptr(offsets), max_lag, z_lo, z_hi, _ptr(stack),
+                                     _ptr(shift), _ptr(peak), _ptr(curv), ctypes.c_void_p(_stream(dev))))
+    return stack, shift, peak, curv
+
+
 def tile_count(op: int) -> int:
     return int(_lib.load().km_tile_count(op))
 

@@ -137,3 +137,33 @@ def test_tune_cache_roundtrip(lib):
     assert lib.km_tune_lookup(0, 0, 4000, 7000) == 1
     assert lib.km_tune_lookup(0, 0, 4010, 7100) == 1  # same shape class
     assert lib.km_tune_record(0, 0, 4000, 7000, 99) == _lib.KM_E_INVALID
+
+
+def test_stack_and_moveout_reject_bad_arguments(lib):
+    from paper_1204_1225_amd import _lib
+
+    p = ctypes.c_void_p(0x1000)
+    assert lib.km_stack_offsets(p, 0, 10, p, None) == _lib.KM_E_INVALID
+    assert lib.km_stack_offsets(p, 2, -1, p, None) == _lib.KM_E_INVALID
+    assert lib.km_stack_offsets(None, 2, 10, p, None) == _lib.KM_E_INVALID
+    assert lib.km_stack_offsets(ctypes.c_void_p(0x1002), 2, 10, p, None) == _lib.KM_E_INVALID
+    assert lib.km_stack_offsets(None, 2, 0, None, None) == _lib.KM_OK  # nothing to do
+    g = _lib.KmGrid(nx=4, ny=2, nz=50, n_bins=3, x=None, y=None)
+    gp = ctypes.byref(g)
+    cases = [
+        ((p, gp, p, -1, 0, 50, None, p, None, None), _lib.KM_E_INVALID, b"max_lag"),
+        ((p, gp, p, 300, 0, 50, None, p, None, None), _lib.KM_E_UNSUPPORTED, b"max_lag"),
+        ((p, gp, p, 4, 10, 10, None, p, None, None), _lib.KM_E_INVALID, b"window"),
+        ((p, gp, p, 4, 0, 51, None, p, None, None), _lib.KM_E_INVALID, b"window"),
+        ((None, gp, p, 4, 0, 50, None, p, None, None), _lib.KM_E_INVALID, b"non-NULL"),
+        ((p, gp, p, 4, 0, 50, None, None, None, None), _lib.KM_E_INVALID, b"non-NULL"),
+        ((p, gp, None, 4, 0, 50, None, p, None, p), _lib.KM_E_INVALID, b"offsets"),
+        ((p, gp, p, 4, 0, 50, ctypes.c_void_p(0x1001), p, None, None), _lib.KM_E_INVALID, b"misaligned"),
+    ]
+    for args, status, msg in cases:
+        assert lib.km_cig_moveout(*args, None) == status, args
+        assert msg in lib.km_last_error()
+    big = _lib.KmGrid(nx=4, ny=2, nz=20000, n_bins=16, x=None, y=None)
+    assert lib.km_cig_moveout(p, ctypes.byref(big), p, 4, 0, 100, None, p, None, None, None) == \
+        _lib.KM_E_UNSUPPORTED
+    assert b"LDS" in lib.km_last_error()
