@@ -48,29 +48,81 @@ __global__ __launch_bounds__(256) void stack_kernel(const float* __restrict__ im
     }
 }
 
-// LDS layout of one column: stack [nz] double, correlations [n_bins][2 L + 1]
-// double, shifts and peaks [n_bins] double each, rows [n_bins][nz + 2 L] float.
+// LDS of one workgroup (one column): stack [nz] double, correlations
+// [n_bins][2 L + 1] double, depth-part partial sums [zs][n_bins][2 L + 1]
+// double, shifts and peaks [n_bins] double each, rows [n_bins][rl] float
+// with rl = nz + 2 L + 2 kLagBlock (even), zero outside the column.
+constexpr int kLagBlock = 5;  // lags per thread in the correlation phase
+
+__host__ __device__ inline int cig_row_len(int nz, int L) { return (nz + 2 * L + 2 * kLagBlock + 1) & ~1; }
+
+__host__ __device__ inline int cig_lag_blocks(int L) { return (2 * L + 1 + kLagBlock - 1) / kLagBlock; }
+
+// depth parts per (bin, lag block) so that the items fill the workgroup
+__host__ __device__ inline int cig_depth_parts(int n_bins, int L) {
+    const int items = n_bins * cig_lag_blocks(L);
+    return items >= kCigThreads ? 1 : kCigThreads / items;
+}
+
+__host__ __device__ inline size_t cig_doubles(int n_bins, int nz, int L) {
+    const size_t nl = 2 * static_cast<size_t>(L) + 1;
+    return static_cast<size_t>(nz) + static_cast<size_t>(n_bins) * nl * (1 + cig_depth_parts(n_bins, L)) +
+           2 * static_cast<size_t>(n_bins) + static_cast<size_t>(n_bins) * cig_row_len(nz, L) / 2;
+}
+
+// Partial C_b(l) over depths [za, zb) for l = lag0 .. lag0 + kLagBlock - 1:
+// a rotating window of the row in registers (slot (u + j) % kLagBlock holds
+// row[z + u + lag0 + j]), so each depth step costs one row read, one stack
+// read and kLagBlock FMAs.  Steps past zb use a zero stack value.
+__device__ __forceinline__ void lag_block(const double* sS, const float* row, int lag0, int za, int zb, double* c) {
+    constexpr int LB = kLagBlock;
+    double w[LB];
+#pragma unroll
+    for (int j = 0; j < LB; ++j) c[j] = 0.0;
+    if (za >= zb) return;
+#pragma unroll
+    for (int m = 0; m < LB - 1; ++m) w[m] = static_cast<double>(row[za + lag0 + m]);
+    for (int z = za; z < zb; z += LB) {
+#pragma unroll
+        for (int u = 0; u < LB; ++u) {
+            w[(u + LB - 1) % LB] = static_cast<double>(row[z + u + lag0 + LB - 1]);
+            const double sv = (z + u < zb) ? sS[z + u] : 0.0;
+#pragma unroll
+            for (int j = 0; j < LB; ++j) c[j] = fma(sv, w[(u + j) % LB], c[j]);
+        }
+    }
+}
+
 __global__ __launch_bounds__(kCigThreads) void cig_kernel(const float* __restrict__ img, int n_bins, int ny, int nx,
                                                          int nz, int L, int z_lo, int z_hi,
                                                          const float* __restrict__ offsets, float* stack,
                                                          float* shift, float* peak, float* curvature) {
     extern __shared__ double cig_lds[];
     const int nl = 2 * L + 1;
-    const int rl = nz + 2 * L;  // padded row length
-    double* sS = cig_lds;                                  // [nz]
-    double* sC = sS + nz;                                  // [n_bins][nl]
-    double* sShift = sC + static_cast<int64_t>(n_bins) * nl;  // [n_bins]
-    double* sPeak = sShift + n_bins;                          // [n_bins]
-    float* sRow = reinterpret_cast<float*>(sPeak + n_bins);   // [n_bins][rl]
+    const int rl = cig_row_len(nz, L);
+    const int nblk = cig_lag_blocks(L);
+    const int zs = cig_depth_parts(n_bins, L);
+    const int items = n_bins * nblk * zs;
+    const int zlen = (z_hi - z_lo + zs - 1) / zs;
+    double* sS = cig_lds;                                           // [nz]
+    double* sC = sS + nz;                                           // [n_bins][nl]
+    double* sP = sC + n_bins * nl;                                  // [zs][n_bins][nl]
+    double* sShift = sP + static_cast<int64_t>(zs) * n_bins * nl;   // [n_bins]
+    double* sPeak = sShift + n_bins;                                // [n_bins]
+    float* sRow = reinterpret_cast<float*>(sPeak + n_bins);         // [n_bins][rl]
     const int64_t ncol = static_cast<int64_t>(ny) * nx;
     const int64_t bin_stride = ncol * nz;
     const int tid = threadIdx.x;
 
     for (int64_t col = blockIdx.x; col < ncol; col += gridDim.x) {
         __syncthreads();  // the previous column's readers are done
-        for (int e = tid; e < n_bins * rl; e += kCigThreads) {
-            const int b = e / rl, k = e % rl - L;
-            sRow[e] = (k >= 0 && k < nz) ? img[b * bin_stride + col * nz + k] : 0.0f;
+        const float* src = img + col * nz;
+        for (int b = 0; b < n_bins; ++b) {
+            float* dst = sRow + b * rl;
+            for (int r = tid; r < rl; r += kCigThreads) {
+                const int k = r - L;
+                dst[r] = (k >= 0 && k < nz) ? src[b * bin_stride + k] : 0.0f;
+            }
         }
         __syncthreads();
         for (int z = tid; z < nz; z += kCigThreads) {
@@ -80,11 +132,22 @@ __global__ __launch_bounds__(kCigThreads) void cig_kernel(const float* __restric
             if (stack) stack[col * nz + z] = static_cast<float>(s);
         }
         __syncthreads();
+        for (int it = tid; it < items; it += kCigThreads) {
+            const int part = it % zs, rest = it / zs;
+            const int b = rest / nblk, blk = rest % nblk;
+            const int lag0 = -L + blk * kLagBlock;
+            const int za = z_lo + part * zlen, zb = min(z_hi, za + zlen);
+            double cc[kLagBlock];
+            lag_block(sS, sRow + b * rl + L, lag0, za, zb, cc);
+            double* out = sP + (static_cast<int64_t>(part) * n_bins + b) * nl + lag0 + L;
+#pragma unroll
+            for (int j = 0; j < kLagBlock; ++j)
+                if (lag0 + j <= L) out[j] = cc[j];
+        }
+        __syncthreads();
         for (int w = tid; w < n_bins * nl; w += kCigThreads) {
-            const int b = w / nl, lag = w % nl - L;
-            const float* row = sRow + b * rl + L + lag;
             double c = 0.0;
-            for (int z = z_lo; z < z_hi; ++z) c = fma(sS[z], static_cast<double>(row[z]), c);
+            for (int part = 0; part < zs; ++part) c += sP[static_cast<int64_t>(part) * n_bins * nl + w];
             sC[w] = c;
         }
         __syncthreads();
@@ -95,15 +158,15 @@ __global__ __launch_bounds__(kCigThreads) void cig_kernel(const float* __restric
                 if (c[-m] > c[best]) best = -m;
                 if (c[m] > c[best]) best = m;
             }
-            double s = best;
+            double sh = best;
             if (best > -L && best < L) {
                 const double cm = c[best - 1], c0 = c[best], cp = c[best + 1];
                 const double den = cm - 2.0 * c0 + cp;
-                if (den < 0.0) s = best + 0.5 * (cm - cp) / den;
+                if (den < 0.0) sh = best + 0.5 * (cm - cp) / den;
             }
-            sShift[b] = s;
+            sShift[b] = sh;
             sPeak[b] = c[best];
-            shift[b * ncol + col] = static_cast<float>(s);
+            shift[b * ncol + col] = static_cast<float>(sh);
             if (peak) peak[b * ncol + col] = static_cast<float>(c[best]);
         }
         __syncthreads();
@@ -138,11 +201,7 @@ __global__ __launch_bounds__(kCigThreads) void cig_kernel(const float* __restric
     }
 }
 
-size_t cig_lds_bytes(int n_bins, int nz, int max_lag) {
-    const size_t nl = 2 * static_cast<size_t>(max_lag) + 1;
-    return sizeof(double) * (static_cast<size_t>(nz) + n_bins * nl + 2 * static_cast<size_t>(n_bins)) +
-           sizeof(float) * static_cast<size_t>(n_bins) * (nz + 2 * static_cast<size_t>(max_lag));
-}
+size_t cig_lds_bytes(int n_bins, int nz, int max_lag) { return sizeof(double) * cig_doubles(n_bins, nz, max_lag); }
 
 hipError_t launch_stack(const float* img, int n_bins, int64_t n_points, float* out, hipStream_t s) {
     const int vec = (n_points % 4 == 0) && (reinterpret_cast<uintptr_t>(img) % 16 == 0) &&
@@ -159,9 +218,9 @@ hipError_t launch_cig(const float* img, int n_bins, int ny, int nx, int nz, int 
                       hipStream_t s) {
     const int64_t ncol = static_cast<int64_t>(ny) * nx;
     const int64_t blocks = std::min<int64_t>(ncol, 1 << 20);
-    const size_t lds = cig_lds_bytes(n_bins, nz, max_lag);
-    return launch_with_lds(cig_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kCigThreads), lds, s, img, n_bins,
-                           ny, nx, nz, max_lag, z_lo, z_hi, offsets, stack, shift, peak, curvature);
+    return launch_with_lds(cig_kernel, dim3(static_cast<unsigned>(blocks)), dim3(kCigThreads),
+                           cig_lds_bytes(n_bins, nz, max_lag), s, img, n_bins, ny, nx, nz, max_lag, z_lo, z_hi,
+                           offsets, stack, shift, peak, curvature);
 }
 
 }  // namespace km

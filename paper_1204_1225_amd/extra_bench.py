@@ -8,6 +8,9 @@ line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
 batch: 64 uneven 2D lines migrated by one persistent hipGraph-captured launch
     against 64 separate launches (same tile shape, chosen by the tuner on the
     largest line), images compared bit for bit.
+cig: the offset stack and the common-image-gather moveout of the migrated 3D
+    survey image (16 x 256 x 256 x 400): HBM bandwidth of both kernels against
+    8 TB/s, and the FP64 oracle timed on a sample of image columns.
 """
 from __future__ import annotations
 
@@ -101,7 +104,64 @@ def _batch(steps, warmup, dev):
             "trace_bytes": int(sum(dp.data.numel() * 4 for dp in dps))}
 
 
+HBM_PEAK = 8.0e12  # bytes/s
+
+
+def _cig(steps, warmup, dev, max_lag=12):
+    import os
+
+    from oracle import cig as ocig
+
+    p = survey.make_survey3d(seed=2, device=dev)
+    dp = ops.to_device(p, dev)
+    img = ops.migrate(dp)
+    hb_np = survey.bin_offsets(p).astype(np.float32)
+    hb = torch.from_numpy(hb_np).to(dev)
+    nb, ny, nx, nz = img.shape
+    stack = torch.empty((ny, nx, nz), device=dev)
+    ms_stack = _time(lambda: ops.stack_offsets(img, out=stack), steps, warmup)
+    res = {}
+
+    def moveout():
+        res["out"] = ops.cig_moveout(img, hb, max_lag=max_lag)
+
+    ms_cig = _time(moveout, steps, warmup)
+    n_pts = ny * nx * nz
+    bytes_stack = (nb + 1) * n_pts * 4
+    bytes_cig = (nb + 1) * n_pts * 4 + 2 * nb * ny * nx * 4 + ny * nx * 4
+    fma = ny * nx * nb * (2 * max_lag + 1) * nz
+    # oracle on a sample of columns, and the GPU values there
+    rng = np.random.default_rng(0)
+    n_s = 512
+    iy, ix = rng.integers(0, ny, n_s), rng.integers(0, nx, n_s)
+    sub = img[:, iy, ix, :].cpu().numpy()[:, :, None, :]
+    t0 = time.perf_counter()
+    o_stack, o_shift, _, _ = ocig.cig_moveout(sub, hb_np.astype(np.float64), max_lag)
+    t_cpu = time.perf_counter() - t0
+    g_shift = res["out"][1][:, iy, ix].cpu().numpy()
+    C = ocig.correlations(sub, max_lag)
+    Cs = np.sort(C, axis=-1)
+    clear = ((Cs[..., -1] - Cs[..., -2]) > 1e-9 * (np.abs(C).max(axis=-1) + 1e-300))[:, :, 0]
+    err = float(np.abs(g_shift - o_shift[:, :, 0])[clear].max())
+    return {"workload": "cig", "metric": "HBM GB/s (offset stack; CIG moveout)", "image": [nb, ny, nx, nz],
+            "max_lag": max_lag, "ms_stack": round(ms_stack, 4), "ms_moveout": round(ms_cig, 4),
+            "roofline_stack": {"bound": "hbm", "achieved": round(bytes_stack / ms_stack / 1e6, 1),
+                               "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                               "frac": round(bytes_stack / ms_stack * 1e3 / HBM_PEAK, 4)},
+            "roofline_moveout": {"bound": "hbm", "achieved": round(bytes_cig / ms_cig / 1e6, 1),
+                                 "peak": HBM_PEAK / 1e9, "unit": "GB/s",
+                                 "frac": round(bytes_cig / ms_cig * 1e3 / HBM_PEAK, 4),
+                                 "fp64_fma_tflops": round(2 * fma / ms_cig / 1e9, 3)},
+            "cpu_baseline": {"value": round(n_s / t_cpu, 1), "unit": "columns/s", "cores": 1, "kind": "oracle",
+                             "sample": f"moveout of {n_s} random columns x {nb} bins x {nz} depths, lag +-{max_lag}"},
+            "gpu_columns_per_s": round(ny * nx / ms_cig * 1e3, 1),
+            "parity_sample_max_shift_err": err, "parity_sample_clear_frac": round(float(clear.mean()), 4),
+            "cpu_count": os.cpu_count()}
+
+
 def run(workload, steps, warmup, dev):
+    if workload == "cig":
+        return _cig(steps, warmup, dev)
     if workload in ("survey3d_bf16", "survey3d_f16"):
         return _survey16(workload.split("_")[1], steps, warmup, dev)
     if workload == "line2d_vz":
