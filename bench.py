@@ -43,9 +43,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "a85c5323f254129362beb07c2c6f1580f3ceb9a270bb87632911b1fc5b5d480f",
-    "migrate": 1.7206e12,
-    "demigrate": 1.0797e12,
+    "sources_sha256": "a456c288b1826cebc5295d5c1ff4779d7f1bdd6d4347a575f044f6a4580dfe75",
+    "migrate": 1.7284e12,
+    "demigrate": 1.1173e12,
 }
 
 
