@@ -40,9 +40,10 @@ __device__ __forceinline__ void stage_block(const Params& P, int64_t j0, int nb,
 // Two slots (k, k + 1) of one (column group, trace) pairing.  MASKED: some
 // valid lane may be outside the aperture, so each value is kept only where
 // hmax <= the lane's aperture value; CLAMP: the time is clamped to the row.
+// R0, R1: the lanes' aperture values of the two slots (read only when MASKED).
 template <bool TF, int WK, bool MASKED, bool CLAMP>
 __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
-                                         const float* row, float tfo, float wlo, float whi, const float* sRk,
+                                         const float* row, float tfo, float wlo, float whi, float R0, float R1,
                                          float& acc0, float& acc1) {
     const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
     const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
@@ -51,14 +52,16 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
     float v0 = fmaf(p0.f, b0 - a0, a0);
     float v1 = fmaf(p1.f, b1 - a1, a1);
     if (MASKED) {
-        v0 = (hm <= sRk[0]) ? v0 : 0.0f;
-        v1 = (hm <= sRk[kGroup]) ? v1 : 0.0f;
+        v0 = (hm <= R0) ? v0 : 0.0f;
+        v1 = (hm <= R1) ? v1 : 0.0f;
     }
     acc0 = (WK == W_COSCOS) ? fmaf(v0, p0.r, acc0) : acc0 + v0;
     acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
 }
 
-template <int NW, int CWQ, int KS, bool TF, int WK>
+// RREG: the masked slots take the lanes' aperture values from registers
+// (else from the LDS copy, which costs fewer registers).
+template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     const int lane = threadIdx.x & (kLanes - 1);
@@ -122,36 +125,53 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                 hmin4 = fminf(hmin4, __shfl_xor(hmin4, 32, kLanes));
                 float hmax4 = fmaxf(Lp.hmax, __shfl_xor(Lp.hmax, 16, kLanes));
                 hmax4 = fmaxf(hmax4, __shfl_xor(hmax4, 32, kLanes));
-                const uint64_t live = __builtin_amdgcn_ballot_w64(hmin4 <= T.rmax) & ((1ull << nbt) - 1ull);
+                uint64_t live = __builtin_amdgcn_ballot_w64(hmin4 <= T.rmax) & ((1ull << nbt) - 1ull);
                 if (!live) continue;
-                for (int t = 0; t < nbt; ++t) {
-                    if (!((live >> t) & 1ull)) continue;
-                    const float hmin = uniform_read(hmin4, t);
-                    const float hmaxw = uniform_read(hmax4, t);
+                // The legs of trace t reach the depth lanes through the LDS crossbar; the
+                // next live trace's are requested before trace t is evaluated.
+                int t = __builtin_ctzll(live);
+                live &= live - 1;
+                float hs2n = lane_read(Lp.hs2, (lane & ~(kGroup - 1)) | t);
+                float hr2n = lane_read(Lp.hr2, (lane & ~(kGroup - 1)) | t);
+                for (;;) {
+                    const int tc = t;
+                    const float hs2 = hs2n, hr2 = hr2n;
+                    const bool more = live != 0;
+                    if (more) {
+                        t = __builtin_ctzll(live);
+                        live &= live - 1;
+                        hs2n = lane_read(Lp.hs2, (lane & ~(kGroup - 1)) | t);
+                        hr2n = lane_read(Lp.hr2, (lane & ~(kGroup - 1)) | t);
+                    }
+                    const float hmin = uniform_read(hmin4, tc);
+                    const float hmaxw = uniform_read(hmax4, tc);
                     uint64_t any, full;
                     slot_masks<KS>(T, hmin, hmaxw, any, full);
-                    if (!any) continue;
-                    const int src = (lane & ~(kGroup - 1)) | t;
-                    const float hs2 = lane_read(Lp.hs2, src);
-                    const float hr2 = lane_read(Lp.hr2, src);
-                    const float hm = fmaxf(hs2, hr2);
-                    const float* row = sTr + (t0 + t) * P.lt + rowoff;
+                    if (any) {
+                        const float hm = fmaxf(hs2, hr2);
+                        const float* row = sTr + (t0 + tc) * P.lt + rowoff;
 #pragma unroll
-                    for (int k = 0; k < KS; k += 2) {
-                        if ((any >> k) & 3ull) {
-                            if (((full >> k) & 3ull) == 3ull) {
-                                if (noclamp)
-                                    mig_pair<TF, WK, false, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
-                                                                   tfo, wlo, whi, nullptr, acc[q][k], acc[q][k + 1]);
-                                else
-                                    mig_pair<TF, WK, false, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
-                                                                  tfo, wlo, whi, nullptr, acc[q][k], acc[q][k + 1]);
-                            } else {
-                                mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row, tfo,
-                                                             wlo, whi, sR + k * kGroup + d, acc[q][k], acc[q][k + 1]);
+                        for (int k = 0; k < KS; k += 2) {
+                            if ((any >> k) & 3ull) {
+                                if (((full >> k) & 3ull) == 3ull) {
+                                    if (noclamp)
+                                        mig_pair<TF, WK, false, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
+                                                                       row, tfo, wlo, whi, 0.0f, 0.0f, acc[q][k],
+                                                                       acc[q][k + 1]);
+                                    else
+                                        mig_pair<TF, WK, false, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
+                                                                      row, tfo, wlo, whi, 0.0f, 0.0f, acc[q][k],
+                                                                      acc[q][k + 1]);
+                                } else {
+                                    const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
+                                    const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
+                                    mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                                                 tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
+                                }
                             }
                         }
                     }
+                    if (!more) break;
                 }
             }
         }
@@ -200,7 +220,7 @@ __device__ __forceinline__ void zero_tile(const Params& P, int b, int tile, int 
 template <int NW, int CWQ, int KS, bool TF, int WK>
 __global__ __launch_bounds__(NW * 64) void migrate_kernel(Params P) {
     extern __shared__ float lds[];
-    migrate_tile<NW, CWQ, KS, TF, WK>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
+    migrate_tile<NW, CWQ, KS, TF, WK, true>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched persistent form: work items (problem, bin, column tile, depth
@@ -224,7 +244,7 @@ void migrate_batch_kernel(const Params* __restrict__ probs,
         const int4 w = items[it];  // (problem, bin, tile, zchunk)
         const Params P = probs[w.x];
         if (w.z < 0) zero_tile<NW, CWQ, KS>(P, w.y, -1 - w.z, w.w);
-        else migrate_tile<NW, CWQ, KS, TF, WK>(P, w.y, w.z, w.w, lds);
+        else migrate_tile<NW, CWQ, KS, TF, WK, false>(P, w.y, w.z, w.w, lds);
     }
 }
 
