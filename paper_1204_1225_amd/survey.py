@@ -437,6 +437,39 @@ def make_flat_line(v_true=2000.0, v_mig=2000.0, z_reflector=800.0, n_t=400, nz=2
     return p
 
 
+def rho_filter_taps(dt: float, alpha: float = 0.5, half_len: int = 32, n_fft: int = 8192):
+    """Taps (float32 [2 half_len + 1], centre index half_len) of the
+    anti-causal fractional derivative (-i w)^alpha in numpy's e^{+i w t}
+    convention (alpha = 1 is -d/dt), by frequency sampling on n_fft points and
+    a Hann window.  Summing a trace family along a traveltime surface that
+    only lies later than its apex acts on the wavelet as (-i w)^(-1/2) per
+    summed surface dimension, so alpha = 1/2 restores a zero-phase image for a
+    line (2D) and alpha = 1 for an areal (3D) acquisition."""
+    w = 2.0 * math.pi * np.fft.fftfreq(n_fft, dt)
+    H = np.power(-1j * w, alpha)
+    h = np.real(np.fft.ifft(H))
+    M = int(half_len)
+    taps = np.concatenate([h[n_fft - M:], h[:M + 1]])
+    win = 0.5 * (1.0 + np.cos(math.pi * np.arange(-M, M + 1) / (M + 1)))
+    return (taps * win).astype(np.float32), M
+
+
+def make_diffractor_line(v=2000.0, x_diff=1000.0, z_diff=600.0, spacing=5.0, n_t=400, dz=2.0, nz=400):
+    """2D zero-offset line over one point diffractor in a constant-velocity
+    earth (no noise): coincident source and receiver every `spacing` m over
+    0 .. 2000 m, 400 samples at 4 ms, 25 Hz Ricker with the cos cos / (T T)
+    amplitude; image: the single column at x_diff, z = dz (k + 1), one bin,
+    aperture 60 degrees."""
+    s = np.arange(0.0, 2000.0 + 1e-9, spacing)
+    src = np.stack([s, np.zeros(s.size)], 1)
+    z = dz * (np.arange(nz) + 1)
+    p = _finish("diffractor_line", src, src.copy(), n_t, 0.004, 0.0, [x_diff], [0.0], z, 1, 1e9,
+                ("const", v), 60.0)
+    p.scatterers = np.array([[x_diff, 0.0, z_diff]])
+    p.data = model_scatterers(p, p.scatterers).numpy()
+    return p
+
+
 def batch_line_shapes(seed=5, n_lines=64):
     """Shapes of the uneven batch: (n_shots, n_rec, n_t, nx, nz) per line,
     drawn inclusive from U{16..512}, U{48..480}, U{1000..3000}, U{256..2048},
