@@ -154,6 +154,26 @@ km_status km_dot_f64(const float* a, const float* b, int64_t n, double* out, voi
  * once).  x may equal y. */
 km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t n, void* stream);
 
+/* ---- trace pre-filter ------------------------------------------------------
+ * Eq. (1) sums the data as recorded.  Summing along a traveltime surface
+ * that lies later than its apex rotates and reshapes the wavelet (a half
+ * integration per summed surface dimension); a finite impulse response applied
+ * to every trace beforehand (the rho filter) compensates it.  The taps are an
+ * input; with taps h[0..n_taps-1], h[center] at zero lag:
+ *   adjoint = 0:  out[n] = sum_k h[k] in[n + center - k]
+ *   adjoint = 1:  out[m] = sum_k h[k] in[m - center + k]   (the transpose)
+ * with in = 0 outside [0, n_samples), float32 arithmetic, summation order
+ * fixed per output.  in, out: device float [n_traces][stride]; out may be
+ * the same buffer as in with the same stride, otherwise they must not
+ * overlap.  taps: device float[n_taps].
+ * KM_E_INVALID: NULL or misaligned pointers, n_traces < 0, n_samples < 0,
+ * stride < n_samples, n_taps < 1, center outside [0, n_taps).
+ * KM_E_UNSUPPORTED: n_taps > 1024, or one trace plus its halo and the taps
+ * exceed the 160 KiB of LDS of a workgroup. */
+km_status km_trace_filter(const float* in, int64_t in_stride, float* out, int64_t out_stride, int64_t n_traces,
+                          int32_t n_samples, const float* taps, int32_t n_taps, int32_t center, int32_t adjoint,
+                          void* stream);
+
 /* ---- offset stack and moveout of the offset images --------------------------
  * The migration gives one image per offset bin: redundant images of the same
  * subsurface.  The depth at which a reflector appears in the different offset

@@ -67,6 +67,7 @@ SIGNATURES = {
     "km_count_contributions": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTraveltime), _vp, _vp]),
     "km_dot_f64": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "km_axpby": (ctypes.c_int, [_f64, _vp, _f64, _vp, _i64, _vp]),
+    "km_trace_filter": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i64, _i32, _vp, _i32, _i32, _i32, _vp]),
     "km_stack_offsets": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp]),
     "km_cig_moveout": (ctypes.c_int, [_vp, _P(KmGrid), _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "km_tile_count": (_i32, [_i32]),

@@ -299,6 +299,31 @@ km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t 
     return e == hipSuccess ? KM_OK : hip_fail(e, "axpby launch");
 }
 
+km_status km_trace_filter(const float* in, int64_t in_stride, float* out, int64_t out_stride, int64_t n_traces,
+                          int32_t n_samples, const float* taps, int32_t n_taps, int32_t center, int32_t adjoint,
+                          void* stream) {
+    if (n_traces < 0 || n_samples < 0) return fail(KM_E_INVALID, "km_trace_filter: negative size");
+    if (n_taps < 1) return fail(KM_E_INVALID, "km_trace_filter: n_taps < 1");
+    if (n_taps > 1024) return fail(KM_E_UNSUPPORTED, "km_trace_filter: n_taps > 1024");
+    if (center < 0 || center >= n_taps) return fail(KM_E_INVALID, "km_trace_filter: center outside [0, n_taps)");
+    if (in_stride < n_samples || out_stride < n_samples)
+        return fail(KM_E_INVALID, "km_trace_filter: stride < n_samples");
+    if (n_traces == 0 || n_samples == 0) return KM_OK;
+    if (!in || !out || !taps || !aligned(in, 4) || !aligned(out, 4) || !aligned(taps, 4))
+        return fail(KM_E_INVALID, "km_trace_filter: in, out, taps NULL/misaligned");
+    if (in != out || in_stride != out_stride) {
+        const uintptr_t a0 = reinterpret_cast<uintptr_t>(in), b0 = reinterpret_cast<uintptr_t>(out);
+        const uintptr_t a1 = a0 + 4 * static_cast<uintptr_t>((n_traces - 1) * in_stride + n_samples);
+        const uintptr_t b1 = b0 + 4 * static_cast<uintptr_t>((n_traces - 1) * out_stride + n_samples);
+        if (a0 < b1 && b0 < a1) return fail(KM_E_INVALID, "km_trace_filter: in and out overlap");
+    }
+    if (km::fir_lds_bytes(n_samples, n_taps) > static_cast<size_t>(kMaxLds))
+        return fail(KM_E_UNSUPPORTED, "km_trace_filter: %d samples and %d taps do not fit in LDS", n_samples, n_taps);
+    const hipError_t e = km::launch_fir(in, in_stride, out, out_stride, n_traces, n_samples, taps, n_taps, center,
+                                        adjoint ? 1 : 0, static_cast<hipStream_t>(stream));
+    return e == hipSuccess ? KM_OK : hip_fail(e, "filter launch");
+}
+
 km_status km_stack_offsets(const float* image, int32_t n_bins, int64_t n_points, float* stack, void* stream) {
     if (n_bins < 1) return fail(KM_E_INVALID, "km_stack_offsets: n_bins < 1");
     if (n_points < 0) return fail(KM_E_INVALID, "km_stack_offsets: n_points < 0");

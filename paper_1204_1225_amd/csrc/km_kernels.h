@@ -61,6 +61,11 @@ hipError_t launch_cig(const float* img, int n_bins, int ny, int nx, int nz, int 
                       const float* offsets, float* stack, float* shift, float* peak, float* curvature,
                       hipStream_t s);
 
+// trace pre-filter (km_filter.hip)
+size_t fir_lds_bytes(int n, int K);
+hipError_t launch_fir(const float* in, int64_t in_stride, float* out, int64_t out_stride, int64_t n_traces, int n,
+                      const float* taps, int K, int c, int adjoint, hipStream_t s);
+
 // counting, reductions, probes (km_misc.hip)
 hipError_t launch_count(const Params& P, unsigned long long* counts, hipStream_t s);
 hipError_t launch_dot_f64(const float* a, const float* b, int64_t n, double* out, hipStream_t s);

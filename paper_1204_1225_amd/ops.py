@@ -195,6 +195,23 @@ def axpby(alpha: float, x: torch.Tensor, beta: float, y: torch.Tensor) -> torch.
     return y
 
 
+def trace_filter(traces: torch.Tensor, taps: torch.Tensor, center: int, adjoint: bool = False,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """FIR pre-filter of every row of traces [n, n_samples] (float32, row
+    stride taken from the tensor): forward out[n] = sum_k h[k] in[n + c - k],
+    adjoint the transpose.  out may be traces itself."""
+    assert traces.dtype == torch.float32 and traces.dim() == 2 and traces.stride(1) == 1
+    assert taps.dtype == torch.float32 and taps.dim() == 1 and taps.is_contiguous() and taps.device == traces.device
+    if out is None:
+        out = torch.empty_like(traces, memory_format=torch.contiguous_format)
+    assert out.shape == traces.shape and out.stride(1) == 1
+    n, ns = traces.shape
+    check(_lib.load().km_trace_filter(_ptr(traces), traces.stride(0) if n else ns, _ptr(out),
+                                      out.stride(0) if n else ns, n, ns, _ptr(taps), taps.numel(), int(center),
+                                      1 if adjoint else 0, ctypes.c_void_p(_stream(traces.device))))
+    return out
+
+
 def stack_offsets(image: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """Sum of the offset images image[n_bins, ...] over the bins (float32)."""
     assert image.dtype == torch.float32 and image.is_contiguous() and image.dim() >= 1

@@ -167,3 +167,25 @@ def test_stack_and_moveout_reject_bad_arguments(lib):
     assert lib.km_cig_moveout(p, ctypes.byref(big), p, 4, 0, 100, None, p, None, None, None) == \
         _lib.KM_E_UNSUPPORTED
     assert b"LDS" in lib.km_last_error()
+
+
+def test_trace_filter_rejects_bad_arguments(lib):
+    from paper_1204_1225_amd import _lib
+
+    p = ctypes.c_void_p(0x1000)
+    q = ctypes.c_void_p(0x10000000)  # far enough from p that the buffers do not overlap
+    cases = [
+        ((p, 10, q, 10, -1, 10, p, 3, 1, 0), _lib.KM_E_INVALID, b"negative"),
+        ((p, 10, q, 10, 4, 10, p, 0, 0, 0), _lib.KM_E_INVALID, b"n_taps"),
+        ((p, 10, q, 10, 4, 10, p, 2000, 0, 0), _lib.KM_E_UNSUPPORTED, b"n_taps"),
+        ((p, 10, q, 10, 4, 10, p, 3, 3, 0), _lib.KM_E_INVALID, b"center"),
+        ((p, 10, q, 10, 4, 10, p, 3, -1, 0), _lib.KM_E_INVALID, b"center"),
+        ((p, 5, q, 10, 4, 10, p, 3, 1, 0), _lib.KM_E_INVALID, b"stride"),
+        ((None, 10, q, 10, 4, 10, p, 3, 1, 0), _lib.KM_E_INVALID, b"NULL"),
+        ((p, 10, ctypes.c_void_p(0x1010), 10, 4, 10, p, 3, 1, 0), _lib.KM_E_INVALID, b"overlap"),
+        ((p, 40000, q, 40000, 4, 40000, p, 1024, 1, 0), _lib.KM_E_UNSUPPORTED, b"LDS"),
+    ]
+    for args, status, msg in cases:
+        assert lib.km_trace_filter(*args, None) == status, args
+        assert msg in lib.km_last_error()
+    assert lib.km_trace_filter(None, 10, None, 10, 0, 10, None, 3, 1, 0, None) == _lib.KM_OK
