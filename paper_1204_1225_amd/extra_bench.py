@@ -8,6 +8,9 @@ line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
 batch: 64 uneven 2D lines migrated by one persistent hipGraph-captured launch
     against 64 separate launches (same tile shape, chosen by the tuner on the
     largest line), images compared bit for bit.
+filter: the rho pre-filter (anti-causal derivative, 65 taps) forward and
+    transposed over the 3D survey's 200 000 x 1500 traces: HBM bandwidth
+    against 8 TB/s and the FP64 oracle timed on sampled traces.
 cig: the offset stack and the common-image-gather moveout of the migrated 3D
     survey image (16 x 256 x 256 x 400): HBM bandwidth of both kernels against
     8 TB/s, and the FP64 oracle timed on a sample of image columns.
@@ -159,7 +162,42 @@ def _cig(steps, warmup, dev, max_lag=12):
             "cpu_count": os.cpu_count()}
 
 
+def _filter(steps, warmup, dev):
+    from oracle import trace_filter as otf
+
+    p = survey.make_survey3d(seed=2, device=dev)
+    dp = ops.to_device(p, dev)
+    taps_np, c = survey.rho_filter_taps(p.dt, 1.0, half_len=32)
+    taps = torch.from_numpy(taps_np).to(dev)
+    x = dp.data
+    y = torch.empty_like(x)
+    ms_f = _time(lambda: ops.trace_filter(x, taps, c, out=y), steps, warmup)
+    z = torch.empty_like(x)
+    ms_a = _time(lambda: ops.trace_filter(y, taps, c, adjoint=True, out=z), steps, warmup)
+    nbytes = 2 * x.numel() * 4
+    fma = x.numel() * taps.numel()
+    rng = np.random.default_rng(0)
+    idx = np.sort(rng.choice(x.shape[0], 512, replace=False))
+    sample = x[idx].cpu().numpy()
+    t0 = time.perf_counter()
+    ref = otf.forward(sample, taps_np, c)
+    t_cpu = time.perf_counter() - t0
+    got = y[idx].cpu().numpy()
+    err = float(np.abs(got - ref).max() / (np.abs(ref).max() + 1e-30))
+    return {"workload": "filter", "metric": "HBM GB/s (rho pre-filter, forward; transpose)",
+            "traces": list(x.shape), "taps": int(taps.numel()), "ms_forward": round(ms_f, 4),
+            "ms_adjoint": round(ms_a, 4),
+            "roofline": {"bound": "hbm", "achieved": round(nbytes / ms_f / 1e6, 1), "peak": HBM_PEAK / 1e9,
+                         "unit": "GB/s", "frac": round(nbytes / ms_f * 1e3 / HBM_PEAK, 4),
+                         "fp32_fma_tflops": round(2 * fma / ms_f / 1e9, 3)},
+            "cpu_baseline": {"value": round(512 / t_cpu, 1), "unit": "traces/s", "cores": 1, "kind": "oracle",
+                             "sample": "forward filter of 512 random traces x 1500 samples, 65 taps"},
+            "gpu_traces_per_s": round(x.shape[0] / ms_f * 1e3, 1), "parity_sample_max_rel_err": err}
+
+
 def run(workload, steps, warmup, dev):
+    if workload == "filter":
+        return _filter(steps, warmup, dev)
     if workload == "cig":
         return _cig(steps, warmup, dev)
     if workload in ("survey3d_bf16", "survey3d_f16"):
