@@ -7,7 +7,8 @@ columns or traces); this module only loads it and passes numpy arrays.
 
 Every function takes a problem object with the attributes of a survey
 problem (src, rec, bin, n_t, dt, t_first, x, y, t0sq, s2, r2, weight,
-n_bins) and, where samples are needed, a float64 data array [n_traces, n_t]
+n_bins, and optionally a one-way traveltime table ttab [n_h][nz] with
+spacing tdh, which replaces the t0sq / s2 form) and, where samples are needed, a float64 data array [n_traces, n_t]
 (default: the problem's own data widened to float64).
 
 Parity status: all functions are pinned by the CPU tests (closed forms,
@@ -47,6 +48,7 @@ class _Problem(ctypes.Structure):
         ("x", ctypes.c_void_p), ("y", ctypes.c_void_p),
         ("t0sq", ctypes.c_void_p), ("s2", ctypes.c_void_p), ("r2", ctypes.c_void_p),
         ("weight", ctypes.c_int32),
+        ("n_h", ctypes.c_int32), ("dh", ctypes.c_double), ("ttab", ctypes.c_void_p),
     ]
 
 
@@ -91,6 +93,10 @@ class _Bound:
                 data = data.detach().cpu().numpy()
             self.keep["data"] = _arr(data, np.float64)
             assert self.keep["data"].shape == (self.keep["src"].shape[0], int(p.n_t))
+        ttab = getattr(p, "ttab", None)
+        if ttab is not None:
+            self.keep["ttab"] = _arr(ttab, np.float32)
+            assert self.keep["ttab"].ndim == 2 and self.keep["ttab"].shape[1] == self.keep["t0sq"].shape[0]
         k = self.keep
         self.s = _Problem(
             n_traces=k["src"].shape[0], n_t=int(p.n_t), t_first=float(p.t_first), dt=float(p.dt),
@@ -98,7 +104,9 @@ class _Bound:
             src=k["src"].ctypes.data, rec=k["rec"].ctypes.data, bin=k["bin"].ctypes.data,
             nx=k["x"].shape[0], ny=k["y"].shape[0], nz=k["t0sq"].shape[0], n_bins=int(p.n_bins),
             x=k["x"].ctypes.data, y=k["y"].ctypes.data, t0sq=k["t0sq"].ctypes.data, s2=k["s2"].ctypes.data,
-            r2=k["r2"].ctypes.data, weight=int(p.weight))
+            r2=k["r2"].ctypes.data, weight=int(p.weight),
+            n_h=k["ttab"].shape[0] if "ttab" in k else 0, dh=float(getattr(p, "tdh", 0.0) or 0.0),
+            ttab=k["ttab"].ctypes.data if "ttab" in k else None)
         assert k["s2"].shape[0] == self.s.nz and k["r2"].shape[0] == self.s.nz
 
     @property

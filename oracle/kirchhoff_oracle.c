@@ -33,6 +33,12 @@
  *  - The adjoint (demigration) is the exact transpose: each in-aperture pair
  *    adds (1 - f) W I to D[i] and f W I to D[i + 1] (samples outside [0, n_t)
  *    are dropped).
+ *  - Table traveltimes (ttab != NULL; curved rays in a laterally invariant
+ *    medium, where a one-way time depends only on the horizontal distance h
+ *    and the depth): T(h, z[iz]) is the linear interpolation in h of
+ *    ttab[ih][iz], the time at h = ih * dh, with h = sqrt(h^2) in FP64 and
+ *    h / dh clamped to [0, n_h - 1] (beyond the table the last value holds).
+ *    The aperture test is unchanged; W = 1 (weight kind 0 only).
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
  */
@@ -62,7 +68,23 @@ typedef struct {
     const double* s2;      /* [nz] */
     const float* r2;       /* [nz] */
     int32_t weight;        /* 0: W = 1; 1: W = t0sq / (a_s a_r) */
+    int32_t n_h;           /* table traveltimes: rows of ttab (>= 2) */
+    double dh;             /* table spacing in h (> 0) */
+    const float* ttab;     /* [n_h][nz] one-way seconds, or NULL for the t0sq / s2 form */
 } ko_problem;
+
+/* Linear interpolation in h of the one-way time table at depth iz. */
+static double ko_table_time(const ko_problem* P, double h, int iz)
+{
+    double hf = h / P->dh;
+    const double top = (double)(P->n_h - 1);
+    if (!(hf < top)) hf = top;
+    int64_t ih = (int64_t)floor(hf);
+    if (ih > P->n_h - 2) ih = P->n_h - 2;
+    const double f = hf - (double)ih;
+    const double t0 = P->ttab[ih * (int64_t)P->nz + iz], t1 = P->ttab[(ih + 1) * (int64_t)P->nz + iz];
+    return t0 + f * (t1 - t0);
+}
 
 /* Aperture decision in float32 (see header). */
 static int ko_in_aperture(float px, float py, float sx, float sy, float rx, float ry, float r2)
@@ -84,6 +106,12 @@ static int ko_pair(const ko_problem* P, int64_t j, int ix, int iy, int iz, doubl
     if (!ko_in_aperture(px, py, sx, sy, rx, ry, P->r2[iz])) return 0;
     double hs2 = ((double)px - sx) * ((double)px - sx) + ((double)py - sy) * ((double)py - sy);
     double hr2 = ((double)px - rx) * ((double)px - rx) + ((double)py - ry) * ((double)py - ry);
+    if (P->ttab) {
+        const double T = ko_table_time(P, sqrt(hs2), iz) + ko_table_time(P, sqrt(hr2), iz);
+        *u = (T - P->t_first) / P->dt;
+        *w = 1.0;
+        return 1;
+    }
     double a_s = P->t0sq[iz] + P->s2[iz] * hs2;
     double a_r = P->t0sq[iz] + P->s2[iz] * hr2;
     double T = sqrt(a_s) + sqrt(a_r);
@@ -111,6 +139,7 @@ static int ko_check(const ko_problem* P)
 {
     if (!P || P->n_traces < 0 || P->n_t < 0 || P->nx < 0 || P->ny < 0 || P->nz < 0 || P->n_bins < 0) return 1;
     if (!(P->dt > 0.0)) return 1;
+    if (P->ttab && (P->n_h < 2 || !(P->dh > 0.0) || P->weight != 0)) return 1;
     return 0;
 }
 

@@ -72,6 +72,9 @@ class Problem:
     scatterers: Optional[np.ndarray] = None  # [m, 3] x, y, z of modelled point scatterers
     diffractor_nodes: Optional[np.ndarray] = None  # [m, 3] (ix, iy, iz) grid nodes
     meta: dict = dataclasses.field(default_factory=dict)
+    # optional one-way traveltime table [n_h][nz] (seconds at h = ih * tdh), replacing t0sq / s2
+    ttab: Optional[np.ndarray] = None
+    tdh: float = 0.0
 
     @property
     def n_traces(self) -> int:
@@ -141,6 +144,38 @@ def traveltime_tables(z: np.ndarray, velocity: tuple):
     return t0 * t0, s2
 
 
+def curved_ray_time(h, z, v0: float, k: float):
+    """One-way time of the curved (circular-arc) ray from a surface point to a
+    point at horizontal distance h and depth z in v(z) = v0 + k z, FP64:
+    T = acosh(1 + k^2 (h^2 + z^2) / (2 v0 v(z))) / k  (straight ray r / v0 at k = 0),
+    with acosh(1 + e) evaluated as log1p(e + sqrt(e (e + 2)))."""
+    h = np.asarray(h, dtype=np.float64)
+    z = np.asarray(z, dtype=np.float64)
+    if k == 0.0:
+        return np.sqrt(h * h + z * z) / v0
+    e = k * k * (h * h + z * z) / (2.0 * v0 * (v0 + k * z))
+    return np.log1p(e + np.sqrt(e * (e + 2.0))) / k  # acosh(1 + e) without cancellation at small e
+
+
+def curved_ray_table(z, v0: float, k: float, dh: float, n_h: int) -> np.ndarray:
+    """ttab[ih][iz] = curved_ray_time(ih dh, z[iz]) rounded once to float32."""
+    h = dh * np.arange(n_h, dtype=np.float64)
+    return curved_ray_time(h[:, None], np.asarray(z, np.float64)[None, :], v0, k).astype(np.float32)
+
+
+def with_curved_ray_table(problem: "Problem", dh: float = 10.0, n_h: Optional[int] = None) -> "Problem":
+    """The problem with its traveltimes replaced by the curved-ray table of its
+    linear (or constant) velocity model, covering every in-aperture leg;
+    weight becomes W = 1."""
+    vel = problem.velocity
+    v0, k = (float(vel[1]), 0.0) if vel[0] == "const" else (float(vel[1]), float(vel[2]))
+    if n_h is None:
+        hmax = float(np.sqrt(np.max(problem.r2.astype(np.float64))))
+        n_h = int(np.ceil(hmax / dh)) + 2
+    tab = curved_ray_table(problem.z, v0, k, dh, n_h)
+    return dataclasses.replace(problem, ttab=tab, tdh=float(dh), weight=WEIGHT_UNIT)
+
+
 def aperture_table(t0sq: np.ndarray, s2: np.ndarray, aperture_deg: float) -> np.ndarray:
     """r2[iz] = tan^2(theta_max) * t0^2 / s2, rounded once to float32.
 
@@ -200,13 +235,15 @@ def _leg_time_and_cos(velocity, sx, sy, rz, px, py):
 
 
 def model_scatterers(problem: Problem, scat: np.ndarray, f_peak: float = 25.0,
-                     device=None, chunk: int = 4096, half_width_s: float = 0.08):
+                     device=None, chunk: int = 4096, half_width_s: float = 0.08, rays: str = "straight"):
     """Trace samples from point scatterers: D_j(t) = sum_k a_kj r(t - tau_kj).
 
-    tau_kj = source-leg + receiver-leg time (straight rays), a_kj the
-    obliquity/spreading factor cos_s cos_r / (T_s T_r) normalised per
-    scatterer to a maximum of 1 over all traces.  Returns float32 [n, n_t]
-    as a torch tensor on `device` (default CPU).
+    tau_kj = source-leg + receiver-leg time, a_kj the obliquity/spreading
+    factor cos_s cos_r / (T_s T_r) normalised per scatterer to a maximum of 1
+    over all traces.  rays = "straight": straight rays (Euclidean for constant
+    v, the RMS model for v(z)); rays = "curved": the exact circular-arc ray
+    times of v(z) = v0 + k z with a_kj = 1 / (T_s T_r) normalised the same way.
+    Returns float32 [n, n_t] as a torch tensor on `device` (default CPU).
     """
     import torch
 
@@ -222,7 +259,21 @@ def model_scatterers(problem: Problem, scat: np.ndarray, f_peak: float = 25.0,
         return out.view(n, nt)
     px, py, pz = sc[:, 0][None, :], sc[:, 1][None, :], sc[:, 2][None, :]
 
+    vel = problem.velocity
+    v0, kg = (float(vel[1]), 0.0) if vel[0] == "const" else (float(vel[1]), float(vel[2]))
+
+    def curved(sx, sy):
+        h2 = (px - sx) ** 2 + (py - sy) ** 2
+        if kg == 0.0:
+            return torch.sqrt(h2 + pz * pz) / v0
+        e = kg * kg * (h2 + pz * pz) / (2.0 * v0 * (v0 + kg * pz))
+        return torch.log1p(e + torch.sqrt(e * (e + 2.0))) / kg
+
     def legs(j0, j1):
+        if rays == "curved":
+            ts = curved(src[j0:j1, 0:1], src[j0:j1, 1:2])
+            tr = curved(rec[j0:j1, 0:1], rec[j0:j1, 1:2])
+            return ts + tr, 1.0 / (ts * tr)
         ts, cs = _leg_time_and_cos(problem.velocity, src[j0:j1, 0:1], src[j0:j1, 1:2], pz, px, py)
         tr, cr = _leg_time_and_cos(problem.velocity, rec[j0:j1, 0:1], rec[j0:j1, 1:2], pz, px, py)
         return ts + tr, cs * cr / (ts * tr)

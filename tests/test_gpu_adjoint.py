@@ -160,3 +160,27 @@ def test_lsm_monotone(ops, tmp_path):
     lsm.lsm(dp, d_obs, n_iter=3, checkpoint=ck)
     res2 = lsm.lsm(dp, d_obs, n_iter=6, checkpoint=ck)
     assert np.allclose(res2.objective, J, rtol=1e-5)
+
+
+def test_demigrate_unordered_grid_and_far_traces(ops, oracle_lib):
+    # The adjoint sweeps, per trace block, only the index box of columns that
+    # can be inside the aperture; the box is found by scanning x[] and y[], so
+    # it must also hold for coordinate arrays in no particular order, for
+    # blocks whose traces are all far outside the image, and for bins with a
+    # single trace.
+    p = survey.make_random(86, n_traces=160, n_t=280, nx=13, ny=6, nz=60, n_bins=3, dz=10.0, spread=400)
+    rng = np.random.default_rng(86)
+    p.x = p.x[rng.permutation(p.x.size)].copy()
+    p.y = p.y[rng.permutation(p.y.size)].copy()
+    far = rng.choice(p.n_traces, 40, replace=False)
+    p.src[far] += np.float32(50000.0)
+    p.rec[far] += np.float32(50000.0)
+    m = survey.random_image(p, 87)
+    ref = oracle_lib.demigrate(p, m)
+    assert np.abs(ref[far]).max() == 0.0
+    dp = ops.to_device(p)
+    mt = torch.from_numpy(m).cuda()
+    for tile in range(ops.tile_count(1)):
+        d = ops.demigrate(dp, mt, tile=tile).cpu().numpy()
+        assert rel_l2(d, ref) <= 1e-5
+        assert np.abs(d[far]).max() == 0.0
