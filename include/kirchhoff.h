@@ -138,6 +138,34 @@ km_status kirchhoff_demigrate(const float* image, const km_grid* grid, const km_
                               const km_weight* weight, const km_traces* out, int32_t accumulate,
                               int32_t tile, void* stream);
 
+/* ---- table traveltimes -----------------------------------------------------
+ * Section 3 takes the propagation times from ray theory in the model.  In a
+ * medium whose velocity varies with depth only, a one-way time depends on the
+ * horizontal distance h and the depth alone, so curved-ray times can be given
+ * as a table: T(h, z_iz) = t[ih][iz] + f (t[ih + 1][iz] - t[ih][iz]) with
+ * h = sqrt(h^2) (the float32 h^2 of the aperture test), h / dh = ih + f
+ * clamped to [0, n_h - 1] (beyond the table its last row holds).  These calls
+ * are kirchhoff_migrate / kirchhoff_demigrate with T_s + T_r from the table in
+ * place of the t0sq / s2 form and W = 1; the aperture test (h^2 <= r2[iz] for
+ * both legs), the interpolation of the trace and the transpose are the same. */
+typedef struct km_ttable {
+    int32_t n_h;     /* table rows (>= 2) */
+    double dh;       /* row spacing in h, same length unit as x, y (finite, > 0) */
+    const float* t;  /* device float [n_h][nz]: one-way time in seconds at h = ih * dh, depth index iz */
+    const float* r2; /* device float [nz]: aperture, as km_traveltime.r2 */
+} km_ttable;
+
+/* As kirchhoff_migrate with table traveltimes and W = 1.  KM_E_INVALID also
+ * for a NULL table, n_h < 2, dh not finite or <= 0, NULL or misaligned t / r2;
+ * KM_E_UNSUPPORTED for n_h * nz >= 2^31. */
+km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, const km_ttable* table, float* image,
+                                  int32_t accumulate, int32_t tile, void* stream);
+
+/* As kirchhoff_demigrate with table traveltimes and W = 1: the exact transpose
+ * of kirchhoff_migrate_table for the same inputs. */
+km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, const km_ttable* table,
+                                    const km_traces* out, int32_t accumulate, int32_t tile, void* stream);
+
 /* Pair counts of Eq. (2) (f_K N_xyz N_tr with N_tr the traces close enough):
  * counts[0] = pairs passing the aperture test, counts[1] = those whose time
  * also falls inside the zero-extended record (-1 < u < n_samples, u in the

@@ -195,8 +195,19 @@ km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {
 }
 
 km_status run_op(int op, const km_traces* t, const km_grid* g, const km_traveltime* tt, const km_weight* w,
-                 float* image, int accumulate, int shape, hipStream_t s) {
+                 float* image, int accumulate, int shape, hipStream_t s, const km_ttable* tab = nullptr) {
     km::Params P = base_params(t, g, tt, w, image, accumulate);
+    if (tab) {
+        P.ttab = tab->t;
+        P.n_h = tab->n_h;
+        P.inv_dh = static_cast<float>(1.0 / tab->dh);
+        P.inv_dt = 1.0 / t->dt;
+        P.tf_off_d = km::kLead - t->t_first / t->dt;
+        P.t0sq = nullptr;
+        P.s2 = nullptr;
+        P.r2 = tab->r2;
+        P.weight = KM_W_UNIT;
+    }
     km_status st = shape_params(op, shape, P);
     if (st != KM_OK) return st;
     if (op == 1 && (P.n_traces + P.tb - 1) / P.tb > INT32_MAX)
@@ -213,19 +224,8 @@ km_status zero_floats(float* p, int64_t n, hipStream_t s) {
     return e == hipSuccess ? KM_OK : hip_fail(e, "zero fill");
 }
 
-}  // namespace
-
-extern "C" {
-
-int km_abi_version(void) { return KM_ABI_VERSION; }
-
-const char* km_last_error(void) { return g_last_error.c_str(); }
-
-// one float64 accumulator row (demigrate), its geometry and the chunk tables fit in 160 KiB
-int32_t km_max_samples(void) { return 20000; }
-
-km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
-                            const km_weight* weight, float* image, int32_t accumulate, int32_t tile, void* stream) {
+km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_traveltime* tt, const km_weight* weight,
+                       float* image, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab) {
     km_status st = check_traces(traces, true, "kirchhoff_migrate");
     if (st != KM_OK) return st;
     st = check_grid(grid, tt, weight, "kirchhoff_migrate");
@@ -238,12 +238,11 @@ km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const 
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (traces->n_traces == 0 && !accumulate)
         return zero_floats(image, static_cast<int64_t>(grid->n_bins) * grid->ny * grid->nx * grid->nz, s);
-    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s);
+    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s, tab);
 }
 
-km_status kirchhoff_demigrate(const float* image, const km_grid* grid, const km_traveltime* tt,
-                              const km_weight* weight, const km_traces* out, int32_t accumulate, int32_t tile,
-                              void* stream) {
+km_status demigrate_impl(const float* image, const km_grid* grid, const km_traveltime* tt, const km_weight* weight,
+                         const km_traces* out, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab) {
     km_status st = check_traces(out, true, "kirchhoff_demigrate");
     if (st != KM_OK) return st;
     if (out->dtype != KM_F32)
@@ -262,8 +261,64 @@ km_status kirchhoff_demigrate(const float* image, const km_grid* grid, const km_
     int shape = 0;
     st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, &shape);
     if (st != KM_OK) return st;
-    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s);
+    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab);
 }
+
+// Table traveltimes: validate the table, then run the shared path with the
+// table in place of t0sq / s2 (only r2 of the traveltime struct is read).
+km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who) {
+    if (!tab) return fail(KM_E_INVALID, "%s: table is NULL", who);
+    if (tab->n_h < 2) return fail(KM_E_INVALID, "%s: n_h < 2", who);
+    if (!(tab->dh > 0.0) || !std::isfinite(tab->dh)) return fail(KM_E_INVALID, "%s: dh must be finite and > 0", who);
+    if (grid && static_cast<int64_t>(tab->n_h) * grid->nz >= (int64_t(1) << 31))
+        return fail(KM_E_UNSUPPORTED, "%s: n_h * nz must be < 2^31", who);
+    if (grid && !grid_empty(grid)) {
+        if (!tab->t || !tab->r2) return fail(KM_E_INVALID, "%s: t and r2 must be non-NULL", who);
+        if (!aligned(tab->t, 4) || !aligned(tab->r2, 4)) return fail(KM_E_INVALID, "%s: t, r2 misaligned", who);
+    }
+    return KM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int km_abi_version(void) { return KM_ABI_VERSION; }
+
+const char* km_last_error(void) { return g_last_error.c_str(); }
+
+// one float64 accumulator row (demigrate), its geometry and the chunk tables fit in 160 KiB
+int32_t km_max_samples(void) { return 20000; }
+
+km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                            const km_weight* weight, float* image, int32_t accumulate, int32_t tile, void* stream) {
+    return migrate_impl(traces, grid, tt, weight, image, accumulate, tile, stream, nullptr);
+}
+
+km_status kirchhoff_demigrate(const float* image, const km_grid* grid, const km_traveltime* tt,
+                              const km_weight* weight, const km_traces* out, int32_t accumulate, int32_t tile,
+                              void* stream) {
+    return demigrate_impl(image, grid, tt, weight, out, accumulate, tile, stream, nullptr);
+}
+
+km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, const km_ttable* tab, float* image,
+                                  int32_t accumulate, int32_t tile, void* stream) {
+    km_status st = check_table(tab, grid, "kirchhoff_migrate_table");
+    if (st != KM_OK) return st;
+    const km_traveltime tt{tab->r2, tab->r2, tab->r2};
+    const km_weight w{KM_W_UNIT};
+    return migrate_impl(traces, grid, &tt, &w, image, accumulate, tile, stream, tab);
+}
+
+km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, const km_ttable* tab,
+                                    const km_traces* out, int32_t accumulate, int32_t tile, void* stream) {
+    km_status st = check_table(tab, grid, "kirchhoff_demigrate_table");
+    if (st != KM_OK) return st;
+    const km_traveltime tt{tab->r2, tab->r2, tab->r2};
+    const km_weight w{KM_W_UNIT};
+    return demigrate_impl(image, grid, &tt, &w, out, accumulate, tile, stream, tab);
+}
+
 
 km_status km_count_contributions(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
                                  int64_t* counts, void* stream) {

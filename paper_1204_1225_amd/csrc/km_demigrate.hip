@@ -101,6 +101,26 @@ __device__ __forceinline__ void dem_masked(float A0, float B0, float A1, float B
     }
 }
 
+// dem_full / dem_masked with table traveltimes (W = 1); iz0, iz1 are the
+// lane's depths of the two slots, clamped into the table.
+template <bool TF, bool MASKED>
+__device__ __forceinline__ void dem_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz0, int iz1, double* row,
+                                               float tfo, float wlo, float whi, float x0, float x1, bool act0,
+                                               bool act1) {
+    if (!MASKED || act0) {
+        const Pair p0 = eval_pair_table<TF>(P, Ls, Lr, iz0, tfo, wlo, whi);
+        const float b0 = p0.f * x0;
+        atomicAdd(row + p0.i, static_cast<double>(x0 - b0));
+        atomicAdd(row + p0.i + 1, static_cast<double>(b0));
+    }
+    if (!MASKED || act1) {
+        const Pair p1 = eval_pair_table<TF>(P, Ls, Lr, iz1, tfo, wlo, whi);
+        const float b1 = p1.f * x1;
+        atomicAdd(row + p1.i, static_cast<double>(x1 - b1));
+        atomicAdd(row + p1.i + 1, static_cast<double>(b1));
+    }
+}
+
 // Coordinates and image values (depth slots of this lane) of column (ix, iy).
 // Lanes past the last depth (only in the last chunk, TAIL) read the last
 // depth instead; they are never inside the aperture, so the value is unused.
@@ -125,7 +145,7 @@ __device__ __forceinline__ void fetch_column(const Params& P, const float* img, 
 // One depth chunk of the segment: wavefront `wave` takes the box columns
 // wave, wave + NW, ... in row-major order and scatters every pairing of a
 // column with the segment's traces into their rows.
-template <int NW, int KS, int NQ, bool TF, int WK, bool CLAMP, bool TAIL>
+template <int NW, int KS, int NQ, bool TF, int WK, bool CLAMP, bool TAIL, int TT>
 __device__ __forceinline__ void sweep_columns(const Params& P, const float* img, int z0, int d, int g, int wave, int t0,
                                               int nseg, int nq, int ix0, int ix1, int iy0, int iy1,
                                               const ChunkTables<KS>& T, const float* S, const float4* G, double* sAcc) {
@@ -167,6 +187,21 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
             if (!any) continue;
             const uint32_t full = fold_and(__builtin_amdgcn_ballot_w64(L.hmax <= T.rlo)) & T.clean;
             double* row = rows[q];
+            if (TT == TT_TABLE) {
+                const TLeg Ls = table_leg(P, L.hs2), Lr = table_leg(P, L.hr2);
+#pragma unroll
+                for (int k = 0; k < KS; k += 2) {
+                    if (!((any >> k) & 3u)) continue;
+                    const int iz0 = min(slot_depth<kIL>(z0, k, d), P.nz - 1);
+                    const int iz1 = min(slot_depth<kIL>(z0, k + 1, d), P.nz - 1);
+                    if (((full >> k) & 3u) == 3u)
+                        dem_pair_table<TF, false>(P, Ls, Lr, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1], true, true);
+                    else
+                        dem_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1],
+                                                 L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
+                }
+                continue;
+            }
 #pragma unroll
             for (int k = 0; k < KS; k += 2) {
                 if (!((any >> k) & 3u)) continue;
@@ -182,7 +217,7 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 }
 
 // Traces t0..t1-1 of the block (one bin b, at most 4 NQ traces).
-template <int NW, int KS, int NQ, bool TF, int WK>
+template <int NW, int KS, int NQ, bool TF, int WK, int TT>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
                                                   double* sAcc) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
@@ -221,7 +256,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     for (int zc = 0; zc < P.n_zchunks; ++zc) {
         const int z0 = zc * KS * kGroup;
         ChunkTables<KS> T;
-        load_chunk_tables<KS, kIL>(P, z0, d, WK == W_COSCOS, T, nullptr);
+        load_chunk_tables<KS, kIL, TT>(P, z0, d, WK == W_COSCOS, T, nullptr);
         if (!(T.rmax >= 0.0f)) continue;
         const bool noclamp = !TF && T.wmax <= whi;
         float S[KS];
@@ -240,7 +275,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
         if (iy0 > iy1) continue;
         const bool tail = z0 + KS * kGroup > P.nz;
 #define KM_SWEEP(CLAMP, TAIL)                                                                                 \
-    sweep_columns<NW, KS, NQ, TF, WK, CLAMP, TAIL>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S, \
+    sweep_columns<NW, KS, NQ, TF, WK, CLAMP, TAIL, TT>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S, \
                                                    G, sAcc)
         if (noclamp) {
             if (tail) KM_SWEEP(false, true);
@@ -253,7 +288,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     }
 }
 
-template <int NW, int KS, int NQ, bool TF, int WK>
+template <int NW, int KS, int NQ, bool TF, int WK, int TT = TT_DSR>
 __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     extern __shared__ float lds[];
     double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
@@ -278,7 +313,7 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
         const int b = P.bin[j0 + t0];
         int t1 = t0 + 1;
         while (t1 < nb && P.bin[j0 + t1] == b) ++t1;
-        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK>(P, b, t0, t1, sGeo, sAcc);
+        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK, TT>(P, b, t0, t1, sGeo, sAcc);
         t0 = t1;
     }
     __syncthreads();
@@ -300,6 +335,10 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     const int64_t nblk = (P.n_traces + P.tb - 1) / P.tb;
     dim3 grid(static_cast<unsigned>(nblk)), block(NW * 64);
     const size_t lds = lds_bytes_f64rows(P);
+    if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
+        if (P.has_tf) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
+        return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
+    }
     if (P.has_tf) {
         if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_COSCOS>, grid, block, lds, s, P);
         return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT>, grid, block, lds, s, P);

@@ -62,7 +62,17 @@ struct Params {
     int32_t n_zchunks;
     int32_t n_coltiles;
     int32_t vec_ok;   // data base 16-byte aligned and stride a multiple of 4 elements (8 for 16-bit)
+    // table traveltimes (used by the TABLE kernels instead of t0sq / s2)
+    const float* ttab;  // [n_h][nz] one-way seconds at h = ih * dh
+    int32_t n_h;
+    float inv_dh;       // 1 / dh
+    double inv_dt;      // 1 / dt
+    double tf_off_d;    // kLead - t_first / dt in float64
 };
+
+// Traveltime kinds of the kernels: the per-depth double-square-root form
+// (t0sq, s2) or a one-way time table T(h, z) interpolated linearly in h.
+enum TravelKind : int32_t { TT_DSR = 0, TT_TABLE = 1 };
 
 // First index in sorted bin[0..n) whose value is >= key.
 __device__ __forceinline__ int64_t lower_bound_bin(const int32_t* __restrict__ bin, int64_t n, int32_t key) {
@@ -174,6 +184,50 @@ __device__ __forceinline__ Pair eval_pair(float A, float B, float hs2, float hr2
     return p;
 }
 
+// Table traveltimes.  A leg's place in the table: the time at horizontal
+// distance h = sqrt(h^2) is t[ih][iz] + f (t[ih + 1][iz] - t[ih][iz]) with
+// h / dh clamped to [0, n_h - 1] (beyond the table the last row holds); off
+// = ih * nz.  Infinite or NaN h^2 (padding) lands on the last row.
+struct TLeg {
+    int32_t off;
+    float f;
+};
+
+__device__ __forceinline__ TLeg table_leg(const Params& P, float h2) {
+    const float top = static_cast<float>(P.n_h - 1);
+    const float hf = fminf(__builtin_amdgcn_sqrtf(h2) * P.inv_dh, top);
+    const int ih = min(static_cast<int>(hf), P.n_h - 2);
+    TLeg L;
+    L.off = ih * P.nz;
+    L.f = hf - static_cast<float>(ih);
+    return L;
+}
+
+// Interpolated one-way time in float64: b - a of two adjacent float32 table
+// values is exact, the interpolation and the sum are float64, so the time
+// keeps the table's own precision (float32 rounding of the time in seconds
+// and again in samples would cost about 1e-5 of a band-limited result).
+__device__ __forceinline__ double table_time(const Params& P, TLeg L, int iz) {
+    const float a = P.ttab[L.off + iz], b = P.ttab[L.off + P.nz + iz];
+    return fma(static_cast<double>(L.f), static_cast<double>(b - a), static_cast<double>(a));
+}
+
+// The pair evaluation of eval_pair with table times (iz < nz; W = 1); the
+// clamp bounds are those of clamp_bounds.
+template <bool TF, bool CLAMP = true>
+__device__ __forceinline__ Pair eval_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz, float tf_off, float wlo,
+                                                float whi) {
+    (void)tf_off;
+    double w = (table_time(P, Ls, iz) + table_time(P, Lr, iz)) * P.inv_dt;
+    if (TF) w = w + P.tf_off_d;
+    if (CLAMP) w = fmin(fmax(w, static_cast<double>(wlo)), static_cast<double>(whi));
+    Pair p;
+    p.i = static_cast<int32_t>(w);
+    p.f = static_cast<float>(w - static_cast<double>(p.i));
+    p.r = 1.0f;
+    return p;
+}
+
 // Clamp bounds of eval_pair for a row of lt floats: reads at floor(w) and
 // floor(w) + 1 stay in [0, lt).  Without t_first the row pointer is advanced
 // by kLead and u >= 0 needs no lower clamp beyond 0.
@@ -212,7 +266,7 @@ struct ChunkTables {
     uint32_t clean;  // bit k: every lane of slot k is valid (wavefront-uniform)
 };
 
-template <int KS, int IL = 1>
+template <int KS, int IL = 1, int TT = TT_DSR>
 __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d, bool zero_weight_guard,
                                                   ChunkTables<KS>& T, float* sR) {
     const int lane = threadIdx.x & (kLanes - 1);
@@ -226,12 +280,19 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         float A = 1.0f, B = 0.0f, R = -1.0f;
         bool valid = false;
         if (iz < P.nz) {
-            const float t0 = P.t0sq[iz];
-            valid = !(zero_weight_guard && !(t0 > 0.0f));
-            if (valid) {
-                A = static_cast<float>(static_cast<double>(t0) * P.inv_dt2);
-                B = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);
+            if (TT == TT_TABLE) {
+                // table times carry no t0sq / s2; A, B are unused and W = 1
+                valid = true;
+                A = 0.0f;
                 R = P.r2[iz];
+            } else {
+                const float t0 = P.t0sq[iz];
+                valid = !(zero_weight_guard && !(t0 > 0.0f));
+                if (valid) {
+                    A = static_cast<float>(static_cast<double>(t0) * P.inv_dt2);
+                    B = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);
+                    R = P.r2[iz];
+                }
             }
         }
         T.A[k] = A;
@@ -244,6 +305,7 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         // A NaN (bad table) propagates and disables the unclamped path.
         float wk = 2.0f * 1.00001f + 1.0f;
         if (valid) wk = B >= 0.0f ? 2.0f * __builtin_amdgcn_sqrtf(fmaf(B, R, A)) * 1.00001f + 1.0f : __builtin_inff();
+        if (TT == TT_TABLE) wk = __builtin_inff();  // no bound known: always clamp
         wmax = (wk > wmax || wk != wk) ? wk : wmax;
         // min / max over the 16 lanes of the group (all groups hold the same depths)
         float lo = valid ? R : __builtin_inff();

@@ -59,9 +59,30 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
     acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
 }
 
+// mig_pair with table traveltimes (W = 1): iz0, iz1 are the lane's depths of
+// the two slots, clamped into the table.
+template <bool TF, bool MASKED>
+__device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz0, int iz1, float hm,
+                                               const float* row, float tfo, float wlo, float whi, float R0, float R1,
+                                               float& acc0, float& acc1) {
+    const Pair p0 = eval_pair_table<TF>(P, Ls, Lr, iz0, tfo, wlo, whi);
+    const Pair p1 = eval_pair_table<TF>(P, Ls, Lr, iz1, tfo, wlo, whi);
+    const float a0 = row[p0.i], b0 = row[p0.i + 1];
+    const float a1 = row[p1.i], b1 = row[p1.i + 1];
+    float v0 = fmaf(p0.f, b0 - a0, a0);
+    float v1 = fmaf(p1.f, b1 - a1, a1);
+    if (MASKED) {
+        v0 = (hm <= R0) ? v0 : 0.0f;
+        v1 = (hm <= R1) ? v1 : 0.0f;
+    }
+    acc0 += v0;
+    acc1 += v1;
+}
+
 // RREG: the masked slots take the lanes' aperture values from registers
 // (else from the LDS copy, which costs fewer registers).
-template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG>
+// TT: traveltime kind (TT_TABLE: one-way time table, W = 1).
+template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     const int lane = threadIdx.x & (kLanes - 1);
@@ -76,7 +97,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     float* sR = lds + P.tb * P.lt + 4 * P.tb;                              // [KS * 16]
 
     ChunkTables<KS> T;
-    load_chunk_tables<KS>(P, z0, d, WK == W_COSCOS, T, sR);
+    load_chunk_tables<KS, 1, TT>(P, z0, d, WK == W_COSCOS, T, sR);
 
     float px[CWQ], py[CWQ];
     int colv[CWQ];
@@ -147,7 +168,27 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     const float hmaxw = uniform_read(hmax4, tc);
                     uint64_t any, full;
                     slot_masks<KS>(T, hmin, hmaxw, any, full);
-                    if (any) {
+                    if (any && TT == TT_TABLE) {
+                        const float hm = fmaxf(hs2, hr2);
+                        const float* row = sTr + (t0 + tc) * P.lt + rowoff;
+                        const TLeg Ls = table_leg(P, hs2), Lr = table_leg(P, hr2);
+#pragma unroll
+                        for (int k = 0; k < KS; k += 2) {
+                            if ((any >> k) & 3ull) {
+                                const int iz0 = min(z0 + k * kGroup + d, P.nz - 1);
+                                const int iz1 = min(z0 + (k + 1) * kGroup + d, P.nz - 1);
+                                if (((full >> k) & 3ull) == 3ull) {
+                                    mig_pair_table<TF, false>(P, Ls, Lr, iz0, iz1, hm, row, tfo, wlo, whi, 0.0f, 0.0f,
+                                                              acc[q][k], acc[q][k + 1]);
+                                } else {
+                                    const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
+                                    const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
+                                    mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, row, tfo, wlo, whi, R0, R1,
+                                                             acc[q][k], acc[q][k + 1]);
+                                }
+                            }
+                        }
+                    } else if (any) {
                         const float hm = fmaxf(hs2, hr2);
                         const float* row = sTr + (t0 + tc) * P.lt + rowoff;
 #pragma unroll
@@ -217,10 +258,10 @@ __device__ __forceinline__ void zero_tile(const Params& P, int b, int tile, int 
     }
 }
 
-template <int NW, int CWQ, int KS, bool TF, int WK>
+template <int NW, int CWQ, int KS, bool TF, int WK, int TT = TT_DSR>
 __global__ __launch_bounds__(NW * 64) void migrate_kernel(Params P) {
     extern __shared__ float lds[];
-    migrate_tile<NW, CWQ, KS, TF, WK, true>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
+    migrate_tile<NW, CWQ, KS, TF, WK, true, TT>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched persistent form: work items (problem, bin, column tile, depth
@@ -256,6 +297,10 @@ template <int NW, int CWQ, int KS>
 static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
     dim3 grid(P.n_coltiles, P.n_zchunks, P.n_bins), block(NW * 64);
     const size_t lds = lds_bytes(P, KS);
+    if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
+        if (P.has_tf) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
+    }
     if (P.has_tf) {
         if (P.weight == W_COSCOS) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS>, grid, block, lds, s, P);
         return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT>, grid, block, lds, s, P);

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmWeight, check
+from ._lib import KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmTtable, KmWeight, check
 
 _DTYPES = {"f32": _lib.KM_F32, "bf16": _lib.KM_BF16, "f16": _lib.KM_F16}
 
@@ -49,6 +49,8 @@ class DeviceProblem:
     data: Optional[torch.Tensor] = None   # [n, n_t] float32, or int16 bit patterns of bf16 / f16
     scale: Optional[torch.Tensor] = None  # float32 [n] for 16-bit data
     dtype: str = "f32"
+    ttab: Optional[torch.Tensor] = None   # float32 [n_h, nz] one-way times: table traveltimes (W = 1)
+    tdh: float = 0.0
 
     @property
     def n_traces(self) -> int:
@@ -96,6 +98,10 @@ class DeviceProblem:
     def c_weight(self) -> KmWeight:
         return KmWeight(kind=int(self.weight))
 
+    def c_table(self) -> KmTtable:
+        assert self.ttab is not None and self.ttab.shape[1] == self.nz and self.ttab.is_contiguous()
+        return KmTtable(n_h=int(self.ttab.shape[0]), dh=float(self.tdh), t=_ptr(self.ttab), r2=_ptr(self.r2))
+
 
 def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DeviceProblem:
     """Copy a survey problem's inputs to the GPU in the ABI layouts.
@@ -117,6 +123,8 @@ def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DevicePr
                        bin=torch.as_tensor(np.ascontiguousarray(problem.bin, dtype=np.int32), device=dev),
                        x=f32(problem.x), y=f32(problem.y), t0sq=f32(problem.t0sq), s2=f32(problem.s2),
                        r2=f32(problem.r2))
+    if getattr(problem, "ttab", None) is not None:
+        dp = dataclasses.replace(dp, ttab=f32(problem.ttab), tdh=float(problem.tdh))
     d = problem.data if data is None else data
     if d is None:
         return dp
@@ -143,6 +151,11 @@ def migrate(dp: DeviceProblem, data: Optional[torch.Tensor] = None, image: Optio
     assert image.shape == dp.image_shape and image.dtype == torch.float32 and image.is_contiguous()
     tr = dp.c_traces(data, dtype if data is not None else None, scale)
     lib = _lib.load()
+    if dp.ttab is not None:
+        check(lib.kirchhoff_migrate_table(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_table()),
+                                          _ptr(image), int(accumulate), int(tile),
+                                          ctypes.c_void_p(_stream(dp.device))))
+        return image
     check(lib.kirchhoff_migrate(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
                                 ctypes.byref(dp.c_weight()), _ptr(image), int(accumulate), int(tile),
                                 ctypes.c_void_p(_stream(dp.device))))
@@ -159,6 +172,11 @@ def demigrate(dp: DeviceProblem, image: torch.Tensor, out: Optional[torch.Tensor
             out.zero_()
     tr = dp.c_traces(out, "f32")
     lib = _lib.load()
+    if dp.ttab is not None:
+        check(lib.kirchhoff_demigrate_table(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_table()),
+                                            ctypes.byref(tr), int(accumulate), int(tile),
+                                            ctypes.c_void_p(_stream(dp.device))))
+        return out
     check(lib.kirchhoff_demigrate(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
                                   ctypes.byref(dp.c_weight()), ctypes.byref(tr), int(accumulate), int(tile),
                                   ctypes.c_void_p(_stream(dp.device))))

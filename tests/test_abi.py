@@ -189,3 +189,23 @@ def test_trace_filter_rejects_bad_arguments(lib):
         assert lib.km_trace_filter(*args, None) == status, args
         assert msg in lib.km_last_error()
     assert lib.km_trace_filter(None, 10, None, 10, 0, 10, None, 3, 1, 0, None) == _lib.KM_OK
+
+
+def test_table_entry_points_reject_bad_tables(lib):
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib)
+    p = ctypes.c_void_p(0x1000)
+    for tab, msg in [(None, b"NULL"), (_lib.KmTtable(n_h=1, dh=10.0, t=p, r2=p), b"n_h"),
+                     (_lib.KmTtable(n_h=4, dh=0.0, t=p, r2=p), b"dh"),
+                     (_lib.KmTtable(n_h=4, dh=float("inf"), t=p, r2=p), b"dh"),
+                     (_lib.KmTtable(n_h=4, dh=10.0, t=None, r2=p), b"non-NULL"),
+                     (_lib.KmTtable(n_h=4, dh=10.0, t=ctypes.c_void_p(0x1002), r2=p), b"misaligned")]:
+        ref = ctypes.byref(tab) if tab is not None else None
+        assert lib.kirchhoff_migrate_table(ctypes.byref(t), ctypes.byref(g), ref, p, 0, -1, None) == _lib.KM_E_INVALID
+        assert msg in lib.km_last_error()
+        assert lib.kirchhoff_demigrate_table(p, ctypes.byref(g), ref, ctypes.byref(t), 0, -1, None) == \
+            _lib.KM_E_INVALID
+    big = _lib.KmTtable(n_h=1 << 30, dh=1.0, t=p, r2=p)
+    assert lib.kirchhoff_migrate_table(ctypes.byref(t), ctypes.byref(g), ctypes.byref(big), p, 0, -1, None) == \
+        _lib.KM_E_UNSUPPORTED
