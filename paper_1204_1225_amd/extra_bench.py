@@ -8,6 +8,9 @@ line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
 batch: 64 uneven 2D lines migrated by one persistent hipGraph-captured launch
     against 64 separate launches (same tile shape, chosen by the tuner on the
     largest line), images compared bit for bit.
+table: the 3D survey migrated and demigrated with curved-ray traveltime
+    tables (v = 1500 + 0.5 z, h every 10 m) instead of the RMS double square
+    root: throughput of both operators next to the table-gather rate.
 filter: the rho pre-filter (anti-causal derivative, 65 taps) forward and
     transposed over the 3D survey's 200 000 x 1500 traces: HBM bandwidth
     against 8 TB/s and the FP64 oracle timed on sampled traces.
@@ -195,7 +198,37 @@ def _filter(steps, warmup, dev):
             "gpu_traces_per_s": round(x.shape[0] / ms_f * 1e3, 1), "parity_sample_max_rel_err": err}
 
 
+def _table(steps, warmup, dev):
+    p = survey.make_survey3d(seed=2, device=dev)
+    pt = survey.with_curved_ray_table(p, dh=10.0)
+    dp = ops.to_device(pt, dev)
+    n_ap, _ = ops.count(dp)
+    img = torch.empty(dp.image_shape, device=dev)
+    out = torch.empty((dp.n_traces, dp.n_t), device=dev)
+    ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
+    ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
+    # minimal full-rate lane-ops per pair of the table evaluation once the legs are
+    # hoisted: per leg 2 widenings + 1 float64 FMA (6), sum + scale + 2 clamps (4),
+    # index, fraction and its narrowing (3), row address, interpolation (2) and
+    # accumulate (1) = 17; the pair also reads 4 table values (16 bytes) from L2
+    c_k = 17
+    peak = 256 * 64 * 2.4e9
+    dom = max(ms_m, ms_d)
+    return {"workload": "table", "metric": "G contributions/s (migrate, demigrate; curved-ray tables)",
+            "pairs_in_aperture": n_ap, "table_shape": list(pt.ttab.shape),
+            "ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
+            "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
+            "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
+            "roofline": {"bound": "alu", "achieved": round(n_ap * c_k / (dom * 1e-3) / 1e12, 3),
+                         "peak": round(peak / 1e12, 3), "unit": "TFLOP/s",
+                         "frac": round(n_ap * c_k / (dom * 1e-3) / peak, 4), "ops_per_pair": c_k,
+                         "kernel": "migrate" if ms_m >= ms_d else "demigrate",
+                         "table_gather_TBps": round(n_ap * 16 / (dom * 1e-3) / 1e12, 3)}}
+
+
 def run(workload, steps, warmup, dev):
+    if workload == "table":
+        return _table(steps, warmup, dev)
     if workload == "filter":
         return _filter(steps, warmup, dev)
     if workload == "cig":
