@@ -5,11 +5,11 @@
 // in registers; the traces of bin b stream through LDS in blocks of P.tb
 // zero-padded rows.  For every column group the wavefront computes the two
 // squared leg lengths of 16 traces at once (lane = (column, trace)), hands
-// them to the depth lanes through the LDS crossbar, derives from two ballots
-// which 16-depth slots can hold a pair inside the aperture and which need no
-// per-lane mask, and evaluates the slots two at a time: per lane two square
-// roots, the sample index and fraction, a two-sample LDS gather, the
-// interpolation and the weight.
+// them to the depth lanes through the LDS crossbar, derives from a ballot
+// which 16-depth slots can hold a pair inside the aperture, and evaluates
+// those slots two at a time: per lane two square roots, the sample index and
+// fraction, a two-sample LDS gather, the interpolation, the weight and the
+// lane's aperture mask.
 #include "km_kernels.h"
 
 namespace km {
@@ -125,8 +125,6 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     clamp_bounds<TF>(P.lt, wlo, whi);
     const float tfo = P.tf_off;
     const int rowoff = TF ? 0 : kLead;
-    // fully-inside slots need no clamp when no pair of the chunk can reach past the row
-    const bool noclamp = !TF && T.wmax <= whi;
 
     for (int64_t j0 = lo; j0 < hi; j0 += P.tb) {
         const int nb = static_cast<int>(min<int64_t>(P.tb, hi - j0));
@@ -168,6 +166,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     const float hmaxw = uniform_read(hmax4, tc);
                     uint64_t any, full;
                     slot_masks<KS>(T, hmin, hmaxw, any, full);
+                    (void)full;
                     if (any && TT == TT_TABLE) {
                         const float hm = fmaxf(hs2, hr2);
                         const float* row = sTr + (t0 + tc) * P.lt + rowoff;
@@ -177,38 +176,25 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                             if ((any >> k) & 3ull) {
                                 const int iz0 = min(z0 + k * kGroup + d, P.nz - 1);
                                 const int iz1 = min(z0 + (k + 1) * kGroup + d, P.nz - 1);
-                                if (((full >> k) & 3ull) == 3ull) {
-                                    mig_pair_table<TF, false>(P, Ls, Lr, iz0, iz1, hm, row, tfo, wlo, whi, 0.0f, 0.0f,
-                                                              acc[q][k], acc[q][k + 1]);
-                                } else {
-                                    const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
-                                    const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                    mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, row, tfo, wlo, whi, R0, R1,
-                                                             acc[q][k], acc[q][k + 1]);
-                                }
+                                const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
+                                const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
+                                mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, row, tfo, wlo, whi, R0, R1, acc[q][k],
+                                                         acc[q][k + 1]);
                             }
                         }
                     } else if (any) {
+                        // Every slot pair goes through the masked, clamped form: one code path
+                        // per pair measured faster than separate unmasked / unclamped variants
+                        // (their extra branches and code cost more than the masks they save).
                         const float hm = fmaxf(hs2, hr2);
                         const float* row = sTr + (t0 + tc) * P.lt + rowoff;
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
                             if ((any >> k) & 3ull) {
-                                if (((full >> k) & 3ull) == 3ull) {
-                                    if (noclamp)
-                                        mig_pair<TF, WK, false, false>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
-                                                                       row, tfo, wlo, whi, 0.0f, 0.0f, acc[q][k],
-                                                                       acc[q][k + 1]);
-                                    else
-                                        mig_pair<TF, WK, false, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
-                                                                      row, tfo, wlo, whi, 0.0f, 0.0f, acc[q][k],
-                                                                      acc[q][k + 1]);
-                                } else {
-                                    const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
-                                    const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                    mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
-                                                                 tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
-                                }
+                                const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
+                                const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
+                                mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                                             tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
                             }
                         }
                     }
