@@ -43,9 +43,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "a456c288b1826cebc5295d5c1ff4779d7f1bdd6d4347a575f044f6a4580dfe75",
-    "migrate": 1.7284e12,
-    "demigrate": 1.1173e12,
+    "sources_sha256": "aa4ec0e6eff65abcf593c9d00e5afd07c3e255b520f71bc4a6c2a1d48f523843",
+    "migrate": 1.7717e12,
+    "demigrate": 1.1155e12,
 }
 
 
