@@ -130,7 +130,7 @@ km::Params base_params(const km_traces* t, const km_grid* g, const km_traveltime
 
 // Traces per LDS block for a shape's budget; 0 if even one row does not fit.
 int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
-    const int64_t fixed = static_cast<int64_t>(16) * ks * 4;
+    const int64_t fixed = static_cast<int64_t>(16) * ks * 4 + (ks > 0 ? km::kBoxFloats * 4 : 0);
     const int64_t per = static_cast<int64_t>(lt) * row_bytes_per_sample + 16;
     int64_t tb = (budget - fixed) / per;
     if (tb < 1 && fixed + per <= kMaxLds) tb = 1;

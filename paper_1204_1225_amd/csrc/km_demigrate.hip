@@ -25,18 +25,6 @@ namespace km {
 // within the aperture and the LDS atomics of one instruction seldom share an address.
 constexpr int kIL = 2;
 
-__device__ __forceinline__ float wave_min(float v) {
-#pragma unroll
-    for (int off = 1; off < kLanes; off <<= 1) v = fminf(v, __shfl_xor(v, off, kLanes));
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
-__device__ __forceinline__ float wave_max(float v) {
-#pragma unroll
-    for (int off = 1; off < kLanes; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, kLanes));
-    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
-}
-
 // First and last index of v[0..n) with a <= v[i] <= b (compared in float64);
 // lo > hi when there is none.  Wavefront-uniform.
 __device__ __forceinline__ void index_range(const float* __restrict__ v, int n, double a, double b, int& lo, int& hi) {

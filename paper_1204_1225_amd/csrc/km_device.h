@@ -354,6 +354,26 @@ __device__ __forceinline__ float depth_factor(const Params& P, int iz) {
     return t0 > 0.0f ? static_cast<float>(static_cast<double>(t0) * P.wscale) : 0.0f;
 }
 
+// Wavefront minimum / maximum (every lane gets it, as a uniform value).
+__device__ __forceinline__ float wave_min(float v) {
+#pragma unroll
+    for (int off = 1; off < kLanes; off <<= 1) v = fminf(v, __shfl_xor(v, off, kLanes));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+__device__ __forceinline__ float wave_max(float v) {
+#pragma unroll
+    for (int off = 1; off < kLanes; off <<= 1) v = fmaxf(v, __shfl_xor(v, off, kLanes));
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
+// Squared distance from (x, y) to the box [x0, x1] x [y0, y1] (0 inside), float32.
+__device__ __forceinline__ float box_dist2(float x, float y, float x0, float x1, float y0, float y1) {
+    const float dx = fmaxf(fmaxf(x0 - x, x - x1), 0.0f);
+    const float dy = fmaxf(fmaxf(y0 - y, y - y1), 0.0f);
+    return dx * dx + dy * dy;
+}
+
 // v from lane `src` (any lane), through the LDS crossbar.
 __device__ __forceinline__ float lane_read(float v, int src) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));

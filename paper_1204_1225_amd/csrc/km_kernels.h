@@ -28,10 +28,13 @@ inline hipError_t launch_with_lds(Kernel kernel, dim3 grid, dim3 block, size_t l
     return hipGetLastError();
 }
 
-// LDS of a migrate / demigrate workgroup: the chunk's aperture table
-// (16 * ks floats), the staged geometry (4 floats per trace) and the rows.
+// LDS of a migrate workgroup: the chunk's aperture table (16 * ks floats),
+// the staged geometry (4 floats per trace), the rows, and the column tile's
+// bounding box (4 floats per wavefront, at most 16 wavefronts).
+constexpr int kBoxFloats = 64;
 inline size_t lds_bytes(const Params& P, int ks) {
-    return (static_cast<size_t>(16) * ks + static_cast<size_t>(4) * P.tb + static_cast<size_t>(P.tb) * P.lt) *
+    return (static_cast<size_t>(16) * ks + static_cast<size_t>(4) * P.tb + static_cast<size_t>(P.tb) * P.lt +
+            kBoxFloats) *
            sizeof(float);
 }
 

@@ -95,6 +95,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     float* sTr = lds;                                                      // [tb][lt]
     float4* sGeo = reinterpret_cast<float4*>(lds + P.tb * P.lt);           // [tb]
     float* sR = lds + P.tb * P.lt + 4 * P.tb;                              // [KS * 16]
+    float* sBox = sR + KS * kGroup;                                        // [NW][4]
 
     ChunkTables<KS> T;
     load_chunk_tables<KS, 1, TT>(P, z0, d, WK == W_COSCOS, T, sR);
@@ -126,12 +127,57 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     const float tfo = P.tf_off;
     const int rowoff = TF ? 0 : kLead;
 
+    // Bounding box of the tile's columns.  A leg longer than sqrt(r2)(1 + 2^-22)
+    // from every column cannot pass the float32 aperture test, so a trace whose
+    // source or receiver lies farther than that from the box (with a 1e-5
+    // margin on the squared radius) has no pair in this tile and depth chunk,
+    // and a block of such traces is neither staged nor evaluated.
+    {
+        float bx0 = __builtin_inff(), bx1 = -__builtin_inff(), by0 = __builtin_inff(), by1 = -__builtin_inff();
+#pragma unroll
+        for (int q = 0; q < CWQ; ++q) {
+            if (colv[q] < ncol) {
+                bx0 = fminf(bx0, px[q]);
+                bx1 = fmaxf(bx1, px[q]);
+                by0 = fminf(by0, py[q]);
+                by1 = fmaxf(by1, py[q]);
+            }
+        }
+        bx0 = wave_min(bx0);
+        bx1 = wave_max(bx1);
+        by0 = wave_min(by0);
+        by1 = wave_max(by1);
+        if (lane == 0) {
+            sBox[4 * wave] = bx0;
+            sBox[4 * wave + 1] = bx1;
+            sBox[4 * wave + 2] = by0;
+            sBox[4 * wave + 3] = by1;
+        }
+    }
+    __syncthreads();
+    float bx0 = sBox[0], bx1 = sBox[1], by0 = sBox[2], by1 = sBox[3];
+    for (int w = 1; w < NW; ++w) {
+        bx0 = fminf(bx0, sBox[4 * w]);
+        bx1 = fmaxf(bx1, sBox[4 * w + 1]);
+        by0 = fminf(by0, sBox[4 * w + 2]);
+        by1 = fmaxf(by1, sBox[4 * w + 3]);
+    }
+    const float reach = T.rmax * 1.00001f;
+
     for (int64_t j0 = lo; j0 < hi; j0 += P.tb) {
         const int nb = static_cast<int>(min<int64_t>(P.tb, hi - j0));
-        __syncthreads();
+        bool live = false;
+        if (T.rmax >= 0.0f) {
+            for (int t = threadIdx.x; t < nb; t += blockDim.x) {
+                const int64_t j = j0 + t;
+                live |= !(box_dist2(P.src[2 * j], P.src[2 * j + 1], bx0, bx1, by0, by1) > reach) &&
+                        !(box_dist2(P.rec[2 * j], P.rec[2 * j + 1], bx0, bx1, by0, by1) > reach);
+            }
+        }
+        // (also the barrier before the rows of the previous block are overwritten)
+        if (!__syncthreads_or(live)) continue;
         stage_block(P, j0, nb, sGeo, sTr);
         __syncthreads();
-        if (T.rmax < 0.0f) continue;
         for (int t0 = 0; t0 < nb; t0 += kGroup) {
             const int nbt = min(kGroup, nb - t0);
             // lane (g, d): legs of column group member g and trace t0 + d
