@@ -122,9 +122,6 @@ km::Params base_params(const km_traces* t, const km_grid* g, const km_traveltime
     P.image = image;
     P.accumulate = accumulate ? 1 : 0;
     P.lt = (t->n_samples + km::kLead + kTailPad + 3) / 4 * 4;
-    const uintptr_t base = reinterpret_cast<uintptr_t>(t->data);
-    P.vec_ok = t->dtype == KM_F32 ? (base % 16 == 0 && t->trace_stride % 4 == 0)
-                                  : (base % 8 == 0 && t->trace_stride % 4 == 0);
     return P;
 }
 
@@ -137,10 +134,26 @@ int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
     return static_cast<int>(std::min<int64_t>(tb, kMaxTracesPerBlock));
 }
 
+// Migrate blocks: at most kMigrateSlots traces, and the shape's LDS budget
+// less the fixed part for their time windows; at least one whole record
+// (samples -1 .. nt + 1) must fit.  Returns the window capacity in floats,
+// 0 if a record does not fit in LDS.
+constexpr int kMigrateSlots = 128;
+int migrate_window_capacity(int nt, int budget, int ks) {
+    const int64_t fixed = static_cast<int64_t>(km::migrate_lds_words(0, kMigrateSlots, ks));
+    int64_t cap = (budget / 4 - fixed) & ~int64_t{3};
+    const int64_t need = (static_cast<int64_t>(nt) + 3 + 3) & ~int64_t{3};
+    if (cap < need) cap = need;
+    if ((fixed + cap) * 4 > kMaxLds) return 0;
+    return static_cast<int>(cap);
+}
+
 km_status shape_params(int op, int shape, km::Params& P) {
     const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
     if (op == 0) {
-        P.tb = traces_per_block(P.lt, S.lds_budget, S.depth_slots, 4);
+        P.tb = kMigrateSlots;
+        P.cap = migrate_window_capacity(P.nt, S.lds_budget, S.depth_slots);
+        if (P.cap == 0) P.tb = 0;
     } else {
         // float64 rows; the four groups of a wavefront take four traces, so
         // whole quads of traces keep every group busy
@@ -212,6 +225,8 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
     if (st != KM_OK) return st;
     if (op == 1 && (P.n_traces + P.tb - 1) / P.tb > INT32_MAX)
         return fail(KM_E_UNSUPPORTED, "kirchhoff_demigrate: too many trace blocks");
+    if (op == 0 && P.n_traces > INT32_MAX)  // block slots record trace indices within a bin as int32
+        return fail(KM_E_UNSUPPORTED, "kirchhoff_migrate: more than 2^31 - 1 traces");
     hipError_t e = op == 0 ? km::launch_migrate(shape, P, s) : km::launch_demigrate(shape, P, s);
     if (e != hipSuccess) return hip_fail(e, op == 0 ? "migrate launch" : "demigrate launch");
     return KM_OK;
@@ -572,6 +587,8 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
     for (int i = 0; i < n; ++i) {
         P[i] = base_params(&probs[i].traces, &probs[i].grid, &probs[i].tt, &probs[i].weight, probs[i].image, 0);
         st = shape_params(0, shape, P[i]);
+        if (st == KM_OK && P[i].n_traces > INT32_MAX)
+            st = fail(KM_E_UNSUPPORTED, "km_batch_create: problem %d has more than 2^31 - 1 traces", i);
         if (st != KM_OK) {
             batch_free(B);
             return st;

@@ -57,11 +57,11 @@ struct Params {
     float* image;
     int32_t accumulate;
     // staging geometry
-    int32_t lt;       // LDS floats per staged row (multiple of 4, >= nt + kLead + 2)
-    int32_t tb;       // traces per LDS block
+    int32_t lt;       // demigrate: LDS row length (multiple of 4, >= nt + kLead + 2)
+    int32_t tb;       // traces per LDS block (migrate: at most)
+    int32_t cap;      // migrate: LDS floats for the staged time windows of a block
     int32_t n_zchunks;
     int32_t n_coltiles;
-    int32_t vec_ok;   // data base 16-byte aligned and stride a multiple of 4 elements (8 for 16-bit)
     // table traveltimes (used by the TABLE kernels instead of t0sq / s2)
     const float* ttab;  // [n_h][nz] one-way seconds at h = ih * dh
     int32_t n_h;
@@ -86,55 +86,6 @@ __device__ __forceinline__ int64_t lower_bound_bin(const int32_t* __restrict__ b
 
 __device__ __forceinline__ float widen16(uint32_t bits, int dtype) {
     return dtype == BF16 ? __uint_as_float(bits << 16) : __half2float(__ushort_as_half(static_cast<uint16_t>(bits)));
-}
-
-// Stage trace j into an LDS row of P.lt floats: row[kLead + k] = D_j[k]
-// (times the per-trace scale for 16-bit storage), zeros elsewhere.  All
-// threads of the block take part; `nthr` threads, this one is `tid`.
-__device__ __forceinline__ void stage_row(const Params& P, int64_t j, float* row, int tid, int nthr) {
-    const int nt = P.nt;
-    const float sc = (P.dtype != F32 && P.scale) ? P.scale[j] : 1.0f;
-    const int nq = P.lt >> 2;  // float4 quads in the row
-    float4* row4 = reinterpret_cast<float4*>(row);
-    if (P.vec_ok) {
-        // quad m holds samples 4m - kLead .. 4m - kLead + 3; kLead = 4 so quad m >= 1 is D[4(m-1)..]
-        for (int m = tid; m < nq; m += nthr) {
-            const int k0 = 4 * m - kLead;
-            float4 v = make_float4(0.f, 0.f, 0.f, 0.f);
-            if (k0 >= 0 && k0 + 3 < nt) {
-                if (P.dtype == F32) {
-                    v = *reinterpret_cast<const float4*>(static_cast<const float*>(P.data) + j * P.stride + k0);
-                } else {
-                    const uint2 w = *reinterpret_cast<const uint2*>(static_cast<const uint16_t*>(P.data) + j * P.stride + k0);
-                    v = make_float4(widen16(w.x & 0xFFFFu, P.dtype) * sc, widen16(w.x >> 16, P.dtype) * sc,
-                                    widen16(w.y & 0xFFFFu, P.dtype) * sc, widen16(w.y >> 16, P.dtype) * sc);
-                }
-            } else if (k0 >= 0 && k0 < nt) {
-                float e[4];
-#pragma unroll
-                for (int c = 0; c < 4; ++c) {
-                    const int k = k0 + c;
-                    e[c] = 0.0f;
-                    if (k < nt) {
-                        if (P.dtype == F32) e[c] = static_cast<const float*>(P.data)[j * P.stride + k];
-                        else e[c] = widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + k], P.dtype) * sc;
-                    }
-                }
-                v = make_float4(e[0], e[1], e[2], e[3]);
-            }
-            row4[m] = v;
-        }
-    } else {
-        for (int k = tid; k < P.lt; k += nthr) {
-            const int ks = k - kLead;
-            float v = 0.0f;
-            if (ks >= 0 && ks < nt) {
-                if (P.dtype == F32) v = static_cast<const float*>(P.data)[j * P.stride + ks];
-                else v = widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + ks], P.dtype) * sc;
-            }
-            row[k] = v;
-        }
-    }
 }
 
 // Horizontal squared leg lengths of a (column, trace) pair, float32 with the
@@ -354,6 +305,11 @@ __device__ __forceinline__ float depth_factor(const Params& P, int iz) {
     return t0 > 0.0f ? static_cast<float>(static_cast<double>(t0) * P.wscale) : 0.0f;
 }
 
+// A value that is equal in every lane, as a scalar register.
+__device__ __forceinline__ float uniform_f(float v) {
+    return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
+}
+
 // Wavefront minimum / maximum (every lane gets it, as a uniform value).
 __device__ __forceinline__ float wave_min(float v) {
 #pragma unroll
@@ -367,10 +323,18 @@ __device__ __forceinline__ float wave_max(float v) {
     return __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(v)));
 }
 
-// Squared distance from (x, y) to the box [x0, x1] x [y0, y1] (0 inside), float32.
+// Squared distance from (x, y) to the box [x0, x1] x [y0, y1] (0 inside), and
+// to its farthest point, float32.  Rounding is monotone, so for a column
+// (px, py) of the box legs() gives box_dist2 <= h^2 <= box_far2 exactly.
 __device__ __forceinline__ float box_dist2(float x, float y, float x0, float x1, float y0, float y1) {
     const float dx = fmaxf(fmaxf(x0 - x, x - x1), 0.0f);
     const float dy = fmaxf(fmaxf(y0 - y, y - y1), 0.0f);
+    return dx * dx + dy * dy;
+}
+
+__device__ __forceinline__ float box_far2(float x, float y, float x0, float x1, float y0, float y1) {
+    const float dx = fmaxf(fabsf(x0 - x), fabsf(x1 - x));
+    const float dy = fmaxf(fabsf(y0 - y), fabsf(y1 - y));
     return dx * dx + dy * dy;
 }
 

@@ -28,15 +28,18 @@ inline hipError_t launch_with_lds(Kernel kernel, dim3 grid, dim3 block, size_t l
     return hipGetLastError();
 }
 
-// LDS of a migrate workgroup: the chunk's aperture table (16 * ks floats),
-// the staged geometry (4 floats per trace), the rows, and the column tile's
-// bounding box (4 floats per wavefront, at most 16 wavefronts).
+// LDS of a migrate workgroup: the staged time windows (cap floats), per
+// block slot the trace geometry and window record (8 words), the chunk's
+// aperture table (16 * ks floats), the column tile's bounding box (4 floats
+// per wavefront, at most 16 wavefronts) and one pass's candidates (6 words
+// each, at most 64).
 constexpr int kBoxFloats = 64;
-inline size_t lds_bytes(const Params& P, int ks) {
-    return (static_cast<size_t>(16) * ks + static_cast<size_t>(4) * P.tb + static_cast<size_t>(P.tb) * P.lt +
-            kBoxFloats) *
-           sizeof(float);
+constexpr int kCandMax = 64;
+inline size_t migrate_lds_words(int cap, int tb, int ks) {
+    return static_cast<size_t>(cap) + static_cast<size_t>(8) * tb + static_cast<size_t>(16) * ks + kBoxFloats +
+           static_cast<size_t>(6) * kCandMax;
 }
+inline size_t lds_bytes(const Params& P, int ks) { return migrate_lds_words(P.cap, P.tb, ks) * sizeof(float); }
 
 // Demigrate workgroups keep their rows as float64 next to the staged geometry.
 inline size_t lds_bytes_f64rows(const Params& P) {

@@ -2,37 +2,42 @@
 //
 // Workgroup = (offset bin b, column tile, depth chunk).  Each wavefront keeps
 // CWQ groups of 4 image columns x (16 * KS) depths of float32 accumulators
-// in registers; the traces of bin b stream through LDS in blocks of P.tb
-// zero-padded rows.  For every column group the wavefront computes the two
-// squared leg lengths of 16 traces at once (lane = (column, trace)), hands
-// them to the depth lanes through the LDS crossbar, derives from a ballot
-// which 16-depth slots can hold a pair inside the aperture, and evaluates
-// those slots two at a time: per lane two square roots, the sample index and
-// fraction, a two-sample LDS gather, the interpolation, the weight and the
-// lane's aperture mask.
+// in registers; the traces of bin b stream through LDS in blocks.  A trace
+// enters a block only if it can have a pair inside the aperture of the tile
+// and chunk, and only the time window its pairs can read is staged (the
+// double-square-root time grows with the squared leg lengths, so the window
+// follows from the tile's bounding box and the chunk's tables).  For every
+// column group the wavefront computes the two squared leg lengths of 16
+// traces at once (lane = (column, trace)), hands them to the depth lanes
+// through the LDS crossbar, derives from a ballot which 16-depth slots can
+// hold a pair inside the aperture, and evaluates those slots two at a time:
+// per lane two square roots, the sample index and fraction, a two-sample LDS
+// gather, the interpolation, the weight and the lane's aperture mask.
 #include "km_kernels.h"
 
 namespace km {
 
-// Stage traces [j0, j0 + nb) of the sorted list into rows 0..tb-1 (rows past
-// nb are zero with far-away geometry).
-__device__ __forceinline__ void stage_block(const Params& P, int64_t j0, int nb, float4* sGeo, float* sTr) {
-    const int nthr = blockDim.x;
-    for (int t = threadIdx.x; t < P.tb; t += nthr) {
-        float4 g = make_float4(kFar, kFar, kFar, kFar);
-        if (t < nb) {
-            const int64_t j = j0 + t;
-            g = make_float4(P.src[2 * j], P.src[2 * j + 1], P.rec[2 * j], P.rec[2 * j + 1]);
+// Stage samples lo .. lo + len - 1 of trace j (zero outside [0, nt); times
+// the per-trace scale for 16-bit storage) into dst[0 .. len); one wavefront.
+__device__ __forceinline__ void stage_window(const Params& P, int64_t j, int lo, int len, float* dst, int lane) {
+    const int nt = P.nt;
+    const float sc = (P.dtype != F32 && P.scale) ? P.scale[j] : 1.0f;
+    for (int e0 = 0; e0 < len; e0 += 4 * kLanes) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            const int k = lo + e;
+            v[u] = 0.0f;
+            if (e < len && k >= 0 && k < nt) {
+                if (P.dtype == F32) v[u] = static_cast<const float*>(P.data)[j * P.stride + k];
+                else v[u] = widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + k], P.dtype) * sc;
+            }
         }
-        sGeo[t] = g;
-    }
-    for (int t = 0; t < P.tb; ++t) {
-        float* row = sTr + static_cast<int64_t>(t) * P.lt;
-        if (t < nb) {
-            stage_row(P, j0 + t, row, threadIdx.x, nthr);
-        } else {
-            float4* row4 = reinterpret_cast<float4*>(row);
-            for (int m = threadIdx.x; m < (P.lt >> 2); m += nthr) row4[m] = make_float4(0.f, 0.f, 0.f, 0.f);
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            if (e < len) dst[e] = v[u];
         }
     }
 }
@@ -82,20 +87,32 @@ __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr
 // RREG: the masked slots take the lanes' aperture values from registers
 // (else from the LDS copy, which costs fewer registers).
 // TT: traveltime kind (TT_TABLE: one-way time table, W = 1).
+//
+// LDS (lds_bytes): window storage [P.cap floats], per block slot the trace
+// geometry (float4) and (offset, first sample, last sample, trace - bin
+// start) (int4) [P.tb each], the aperture values [KS * 16], the tile box
+// [4 per wavefront] and the candidates of one pass [NW * 4 x (int2, float4)].
 template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
+    constexpr int NG = NW * kGroupsPerWave;  // candidate traces per pass: one per 16-lane group
+    static_assert(NG <= kLanes && NW <= kBoxFloats / 4, "at most 16 wavefronts");
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = threadIdx.x / kLanes;
     const int g = lane / kGroup, d = lane % kGroup;
     const int ncol = P.nx * P.ny;
     const int z0 = zc * KS * kGroup;
+    const int nt = P.nt;
+    // staged-row index of sample k is k + koff (eval_pair adds kLead with t_first)
+    const int koff = TF ? kLead : 0;
 
-    // LDS: rows first, so that a row's lead pad folds into the gather's offset field
-    float* sTr = lds;                                                      // [tb][lt]
-    float4* sGeo = reinterpret_cast<float4*>(lds + P.tb * P.lt);           // [tb]
-    float* sR = lds + P.tb * P.lt + 4 * P.tb;                              // [KS * 16]
-    float* sBox = sR + KS * kGroup;                                        // [NW][4]
+    float* sTr = lds;                                                    // [cap]
+    float4* sGeo = reinterpret_cast<float4*>(lds + P.cap);               // [tb]
+    int4* sMeta = reinterpret_cast<int4*>(lds + P.cap + 4 * P.tb);       // [tb]
+    float* sR = lds + P.cap + 8 * P.tb;                                  // [KS * 16]
+    float* sBox = sR + KS * kGroup;                                      // [kBoxFloats]
+    int2* sCand = reinterpret_cast<int2*>(sBox + kBoxFloats);            // [kCandMax]
+    float4* sCandGeo = reinterpret_cast<float4*>(sBox + kBoxFloats + 2 * kCandMax);  // [kCandMax]
 
     ChunkTables<KS> T;
     load_chunk_tables<KS, 1, TT>(P, z0, d, WK == W_COSCOS, T, sR);
@@ -122,16 +139,12 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
 
     const int64_t lo = lower_bound_bin(P.bin, P.n_traces, b);
     const int64_t hi = lower_bound_bin(P.bin, P.n_traces, b + 1);
-    float wlo, whi;
-    clamp_bounds<TF>(P.lt, wlo, whi);
     const float tfo = P.tf_off;
-    const int rowoff = TF ? 0 : kLead;
 
     // Bounding box of the tile's columns.  A leg longer than sqrt(r2)(1 + 2^-22)
     // from every column cannot pass the float32 aperture test, so a trace whose
     // source or receiver lies farther than that from the box (with a 1e-5
-    // margin on the squared radius) has no pair in this tile and depth chunk,
-    // and a block of such traces is neither staged nor evaluated.
+    // margin on the squared radius) has no pair in this tile and depth chunk.
     {
         float bx0 = __builtin_inff(), bx1 = -__builtin_inff(), by0 = __builtin_inff(), by1 = -__builtin_inff();
 #pragma unroll
@@ -162,26 +175,144 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         by0 = fminf(by0, sBox[4 * w + 2]);
         by1 = fmaxf(by1, sBox[4 * w + 3]);
     }
-    const float reach = T.rmax * 1.00001f;
+    // wavefront-uniform: kept in scalar registers
+    bx0 = uniform_f(bx0);
+    bx1 = uniform_f(bx1);
+    by0 = uniform_f(by0);
+    by1 = uniform_f(by1);
+    const float reach = uniform_f(T.rmax * 1.00001f);
 
-    for (int64_t j0 = lo; j0 < hi; j0 += P.tb) {
-        const int nb = static_cast<int>(min<int64_t>(P.tb, hi - j0));
-        bool live = false;
-        if (T.rmax >= 0.0f) {
-            for (int t = threadIdx.x; t < nb; t += blockDim.x) {
-                const int64_t j = j0 + t;
-                live |= !(box_dist2(P.src[2 * j], P.src[2 * j + 1], bx0, bx1, by0, by1) > reach) &&
-                        !(box_dist2(P.rec[2 * j], P.rec[2 * j + 1], bx0, bx1, by0, by1) > reach);
+    // Windows need a time that does not decrease with the squared leg length:
+    // B >= 0 on every depth that can be inside the aperture (else, and for
+    // table times, the whole record is staged).
+    bool mono_lane = true;
+#pragma unroll
+    for (int k = 0; k < KS; ++k) mono_lane = mono_lane && (!(T.R[k] >= 0.0f) || T.B[k] >= 0.0f);
+    const bool windows = TT == TT_DSR && __builtin_amdgcn_ballot_w64(!mono_lane) == 0;
+    const int first_lo = TF ? -1 : 0;  // lowest staged sample (t_first = 0 gives u >= 0)
+
+    int64_t jn = (T.rmax >= 0.0f) ? lo : hi;
+    while (jn < hi) {
+        // ---- Build a block: passes of NG candidates; candidate gi is trace jn + gi,
+        // evaluated by the 16 lanes of group gi.  Its window [wl, wl + len) of
+        // samples covers, with a 2-sample margin, every time of a pair inside the
+        // aperture: over the chunk's depths that can hold such a pair, the time at
+        // the box's nearest distances bounds it from below, the time at the
+        // farthest distances (capped at the depth's aperture) from above.
+        int nb = 0, used = 0;
+        for (;;) {
+            const int gi = wave * kGroupsPerWave + g;
+            const int64_t j = jn + gi;
+            int wl = 0, len = 0;
+            float4 sr = make_float4(kFar, kFar, kFar, kFar);
+            if (j < hi) {
+                sr = make_float4(P.src[2 * j], P.src[2 * j + 1], P.rec[2 * j], P.rec[2 * j + 1]);
+                const float ls = box_dist2(sr.x, sr.y, bx0, bx1, by0, by1);
+                const float lr = box_dist2(sr.z, sr.w, bx0, bx1, by0, by1);
+                const float m = fmaxf(ls, lr);
+                if (m <= reach) {
+                    wl = first_lo;
+                    len = nt + 2 - first_lo;  // samples first_lo .. nt + 1
+                    if (windows) {
+                        const float ms = box_far2(sr.x, sr.y, bx0, bx1, by0, by1);
+                        const float mr = box_far2(sr.z, sr.w, bx0, bx1, by0, by1);
+                        float umin = __builtin_inff(), umax = -__builtin_inff();
+                        bool any = false, bad = false;
+#pragma unroll
+                        for (int k = 0; k < KS; ++k) {
+                            const float R = RREG ? T.R[k] : sR[k * kGroup + d];
+                            if (m <= R) {
+                                const float a = __builtin_amdgcn_sqrtf(fmaf(T.B[k], ls, T.A[k])) +
+                                                __builtin_amdgcn_sqrtf(fmaf(T.B[k], lr, T.A[k]));
+                                const float c = __builtin_amdgcn_sqrtf(fmaf(T.B[k], fminf(ms, R), T.A[k])) +
+                                                __builtin_amdgcn_sqrtf(fmaf(T.B[k], fminf(mr, R), T.A[k]));
+                                any = true;
+                                bad = bad || !(a == a && c == c);
+                                umin = fminf(umin, a);
+                                umax = fmaxf(umax, c);
+                            }
+                        }
+#pragma unroll
+                        for (int off = 1; off < kGroup; off <<= 1) {
+                            umin = fminf(umin, __shfl_xor(umin, off, kLanes));
+                            umax = fmaxf(umax, __shfl_xor(umax, off, kLanes));
+                        }
+                        const uint32_t gany = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(any) >> (kGroup * g)) & 0xFFFFu;
+                        const uint32_t gbad = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(bad) >> (kGroup * g)) & 0xFFFFu;
+                        if (!gany) {
+                            len = 0;  // no depth of the chunk can hold a pair
+                        } else if (!gbad) {
+                            if (TF) {
+                                umin = umin + tfo;
+                                umax = umax + tfo;
+                            }
+                            // sample indices, clamped before conversion
+                            const float cl = static_cast<float>(nt + 8);
+                            const int s0 = static_cast<int>(floorf(fminf(fmaxf(umin, -8.0f), cl))) - koff - 2;
+                            const int s1 = static_cast<int>(floorf(fminf(fmaxf(umax, -8.0f), cl))) - koff + 3;
+                            if (s0 > nt - 1 || s1 < 0) {
+                                len = 0;  // every such time reads zeros: nothing to add
+                            } else {
+                                wl = max(s0, first_lo);
+                                len = max(min(s1, nt + 1) - wl + 1, 2);
+                            }
+                        }
+                    }
+                }
             }
+            __syncthreads();  // the previous pass (or block) is done with the candidates and rows
+            if (d == 0) {
+                sCand[gi] = make_int2(wl, len);
+                sCandGeo[gi] = sr;
+            }
+            __syncthreads();
+            // Every wavefront takes the same decision: candidates 0 .. k - 1 join the
+            // block (the others do not fit and open the next one).
+            int clen = 0;
+            if (lane < NG) clen = sCand[lane].y;
+            int plen = clen, pcnt = clen > 0 ? 1 : 0;  // inclusive prefix sums
+#pragma unroll
+            for (int off = 1; off < NG; off <<= 1) {
+                const int tl = __shfl_up(plen, off, kLanes), tc = __shfl_up(pcnt, off, kLanes);
+                if (lane >= off) {
+                    plen += tl;
+                    pcnt += tc;
+                }
+            }
+            const bool fits = used + plen <= P.cap && nb + pcnt <= P.tb;
+            const uint64_t nofit = __builtin_amdgcn_ballot_w64(lane < NG && !fits);
+            const int k = nofit ? static_cast<int>(__builtin_ctzll(nofit)) : NG;
+            if (wave == 0 && lane < k && clen > 0) {
+                const int slot = nb + pcnt - 1;
+                const int cwl = sCand[lane].x;
+                sGeo[slot] = sCandGeo[lane];
+                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + clen - 1, static_cast<int>(jn + lane - lo));
+            }
+            if (k > 0) {
+                nb += __builtin_amdgcn_readlane(pcnt, k - 1);
+                used += __builtin_amdgcn_readlane(plen, k - 1);
+            }
+            jn += k;
+            if (k < NG || jn >= hi) break;
         }
-        // (also the barrier before the rows of the previous block are overwritten)
-        if (!__syncthreads_or(live)) continue;
-        stage_block(P, j0, nb, sGeo, sTr);
+        if (nb == 0) continue;  // only when the bin is exhausted
+        __syncthreads();        // the block's slots
+        for (int t = wave; t < nb; t += NW) {
+            const int4 mt = sMeta[t];
+            stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, sTr + mt.x, lane);
+        }
         __syncthreads();
+
         for (int t0 = 0; t0 < nb; t0 += kGroup) {
             const int nbt = min(kGroup, nb - t0);
-            // lane (g, d): legs of column group member g and trace t0 + d
-            const float4 sr = sGeo[min(t0 + d, P.tb - 1)];
+            // lane (g, d): legs of column group member g and trace t0 + d; the
+            // trace's row offset and clamp bounds (window samples wl .. wh)
+            const int ts = min(t0 + d, nb - 1);
+            const float4 sr = sGeo[ts];
+            const int4 mt = sMeta[ts];
+            const int lrow = mt.x - mt.y - koff;
+            const float lwlo = static_cast<float>(mt.y + koff);
+            const float lwhi = static_cast<float>(mt.z - 1 + koff);
 #pragma unroll
             for (int q = 0; q < CWQ; ++q) {
                 const Legs Lp = legs(px[q], py[q], sr);
@@ -213,9 +344,14 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     uint64_t any, full;
                     slot_masks<KS>(T, hmin, hmaxw, any, full);
                     (void)full;
-                    if (any && TT == TT_TABLE) {
-                        const float hm = fmaxf(hs2, hr2);
-                        const float* row = sTr + (t0 + tc) * P.lt + rowoff;
+                    if (!any) {
+                        if (!more) break;
+                        continue;
+                    }
+                    const float* row = sTr + __builtin_amdgcn_readlane(lrow, tc);
+                    const float wlo = uniform_read(lwlo, tc), whi = uniform_read(lwhi, tc);
+                    const float hm = fmaxf(hs2, hr2);
+                    if (TT == TT_TABLE) {
                         const TLeg Ls = table_leg(P, hs2), Lr = table_leg(P, hr2);
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
@@ -228,12 +364,10 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                                          acc[q][k + 1]);
                             }
                         }
-                    } else if (any) {
+                    } else {
                         // Every slot pair goes through the masked, clamped form: one code path
                         // per pair measured faster than separate unmasked / unclamped variants
                         // (their extra branches and code cost more than the masks they save).
-                        const float hm = fmaxf(hs2, hr2);
-                        const float* row = sTr + (t0 + tc) * P.lt + rowoff;
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
                             if ((any >> k) & 3ull) {
