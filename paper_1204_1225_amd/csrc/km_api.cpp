@@ -135,25 +135,29 @@ int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
 }
 
 // Migrate blocks: at most kMigrateSlots traces, and the shape's LDS budget
-// less the fixed part for their time windows; at least one whole record
-// (samples -1 .. nt + 1) must fit.  Returns the window capacity in floats,
-// 0 if a record does not fit in LDS.
+// less the fixed part for their time windows (2 floats per staged sample);
+// at least one whole record (samples -1 .. nt + 1) must fit, with fewer
+// slots for the longest records.  Sets P.tb and P.cap (floats); false if a
+// record does not fit in LDS.
 constexpr int kMigrateSlots = 128;
-int migrate_window_capacity(int nt, int budget, int ks) {
-    const int64_t fixed = static_cast<int64_t>(km::migrate_lds_words(0, kMigrateSlots, ks));
-    int64_t cap = (budget / 4 - fixed) & ~int64_t{3};
-    const int64_t need = (static_cast<int64_t>(nt) + 3 + 3) & ~int64_t{3};
-    if (cap < need) cap = need;
-    if ((fixed + cap) * 4 > kMaxLds) return 0;
-    return static_cast<int>(cap);
+bool migrate_block_params(km::Params& P, int budget, int ks) {
+    const int64_t need = (2 * (static_cast<int64_t>(P.nt) + 2) + 3) & ~int64_t{3};
+    for (int tb = kMigrateSlots; tb >= 1; tb /= 2) {
+        const int64_t fixed = static_cast<int64_t>(km::migrate_lds_words(0, tb, ks));
+        const int64_t cap = std::max<int64_t>((budget / 4 - fixed) & ~int64_t{3}, need);
+        if ((fixed + cap) * 4 <= kMaxLds) {
+            P.tb = tb;
+            P.cap = static_cast<int>(cap);
+            return true;
+        }
+    }
+    return false;
 }
 
 km_status shape_params(int op, int shape, km::Params& P) {
     const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
     if (op == 0) {
-        P.tb = kMigrateSlots;
-        P.cap = migrate_window_capacity(P.nt, S.lds_budget, S.depth_slots);
-        if (P.cap == 0) P.tb = 0;
+        if (!migrate_block_params(P, S.lds_budget, S.depth_slots)) P.tb = 0;
     } else {
         // float64 rows; the four groups of a wavefront take four traces, so
         // whole quads of traces keep every group busy

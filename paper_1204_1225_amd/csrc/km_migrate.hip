@@ -17,27 +17,35 @@
 
 namespace km {
 
-// Stage samples lo .. lo + len - 1 of trace j (zero outside [0, nt); times
-// the per-trace scale for 16-bit storage) into dst[0 .. len); one wavefront.
-__device__ __forceinline__ void stage_window(const Params& P, int64_t j, int lo, int len, float* dst, int lane) {
-    const int nt = P.nt;
+// Sample k of trace j: zero outside [0, nt), times the per-trace scale for
+// 16-bit storage.
+__device__ __forceinline__ float trace_sample(const Params& P, int64_t j, int k, float sc) {
+    if (k < 0 || k >= P.nt) return 0.0f;
+    if (P.dtype == F32) return static_cast<const float*>(P.data)[j * P.stride + k];
+    return widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + k], P.dtype) * sc;
+}
+
+// Stage the window of samples lo .. lo + len - 1 of trace j as len - 1 pairs
+// dst[e] = (D[lo + e], D[lo + e + 1] - D[lo + e]): the interpolation then
+// reads one pair and needs one FMA.  One wavefront.
+__device__ __forceinline__ void stage_window(const Params& P, int64_t j, int lo, int len, float2* dst, int lane) {
     const float sc = (P.dtype != F32 && P.scale) ? P.scale[j] : 1.0f;
-    for (int e0 = 0; e0 < len; e0 += 4 * kLanes) {
-        float v[4];
+    for (int e0 = 0; e0 < len - 1; e0 += 2 * kLanes) {
+        float a[2], b[2];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
             const int e = e0 + u * kLanes + lane;
-            const int k = lo + e;
-            v[u] = 0.0f;
-            if (e < len && k >= 0 && k < nt) {
-                if (P.dtype == F32) v[u] = static_cast<const float*>(P.data)[j * P.stride + k];
-                else v[u] = widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + k], P.dtype) * sc;
+            a[u] = 0.0f;
+            b[u] = 0.0f;
+            if (e < len - 1) {
+                a[u] = trace_sample(P, j, lo + e, sc);
+                b[u] = trace_sample(P, j, lo + e + 1, sc);
             }
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < 2; ++u) {
             const int e = e0 + u * kLanes + lane;
-            if (e < len) dst[e] = v[u];
+            if (e < len - 1) dst[e] = make_float2(a[u], b[u] - a[u]);
         }
     }
 }
@@ -46,16 +54,17 @@ __device__ __forceinline__ void stage_window(const Params& P, int64_t j, int lo,
 // valid lane may be outside the aperture, so each value is kept only where
 // hmax <= the lane's aperture value; CLAMP: the time is clamped to the row.
 // R0, R1: the lanes' aperture values of the two slots (read only when MASKED).
+// row[i] = (D[i], D[i + 1] - D[i]) of the staged window.
 template <bool TF, int WK, bool MASKED, bool CLAMP>
 __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
-                                         const float* row, float tfo, float wlo, float whi, float R0, float R1,
+                                         const float2* row, float tfo, float wlo, float whi, float R0, float R1,
                                          float& acc0, float& acc1) {
     const Pair p0 = eval_pair<TF, WK, CLAMP>(A0, B0, hs2, hr2, tfo, wlo, whi);
     const Pair p1 = eval_pair<TF, WK, CLAMP>(A1, B1, hs2, hr2, tfo, wlo, whi);
-    const float a0 = row[p0.i], b0 = row[p0.i + 1];
-    const float a1 = row[p1.i], b1 = row[p1.i + 1];
-    float v0 = fmaf(p0.f, b0 - a0, a0);
-    float v1 = fmaf(p1.f, b1 - a1, a1);
+    const float2 e0 = row[p0.i];
+    const float2 e1 = row[p1.i];
+    float v0 = fmaf(p0.f, e0.y, e0.x);
+    float v1 = fmaf(p1.f, e1.y, e1.x);
     if (MASKED) {
         v0 = (hm <= R0) ? v0 : 0.0f;
         v1 = (hm <= R1) ? v1 : 0.0f;
@@ -68,14 +77,14 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
 // the two slots, clamped into the table.
 template <bool TF, bool MASKED>
 __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz0, int iz1, float hm,
-                                               const float* row, float tfo, float wlo, float whi, float R0, float R1,
+                                               const float2* row, float tfo, float wlo, float whi, float R0, float R1,
                                                float& acc0, float& acc1) {
     const Pair p0 = eval_pair_table<TF>(P, Ls, Lr, iz0, tfo, wlo, whi);
     const Pair p1 = eval_pair_table<TF>(P, Ls, Lr, iz1, tfo, wlo, whi);
-    const float a0 = row[p0.i], b0 = row[p0.i + 1];
-    const float a1 = row[p1.i], b1 = row[p1.i + 1];
-    float v0 = fmaf(p0.f, b0 - a0, a0);
-    float v1 = fmaf(p1.f, b1 - a1, a1);
+    const float2 e0 = row[p0.i];
+    const float2 e1 = row[p1.i];
+    float v0 = fmaf(p0.f, e0.y, e0.x);
+    float v1 = fmaf(p1.f, e1.y, e1.x);
     if (MASKED) {
         v0 = (hm <= R0) ? v0 : 0.0f;
         v1 = (hm <= R1) ? v1 : 0.0f;
@@ -88,9 +97,9 @@ __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr
 // (else from the LDS copy, which costs fewer registers).
 // TT: traveltime kind (TT_TABLE: one-way time table, W = 1).
 //
-// LDS (lds_bytes): window storage [P.cap floats], per block slot the trace
-// geometry (float4) and (offset, first sample, last sample, trace - bin
-// start) (int4) [P.tb each], the aperture values [KS * 16], the tile box
+// LDS (lds_bytes): window storage [P.cap floats; a window of n samples takes
+// n - 1 pairs], per block slot the trace geometry (float4) and (float offset,
+// first sample, last sample, trace - bin start) (int4) [P.tb each], the aperture values [KS * 16], the tile box
 // [4 per wavefront] and the candidates of one pass [NW * 4 x (int2, float4)].
 template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
@@ -268,8 +277,12 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             __syncthreads();
             // Every wavefront takes the same decision: candidates 0 .. k - 1 join the
             // block (the others do not fit and open the next one).
-            int clen = 0;
-            if (lane < NG) clen = sCand[lane].y;
+            int clen = 0, cwl = 0;  // LDS floats of the candidate's window
+            if (lane < NG) {
+                const int2 c = sCand[lane];
+                cwl = c.x;
+                clen = c.y > 0 ? 2 * (c.y - 1) : 0;
+            }
             int plen = clen, pcnt = clen > 0 ? 1 : 0;  // inclusive prefix sums
 #pragma unroll
             for (int off = 1; off < NG; off <<= 1) {
@@ -284,9 +297,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             const int k = nofit ? static_cast<int>(__builtin_ctzll(nofit)) : NG;
             if (wave == 0 && lane < k && clen > 0) {
                 const int slot = nb + pcnt - 1;
-                const int cwl = sCand[lane].x;
                 sGeo[slot] = sCandGeo[lane];
-                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + clen - 1, static_cast<int>(jn + lane - lo));
+                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + clen / 2, static_cast<int>(jn + lane - lo));
             }
             if (k > 0) {
                 nb += __builtin_amdgcn_readlane(pcnt, k - 1);
@@ -299,7 +311,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         __syncthreads();        // the block's slots
         for (int t = wave; t < nb; t += NW) {
             const int4 mt = sMeta[t];
-            stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, sTr + mt.x, lane);
+            stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<float2*>(sTr + mt.x), lane);
         }
         __syncthreads();
 
@@ -310,7 +322,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             const int ts = min(t0 + d, nb - 1);
             const float4 sr = sGeo[ts];
             const int4 mt = sMeta[ts];
-            const int lrow = mt.x - mt.y - koff;
+            const int lrow = mt.x / 2 - mt.y - koff;  // in pairs
             const float lwlo = static_cast<float>(mt.y + koff);
             const float lwhi = static_cast<float>(mt.z - 1 + koff);
 #pragma unroll
@@ -327,17 +339,21 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                 // next live trace's are requested before trace t is evaluated.
                 int t = __builtin_ctzll(live);
                 live &= live - 1;
+                // (The upper clamp bound also comes through the crossbar, as a vector
+                // register: a clamp with two scalar bounds costs a move per pair.)
                 float hs2n = lane_read(Lp.hs2, (lane & ~(kGroup - 1)) | t);
                 float hr2n = lane_read(Lp.hr2, (lane & ~(kGroup - 1)) | t);
+                float whin = lane_read(lwhi, t);
                 for (;;) {
                     const int tc = t;
-                    const float hs2 = hs2n, hr2 = hr2n;
+                    const float hs2 = hs2n, hr2 = hr2n, whi = whin;
                     const bool more = live != 0;
                     if (more) {
                         t = __builtin_ctzll(live);
                         live &= live - 1;
                         hs2n = lane_read(Lp.hs2, (lane & ~(kGroup - 1)) | t);
                         hr2n = lane_read(Lp.hr2, (lane & ~(kGroup - 1)) | t);
+                        whin = lane_read(lwhi, t);
                     }
                     const float hmin = uniform_read(hmin4, tc);
                     const float hmaxw = uniform_read(hmax4, tc);
@@ -348,9 +364,11 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                         if (!more) break;
                         continue;
                     }
-                    const float* row = sTr + __builtin_amdgcn_readlane(lrow, tc);
-                    const float wlo = uniform_read(lwlo, tc), whi = uniform_read(lwhi, tc);
-                    const float hm = fmaxf(hs2, hr2);
+                    const float2* row = reinterpret_cast<const float2*>(sTr) + __builtin_amdgcn_readlane(lrow, tc);
+                    const float wlo = uniform_read(lwlo, tc);
+                    // max(hs2, hr2): one v_max (fmaxf would first quiet both inputs)
+                    float hm;
+                    asm("v_max_f32 %0, %1, %2" : "=v"(hm) : "v"(hs2), "v"(hr2));
                     if (TT == TT_TABLE) {
                         const TLeg Ls = table_leg(P, hs2), Lr = table_leg(P, hr2);
 #pragma unroll
