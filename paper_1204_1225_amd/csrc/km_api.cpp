@@ -135,13 +135,15 @@ int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
 }
 
 // Migrate blocks: at most kMigrateSlots traces, and the shape's LDS budget
-// less the fixed part for their time windows (2 floats per staged sample);
+// less the fixed part for their time windows (2 floats per staged sample, 1
+// for table traveltimes);
 // at least one whole record (samples -1 .. nt + 1) must fit, with fewer
 // slots for the longest records.  Sets P.tb and P.cap (floats); false if a
 // record does not fit in LDS.
 constexpr int kMigrateSlots = 128;
 bool migrate_block_params(km::Params& P, int budget, int ks) {
-    const int64_t need = (2 * (static_cast<int64_t>(P.nt) + 2) + 3) & ~int64_t{3};
+    // square-root times stage (sample, difference) pairs, table times samples
+    const int64_t need = (P.ttab ? static_cast<int64_t>(P.nt) + 3 : 2 * (static_cast<int64_t>(P.nt) + 2)) + 3 & ~int64_t{3};
     for (int tb = kMigrateSlots; tb >= 1; tb /= 2) {
         const int64_t fixed = static_cast<int64_t>(km::migrate_lds_words(0, tb, ks));
         const int64_t cap = std::max<int64_t>((budget / 4 - fixed) & ~int64_t{3}, need);

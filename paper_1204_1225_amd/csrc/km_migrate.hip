@@ -25,6 +25,25 @@ __device__ __forceinline__ float trace_sample(const Params& P, int64_t j, int k,
     return widen16(static_cast<const uint16_t*>(P.data)[j * P.stride + k], P.dtype) * sc;
 }
 
+// Stage the window of samples lo .. lo + len - 1 of trace j as len floats
+// (the whole-record windows of table traveltimes).  One wavefront.
+__device__ __forceinline__ void stage_window_f(const Params& P, int64_t j, int lo, int len, float* dst, int lane) {
+    const float sc = (P.dtype != F32 && P.scale) ? P.scale[j] : 1.0f;
+    for (int e0 = 0; e0 < len; e0 += 4 * kLanes) {
+        float v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            v[u] = e < len ? trace_sample(P, j, lo + e, sc) : 0.0f;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            if (e < len) dst[e] = v[u];
+        }
+    }
+}
+
 // Stage the window of samples lo .. lo + len - 1 of trace j as len - 1 pairs
 // dst[e] = (D[lo + e], D[lo + e + 1] - D[lo + e]): the interpolation then
 // reads one pair and needs one FMA.  One wavefront.
@@ -77,14 +96,14 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
 // the two slots, clamped into the table.
 template <bool TF, bool MASKED>
 __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz0, int iz1, float hm,
-                                               const float2* row, float tfo, float wlo, float whi, float R0, float R1,
+                                               const float* row, float tfo, float wlo, float whi, float R0, float R1,
                                                float& acc0, float& acc1) {
     const Pair p0 = eval_pair_table<TF>(P, Ls, Lr, iz0, tfo, wlo, whi);
     const Pair p1 = eval_pair_table<TF>(P, Ls, Lr, iz1, tfo, wlo, whi);
-    const float2 e0 = row[p0.i];
-    const float2 e1 = row[p1.i];
-    float v0 = fmaf(p0.f, e0.y, e0.x);
-    float v1 = fmaf(p1.f, e1.y, e1.x);
+    const float a0 = row[p0.i], b0 = row[p0.i + 1];
+    const float a1 = row[p1.i], b1 = row[p1.i + 1];
+    float v0 = fmaf(p0.f, b0 - a0, a0);
+    float v1 = fmaf(p1.f, b1 - a1, a1);
     if (MASKED) {
         v0 = (hm <= R0) ? v0 : 0.0f;
         v1 = (hm <= R1) ? v1 : 0.0f;
@@ -114,6 +133,10 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     const int nt = P.nt;
     // staged-row index of sample k is k + koff (eval_pair adds kLead with t_first)
     const int koff = TF ? kLead : 0;
+    // staged form: (sample, difference) pairs for the square-root times (windows
+    // of a few hundred samples), plain samples for the whole-record windows of
+    // table times (half the LDS per trace)
+    constexpr bool PAIRS = TT == TT_DSR;
 
     float* sTr = lds;                                                    // [cap]
     float4* sGeo = reinterpret_cast<float4*>(lds + P.cap);               // [tb]
@@ -281,7 +304,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             if (lane < NG) {
                 const int2 c = sCand[lane];
                 cwl = c.x;
-                clen = c.y > 0 ? 2 * (c.y - 1) : 0;
+                clen = c.y > 0 ? (PAIRS ? 2 * (c.y - 1) : c.y) : 0;
             }
             int plen = clen, pcnt = clen > 0 ? 1 : 0;  // inclusive prefix sums
 #pragma unroll
@@ -298,7 +321,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             if (wave == 0 && lane < k && clen > 0) {
                 const int slot = nb + pcnt - 1;
                 sGeo[slot] = sCandGeo[lane];
-                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + clen / 2, static_cast<int>(jn + lane - lo));
+                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + (PAIRS ? clen / 2 : clen - 1),
+                                        static_cast<int>(jn + lane - lo));
             }
             if (k > 0) {
                 nb += __builtin_amdgcn_readlane(pcnt, k - 1);
@@ -311,7 +335,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         __syncthreads();        // the block's slots
         for (int t = wave; t < nb; t += NW) {
             const int4 mt = sMeta[t];
-            stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<float2*>(sTr + mt.x), lane);
+            if (PAIRS) stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<float2*>(sTr + mt.x), lane);
+            else stage_window_f(P, lo + mt.w, mt.y, mt.z - mt.y + 1, sTr + mt.x, lane);
         }
         __syncthreads();
 
@@ -322,7 +347,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             const int ts = min(t0 + d, nb - 1);
             const float4 sr = sGeo[ts];
             const int4 mt = sMeta[ts];
-            const int lrow = mt.x / 2 - mt.y - koff;  // in pairs
+            const int lrow = (PAIRS ? mt.x / 2 : mt.x) - mt.y - koff;  // in pairs / floats
             const float lwlo = static_cast<float>(mt.y + koff);
             const float lwhi = static_cast<float>(mt.z - 1 + koff);
 #pragma unroll
@@ -364,7 +389,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                         if (!more) break;
                         continue;
                     }
-                    const float2* row = reinterpret_cast<const float2*>(sTr) + __builtin_amdgcn_readlane(lrow, tc);
+                    const int rb = __builtin_amdgcn_readlane(lrow, tc);
                     const float wlo = uniform_read(lwlo, tc);
                     // max(hs2, hr2): one v_max (fmaxf would first quiet both inputs)
                     float hm;
@@ -378,7 +403,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 const int iz1 = min(z0 + (k + 1) * kGroup + d, P.nz - 1);
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, row, tfo, wlo, whi, R0, R1, acc[q][k],
+                                mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, tfo, wlo, whi, R0, R1, acc[q][k],
                                                          acc[q][k + 1]);
                             }
                         }
@@ -391,7 +416,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                             if ((any >> k) & 3ull) {
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, row,
+                                mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
+                                                             reinterpret_cast<const float2*>(sTr) + rb,
                                                              tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
                             }
                         }
