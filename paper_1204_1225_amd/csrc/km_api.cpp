@@ -188,8 +188,8 @@ std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
 int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
-// 8 waves x 4 column groups x 8 slots; demigrate: 16 waves x 8 slots x 3
-// trace quads).
+// 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 8 slots x 1
+// trace quad).
 int default_shape(int op, int nz) {
     (void)nz;
     return op == 0 ? 2 : 0;

@@ -305,11 +305,16 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT>, grid, block, lds, s, P);
 }
 
-// (waves, depth slots, trace quads per workgroup, LDS budget for the trace accumulators)
+// (waves, depth slots, trace quads per workgroup, LDS budget for the trace
+// accumulators).  The first is the default: one quad of traces per 8-wavefront
+// workgroup, so that two workgroups share a CU; measured faster than 12 traces
+// per 16-wavefront workgroup (one per CU), although each workgroup then reads
+// its box of image columns for 4 traces instead of 12.
 #define KM_DEMIGRATE_SHAPES(X) \
+    X(8, 8, 1, 49152)          \
     X(16, 8, 3, 147456)        \
     X(16, 8, 2, 98304)         \
-    X(12, 8, 3, 147456)        \
+    X(8, 4, 1, 49152)          \
     X(8, 8, 3, 147456)
 
 static const TileShape kDemigrateShapes[] = {
