@@ -193,3 +193,30 @@ def test_strided_traces(ops, oracle_lib):
     wide[:, :200] = torch.from_numpy(p.data).cuda()
     img = ops.migrate(dp, data=wide[:, :200], dtype="f32")
     assert_close(img, oracle_lib.migrate(p), what="strided")
+
+
+@pytest.mark.gpu
+def test_staged_windows_edges(ops, oracle_lib):
+    # Staged time windows follow from the growth of the time with the squared
+    # leg length; a table with s2 < 0 on some depths (time decreasing with
+    # offset) must fall back to whole records, every tile.
+    p = survey.make_random(81, n_traces=300, n_t=500, nx=24, ny=3, nz=90, n_bins=2, dz=10.0, spread=400.0)
+    s2 = p.s2.copy()
+    s2[30:60] *= -0.01  # a = t0^2 + s2 h^2 stays > 0 inside the 60 degree aperture
+    q = dataclasses.replace(p, s2=s2)
+    ref = oracle_lib.migrate(q)
+    assert np.count_nonzero(ref[:, :, :, 30:60]) > 0
+    for tile in range(ops.tile_count(0)):
+        assert_close(ops.migrate(ops.to_device(q), tile=tile), ref, what=f"s2 < 0 tile{tile}")
+    # short record under a deep image: most times fall past the record end
+    r = survey.make_random(82, n_traces=200, n_t=60, nx=20, ny=2, nz=200, n_bins=3, dz=10.0)
+    ref = oracle_lib.migrate(r)
+    assert np.count_nonzero(ref) > 0 and np.all(ref[:, :, :, 150:] == 0)
+    for tile in range(ops.tile_count(0)):
+        assert_close(ops.migrate(ops.to_device(r), tile=tile), ref, what=f"short record tile{tile}")
+    # many short windows per block: dense traces close to a shallow image
+    s = survey.make_random(83, n_traces=3000, n_t=300, nx=16, ny=4, nz=40, n_bins=1, dz=5.0, spread=50.0)
+    assert_close(ops.migrate(ops.to_device(s)), oracle_lib.migrate(s), what="dense traces")
+    # traces far outside every aperture: the image is exactly zero
+    f = dataclasses.replace(s, src=s.src + np.float32(1.0e5), rec=s.rec + np.float32(1.0e5))
+    assert np.all(ops.migrate(ops.to_device(f)).cpu().numpy() == 0)
