@@ -43,9 +43,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "aa4ec0e6eff65abcf593c9d00e5afd07c3e255b520f71bc4a6c2a1d48f523843",
-    "migrate": 1.7717e12,
-    "demigrate": 1.1155e12,
+    "sources_sha256": "e7b7a46bd65135b08131a2746b6e7b5e6500ae874d3e8422c2dfd1816199c643",
+    "migrate": 9.1697e10,
+    "demigrate": 3.2723e12,
 }
 
 

@@ -189,19 +189,23 @@ int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demig
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
 // 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 8 slots x 1
-// trace quad).
-int default_shape(int op, int nz) {
+// trace quad, and 16 waves x 8 slots x 3 quads with table traveltimes, whose
+// table gathers favour more traces per workgroup).
+int default_shape(int op, int nz, bool table) {
     (void)nz;
-    return op == 0 ? 2 : 0;
+    if (op == 0) return 2;
+    return table ? 1 : 0;
 }
 
-km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {
+// The tuning cache is keyed without the traveltime kind, so table calls use
+// the untuned choice unless a tile is given.
+km_status pick_shape(int op, int tile, int dtype, int nz, int nt, bool table, int* shape) {
     if (tile >= 0) {
         if (tile >= shape_count(op)) return fail(KM_E_INVALID, "tile %d out of range [0, %d)", tile, shape_count(op));
         *shape = tile;
         return KM_OK;
     }
-    {
+    if (!table) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(tune_key(op, dtype, nz, nt));
         if (it != g_tune.end()) {
@@ -209,7 +213,7 @@ km_status pick_shape(int op, int tile, int dtype, int nz, int nt, int* shape) {
             return KM_OK;
         }
     }
-    *shape = default_shape(op, nz);
+    *shape = default_shape(op, nz, table);
     return KM_OK;
 }
 
@@ -254,7 +258,7 @@ km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_tr
     if (grid_empty(grid)) return KM_OK;
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_migrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_shape(0, tile, traces->dtype, grid->nz, traces->n_samples, &shape);
+    st = pick_shape(0, tile, traces->dtype, grid->nz, traces->n_samples, tab != nullptr, &shape);
     if (st != KM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (traces->n_traces == 0 && !accumulate)
@@ -280,7 +284,7 @@ km_status demigrate_impl(const float* image, const km_grid* grid, const km_trave
     }
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_demigrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, &shape);
+    st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, tab != nullptr, &shape);
     if (st != KM_OK) return st;
     return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab);
 }
@@ -572,7 +576,7 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
         max_nt = std::max(max_nt, probs[i].traces.n_samples);
     }
     int shape = 0;
-    km_status st = pick_shape(0, tile, probs[0].traces.dtype, max_nz, max_nt, &shape);
+    km_status st = pick_shape(0, tile, probs[0].traces.dtype, max_nz, max_nt, false, &shape);
     if (st != KM_OK) return st;
     const km::TileShape& S = km::migrate_shape(shape);
 
