@@ -8,7 +8,8 @@ columns or traces); this module only loads it and passes numpy arrays.
 Every function takes a problem object with the attributes of a survey
 problem (src, rec, bin, n_t, dt, t_first, x, y, t0sq, s2, r2, weight,
 n_bins, and optionally a one-way traveltime table ttab [n_h][nz] with
-spacing tdh, which replaces the t0sq / s2 form) and, where samples are needed, a float64 data array [n_traces, n_t]
+spacing tdh, which replaces the t0sq / s2 form, and optionally aa = (dx, dy,
+max half-width) for the anti-alias triangle filter) and, where samples are needed, a float64 data array [n_traces, n_t]
 (default: the problem's own data widened to float64).
 
 Parity status: all functions are pinned by the CPU tests (closed forms,
@@ -49,6 +50,7 @@ class _Problem(ctypes.Structure):
         ("t0sq", ctypes.c_void_p), ("s2", ctypes.c_void_p), ("r2", ctypes.c_void_p),
         ("weight", ctypes.c_int32),
         ("n_h", ctypes.c_int32), ("dh", ctypes.c_double), ("ttab", ctypes.c_void_p),
+        ("aa_dx", ctypes.c_double), ("aa_dy", ctypes.c_double), ("aa_max", ctypes.c_int32),
     ]
 
 
@@ -107,6 +109,9 @@ class _Bound:
             r2=k["r2"].ctypes.data, weight=int(p.weight),
             n_h=k["ttab"].shape[0] if "ttab" in k else 0, dh=float(getattr(p, "tdh", 0.0) or 0.0),
             ttab=k["ttab"].ctypes.data if "ttab" in k else None)
+        aa = getattr(p, "aa", None)  # (dx, dy, max half-width) or None
+        if aa is not None:
+            self.s.aa_dx, self.s.aa_dy, self.s.aa_max = float(aa[0]), float(aa[1]), int(aa[2])
         assert k["s2"].shape[0] == self.s.nz and k["r2"].shape[0] == self.s.nz
 
     @property

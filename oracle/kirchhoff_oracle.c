@@ -33,6 +33,17 @@
  *  - The adjoint (demigration) is the exact transpose: each in-aperture pair
  *    adds (1 - f) W I to D[i] and f W I to D[i + 1] (samples outside [0, n_t)
  *    are dropped).
+ *  - Anti-aliasing (aa_max > 0; the operator anti-alias filter of production
+ *    Kirchhoff migration, which the paper does not discuss): the trace is
+ *    smoothed, per pair, by a triangle whose half-width is the time the
+ *    operator moves between neighbouring image points.  In samples,
+ *        p = |du/dx| aa_dx + |du/dy| aa_dy,
+ *        du/dx = (s2 / dt) ((x - x_s) / T_s + (x - x_r) / T_r)   (likewise y),
+ *    clamped to [1, aa_max]; with L = floor(p), phi = p - L,
+ *        T_L(c) = sum_{|k| < L} (L - |k|) / L^2 D(c + k)   (unit area; T_1 = D),
+ *        T_p(c) = (1 - phi) T_L(c) + phi T_{L+1}(c)        (continuous in p),
+ *    and the data value is (1 - f) T_p(i) + f T_p(i + 1).  Square-root times
+ *    only.  The adjoint spreads each pair the same way.
  *  - Table traveltimes (ttab != NULL; curved rays in a laterally invariant
  *    medium, where a one-way time depends only on the horizontal distance h
  *    and the depth): T(h, z[iz]) is the linear interpolation in h of
@@ -71,6 +82,8 @@ typedef struct {
     int32_t n_h;           /* table traveltimes: rows of ttab (>= 2) */
     double dh;             /* table spacing in h (> 0) */
     const float* ttab;     /* [n_h][nz] one-way seconds, or NULL for the t0sq / s2 form */
+    double aa_dx, aa_dy;   /* anti-aliasing: image spacings the dip is measured over */
+    int32_t aa_max;        /* anti-aliasing: largest triangle half-width (samples); 0 = off */
 } ko_problem;
 
 /* Linear interpolation in h of the one-way time table at depth iz. */
@@ -97,8 +110,9 @@ static int ko_in_aperture(float px, float py, float sx, float sy, float rx, floa
 }
 
 /* One (trace, image point) pair.  Returns 0 when the pair is outside the
- * aperture; otherwise sets *u (fractional sample index) and *w (weight). */
-static int ko_pair(const ko_problem* P, int64_t j, int ix, int iy, int iz, double* u, double* w)
+ * aperture; otherwise sets *u (fractional sample index), *w (weight) and,
+ * with anti-aliasing, *p (triangle half-width in samples, in [1, aa_max]). */
+static int ko_pair_p(const ko_problem* P, int64_t j, int ix, int iy, int iz, double* u, double* w, double* p)
 {
     const float px = P->x[ix], py = P->y[iy];
     const float sx = P->src[2 * j], sy = P->src[2 * j + 1];
@@ -120,7 +134,55 @@ static int ko_pair(const ko_problem* P, int64_t j, int ix, int iy, int iz, doubl
         *w = P->t0sq[iz] > 0.0 ? P->t0sq[iz] / (a_s * a_r) : 0.0;
     else
         *w = 1.0;
+    if (P->aa_max > 0 && p) {
+        const double g = P->s2[iz] / P->dt;
+        const double ux = g * (((double)px - sx) / sqrt(a_s) + ((double)px - rx) / sqrt(a_r));
+        const double uy = g * (((double)py - sy) / sqrt(a_s) + ((double)py - ry) / sqrt(a_r));
+        double q = fabs(ux) * P->aa_dx + fabs(uy) * P->aa_dy;
+        if (!(q >= 1.0)) q = 1.0;
+        if (q > (double)P->aa_max) q = (double)P->aa_max;
+        *p = q;
+    }
     return 1;
+}
+
+static int ko_pair(const ko_problem* P, int64_t j, int ix, int iy, int iz, double* u, double* w)
+{
+    return ko_pair_p(P, j, ix, iy, iz, u, w, NULL);
+}
+
+/* Weight of sample c + k in the triangle-smoothed value at c, half-width p
+ * (see header): (1 - phi) (L - |k|)+ / L^2 + phi (L + 1 - |k|)+ / (L + 1)^2. */
+static double ko_tri_weight(double p, int64_t k)
+{
+    const double L = floor(p), phi = p - L;
+    const double a = fabs((double)k);
+    double wt = 0.0;
+    if (a < L) wt += (1.0 - phi) * (L - a) / (L * L);
+    if (a < L + 1.0) wt += phi * (L + 1.0 - a) / ((L + 1.0) * (L + 1.0));
+    return wt;
+}
+
+/* Triangle-smoothed sample of row d at integer index c (zero outside [0, n_t)). */
+static double ko_tri_sample(const double* d, int32_t n_t, int64_t c, double p)
+{
+    const int64_t r = (int64_t)floor(p) + 1;
+    double acc = 0.0;
+    for (int64_t k = -r; k <= r; ++k) {
+        const int64_t n = c + k;
+        if (n >= 0 && n < n_t) acc += ko_tri_weight(p, k) * d[n];
+    }
+    return acc;
+}
+
+/* Anti-aliased data value: (1 - f) T_p(i) + f T_p(i + 1), u = i + f. */
+static double ko_sample_aa(const double* d, int32_t n_t, double u, double p)
+{
+    const double fl = floor(u), reach = floor(p) + 2.0;
+    if (!(fl > -reach && fl < (double)n_t + reach)) return 0.0;  /* no overlap with the record */
+    const int64_t i = (int64_t)fl;
+    const double f = u - fl;
+    return (1.0 - f) * ko_tri_sample(d, n_t, i, p) + f * ko_tri_sample(d, n_t, i + 1, p);
 }
 
 /* Zero-extended linear interpolation of trace row d at fractional index u. */
@@ -135,11 +197,43 @@ static double ko_sample(const double* d, int32_t n_t, double u)
     return (1.0 - f) * d0 + f * d1;
 }
 
+/* Pair value of trace row d: the interpolated sample, anti-aliased when enabled. */
+static double ko_value(const ko_problem* P, const double* d, double u, double p)
+{
+    return P->aa_max > 0 ? ko_sample_aa(d, P->n_t, u, p) : ko_sample(d, P->n_t, u);
+}
+
+/* Adjoint of ko_value: adds val times the weight of each sample to row d. */
+static void ko_spread(const ko_problem* P, double* d, double u, double p, double val)
+{
+    const int32_t nt = P->n_t;
+    if (P->aa_max <= 0) {
+        if (!(u > -1.0 && u < (double)nt)) return;
+        const double fl = floor(u);
+        const int64_t i = (int64_t)fl;
+        const double f = u - fl;
+        if (i >= 0) d[i] += (1.0 - f) * val;
+        if (i + 1 < nt) d[i + 1] += f * val;
+        return;
+    }
+    const double fl = floor(u), reach = floor(p) + 2.0;
+    if (!(fl > -reach && fl < (double)nt + reach)) return;
+    const int64_t i = (int64_t)fl;
+    const double f = u - fl;
+    const int64_t r = (int64_t)floor(p) + 1;
+    for (int64_t k = -r; k <= r; ++k) {
+        const double wt = ko_tri_weight(p, k);
+        if (i + k >= 0 && i + k < nt) d[i + k] += (1.0 - f) * wt * val;
+        if (i + 1 + k >= 0 && i + 1 + k < nt) d[i + 1 + k] += f * wt * val;
+    }
+}
+
 static int ko_check(const ko_problem* P)
 {
     if (!P || P->n_traces < 0 || P->n_t < 0 || P->nx < 0 || P->ny < 0 || P->nz < 0 || P->n_bins < 0) return 1;
     if (!(P->dt > 0.0)) return 1;
     if (P->ttab && (P->n_h < 2 || !(P->dh > 0.0) || P->weight != 0)) return 1;
+    if (P->aa_max < 0 || (P->aa_max > 0 && (P->ttab || !(P->aa_dx >= 0.0) || !(P->aa_dy >= 0.0)))) return 1;
     return 0;
 }
 
@@ -157,9 +251,9 @@ int oracle_migrate_columns(const ko_problem* P, int64_t n_cols, const int32_t* c
             if (P->bin[j] != b) continue;
             const double* d = P->data + j * (int64_t)P->n_t;
             for (int iz = 0; iz < nz; ++iz) {
-                double u, w;
-                if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
-                o[iz] += w * ko_sample(d, P->n_t, u);
+                double u, w, p = 1.0;
+                if (!ko_pair_p(P, j, ix, iy, iz, &u, &w, &p)) continue;
+                o[iz] += w * ko_value(P, d, u, p);
             }
         }
     }
@@ -194,9 +288,9 @@ int oracle_migrate_points(const ko_problem* P, int64_t n_pts, const int32_t* pts
         double acc = 0.0;
         for (int64_t j = 0; j < P->n_traces; ++j) {
             if (P->bin[j] != b) continue;
-            double u, w;
-            if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
-            acc += w * ko_sample(P->data + j * (int64_t)P->n_t, P->n_t, u);
+            double u, w, p = 1.0;
+            if (!ko_pair_p(P, j, ix, iy, iz, &u, &w, &p)) continue;
+            acc += w * ko_value(P, P->data + j * (int64_t)P->n_t, u, p);
         }
         out[k] = acc;
     }
@@ -218,15 +312,9 @@ int oracle_demigrate(const ko_problem* P, const double* image, double* data)
             for (int ix = 0; ix < P->nx; ++ix) {
                 const double* m = image + (((int64_t)b * P->ny + iy) * P->nx + ix) * nz;
                 for (int iz = 0; iz < nz; ++iz) {
-                    double u, w;
-                    if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
-                    if (!(u > -1.0 && u < (double)nt)) continue;
-                    double fl = floor(u);
-                    int64_t i = (int64_t)fl;
-                    double f = u - fl;
-                    double val = w * m[iz];
-                    if (i >= 0) d[i] += (1.0 - f) * val;
-                    if (i + 1 < nt) d[i + 1] += f * val;
+                    double u, w, p = 1.0;
+                    if (!ko_pair_p(P, j, ix, iy, iz, &u, &w, &p)) continue;
+                    ko_spread(P, d, u, p, w * m[iz]);
                 }
             }
     }
@@ -250,8 +338,16 @@ int oracle_demigrate_samples(const ko_problem* P, const double* image, int64_t n
                 for (int ix = 0; ix < P->nx; ++ix) {
                     const double* m = image + (((int64_t)b * P->ny + iy) * P->nx + ix) * nz;
                     for (int iz = 0; iz < nz; ++iz) {
-                        double u, w;
-                        if (!ko_pair(P, j, ix, iy, iz, &u, &w)) continue;
+                        double u, w, p = 1.0;
+                        if (!ko_pair_p(P, j, ix, iy, iz, &u, &w, &p)) continue;
+                        if (P->aa_max > 0) {
+                            const double fl = floor(u), reach = floor(p) + 2.0;
+                            if (!(fl > -reach && fl < (double)nt + reach)) continue;
+                            const double f = u - fl;
+                            const int64_t i = (int64_t)fl;
+                            acc += ((1.0 - f) * ko_tri_weight(p, n - i) + f * ko_tri_weight(p, n - i - 1)) * w * m[iz];
+                            continue;
+                        }
                         if (!(u > -1.0 && u < (double)nt)) continue;
                         double fl = floor(u);
                         int64_t i = (int64_t)fl;

@@ -75,6 +75,8 @@ class Problem:
     # optional one-way traveltime table [n_h][nz] (seconds at h = ih * tdh), replacing t0sq / s2
     ttab: Optional[np.ndarray] = None
     tdh: float = 0.0
+    # optional anti-alias triangle filter: (dx, dy, largest half-width in samples)
+    aa: Optional[tuple] = None
 
     @property
     def n_traces(self) -> int:
