@@ -166,6 +166,35 @@ km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, 
 km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, const km_ttable* table,
                                     const km_traces* out, int32_t accumulate, int32_t tile, void* stream);
 
+/* Anti-alias operator filter (the paper is silent on aliasing; this is the
+ * triangle filter of production Kirchhoff migration).  Per pair the trace is
+ * smoothed by a unit-area triangle whose half-width is the time, in samples,
+ * the operator moves between neighbouring image points:
+ *   p = |du/dx| dx + |du/dy| dy,  du/dx = (s2 / dt) ((x - x_s) / T_s + (x - x_r) / T_r)
+ * (likewise y), clamped to [1, max_half]; with L = floor(p), phi = p - L,
+ *   T_L(c) = sum_{|k| < L} (L - |k|) / L^2 D[c + k],  T_p = (1 - phi) T_L + phi T_{L+1},
+ * and the pair's value is (1 - f) T_p(i) + f T_p(i + 1) in place of
+ * (1 - f) D[i] + f D[i + 1] (D zero outside [0, n_samples)).  p = 1 gives the
+ * plain operator. */
+typedef struct km_antialias {
+    double dx, dy;     /* spacings the dip is measured over (image x / y spacing; finite, >= 0) */
+    int32_t max_half;  /* largest triangle half-width in samples, 1 .. 32 */
+} km_antialias;
+
+/* As kirchhoff_migrate with the anti-alias filter (square-root traveltimes).
+ * KM_E_INVALID also for NULL options, dx or dy negative or not finite,
+ * max_half outside [1, 32]; KM_E_UNSUPPORTED for records whose anti-aliased
+ * staging does not fit in LDS (n_samples + 4 max_half + 9 float64 values). */
+km_status kirchhoff_migrate_aa(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                               const km_weight* weight, const km_antialias* aa, float* image, int32_t accumulate,
+                               int32_t tile, void* stream);
+
+/* As kirchhoff_demigrate with the anti-alias filter: the exact transpose of
+ * kirchhoff_migrate_aa for the same inputs. */
+km_status kirchhoff_demigrate_aa(const float* image, const km_grid* grid, const km_traveltime* tt,
+                                 const km_weight* weight, const km_antialias* aa, const km_traces* out,
+                                 int32_t accumulate, int32_t tile, void* stream);
+
 /* Pair counts of Eq. (2) (f_K N_xyz N_tr with N_tr the traces close enough):
  * counts[0] = pairs passing the aperture test, counts[1] = those whose time
  * also falls inside the zero-extended record (-1 < u < n_samples, u in the

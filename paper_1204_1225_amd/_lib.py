@@ -39,6 +39,10 @@ class KmTtable(ctypes.Structure):
     _fields_ = [("n_h", _i32), ("dh", _f64), ("t", _vp), ("r2", _vp)]
 
 
+class KmAntialias(ctypes.Structure):
+    _fields_ = [("dx", _f64), ("dy", _f64), ("max_half", _i32)]
+
+
 class KmWeight(ctypes.Structure):
     _fields_ = [("kind", _i32)]
 
@@ -70,6 +74,10 @@ SIGNATURES = {
     "kirchhoff_demigrate": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmTraces), _i32, _i32, _vp]),
     "kirchhoff_migrate_table": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTtable), _vp, _i32, _i32, _vp]),
     "kirchhoff_demigrate_table": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTtable), _P(KmTraces), _i32, _i32, _vp]),
+    "kirchhoff_migrate_aa": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTraveltime), _P(KmWeight),
+                                            _P(KmAntialias), _vp, _i32, _i32, _vp]),
+    "kirchhoff_demigrate_aa": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmAntialias),
+                                              _P(KmTraces), _i32, _i32, _vp]),
     "km_count_contributions": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTraveltime), _vp, _vp]),
     "km_dot_f64": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "km_axpby": (ctypes.c_int, [_f64, _vp, _f64, _vp, _i64, _vp]),

@@ -142,8 +142,10 @@ int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
 // record does not fit in LDS.
 constexpr int kMigrateSlots = 128;
 bool migrate_block_params(km::Params& P, int budget, int ks) {
-    // square-root times stage (sample, difference) pairs, table times samples
-    const int64_t need = (P.ttab ? static_cast<int64_t>(P.nt) + 3 : 2 * (static_cast<int64_t>(P.nt) + 2)) + 3 & ~int64_t{3};
+    // square-root times stage (sample, difference) pairs, table times samples,
+    // anti-aliasing float64 running sums over nt + 4 max_half + 9 positions
+    const int64_t nt = P.nt;
+    const int64_t need = (P.aa_max > 0 ? 2 * (nt + 4 * P.aa_max + 9) : P.ttab ? nt + 3 : 2 * (nt + 2)) + 3 & ~int64_t{3};
     for (int tb = kMigrateSlots; tb >= 1; tb /= 2) {
         const int64_t fixed = static_cast<int64_t>(km::migrate_lds_words(0, tb, ks));
         const int64_t cap = std::max<int64_t>((budget / 4 - fixed) & ~int64_t{3}, need);
@@ -163,7 +165,9 @@ km_status shape_params(int op, int shape, km::Params& P) {
     } else {
         // float64 rows; the four groups of a wavefront take four traces, so
         // whole quads of traces keep every group busy
-        P.tb = traces_per_block(P.lt, S.lds_budget, 0, 8);
+        // (anti-aliased rows are longer: the budget grows with them, keeping whole quads)
+        const int extra = P.aa_max > 0 ? 4 * 8 * (P.lt - (P.nt + km::kLead + kTailPad + 3) / 4 * 4) : 0;
+        P.tb = traces_per_block(P.lt, S.lds_budget + extra, 0, 8);
         if (S.max_quads > 0) P.tb = std::min(P.tb, 4 * S.max_quads);
         if (P.tb >= 4) P.tb &= ~3;
     }
@@ -197,15 +201,16 @@ int default_shape(int op, int nz, bool table) {
     return table ? 1 : 0;
 }
 
-// The tuning cache is keyed without the traveltime kind, so table calls use
-// the untuned choice unless a tile is given.
-km_status pick_shape(int op, int tile, int dtype, int nz, int nt, bool table, int* shape) {
+// The tuning cache is keyed without the traveltime kind or the anti-alias
+// filter, so table and anti-aliased calls use the untuned choice unless a
+// tile is given.
+km_status pick_shape(int op, int tile, int dtype, int nz, int nt, bool table, int* shape, bool aa = false) {
     if (tile >= 0) {
         if (tile >= shape_count(op)) return fail(KM_E_INVALID, "tile %d out of range [0, %d)", tile, shape_count(op));
         *shape = tile;
         return KM_OK;
     }
-    if (!table) {
+    if (!table && !aa) {
         std::lock_guard<std::mutex> lk(g_tune_mu);
         auto it = g_tune.find(tune_key(op, dtype, nz, nt));
         if (it != g_tune.end()) {
@@ -218,8 +223,18 @@ km_status pick_shape(int op, int tile, int dtype, int nz, int nt, bool table, in
 }
 
 km_status run_op(int op, const km_traces* t, const km_grid* g, const km_traveltime* tt, const km_weight* w,
-                 float* image, int accumulate, int shape, hipStream_t s, const km_ttable* tab = nullptr) {
+                 float* image, int accumulate, int shape, hipStream_t s, const km_ttable* tab = nullptr,
+                 const km_antialias* aa = nullptr) {
     km::Params P = base_params(t, g, tt, w, image, accumulate);
+    if (aa) {
+        P.aa_dx = static_cast<float>(aa->dx);
+        P.aa_dy = static_cast<float>(aa->dy);
+        P.aa_max = aa->max_half;
+        // demigrate rows: samples -aa_lead .. nt + aa_lead - 1 (the dual of the
+        // double running sum reaches 2 max_half + 4 past either end)
+        P.aa_lead = 2 * aa->max_half + 5;
+        P.lt = (t->n_samples + 2 * P.aa_lead + 3) / 4 * 4;
+    }
     if (tab) {
         P.ttab = tab->t;
         P.n_h = tab->n_h;
@@ -250,7 +265,8 @@ km_status zero_floats(float* p, int64_t n, hipStream_t s) {
 }
 
 km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_traveltime* tt, const km_weight* weight,
-                       float* image, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab) {
+                       float* image, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab,
+                       const km_antialias* aa = nullptr) {
     km_status st = check_traces(traces, true, "kirchhoff_migrate");
     if (st != KM_OK) return st;
     st = check_grid(grid, tt, weight, "kirchhoff_migrate");
@@ -258,16 +274,17 @@ km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_tr
     if (grid_empty(grid)) return KM_OK;
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_migrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_shape(0, tile, traces->dtype, grid->nz, traces->n_samples, tab != nullptr, &shape);
+    st = pick_shape(0, tile, traces->dtype, grid->nz, traces->n_samples, tab != nullptr, &shape, aa != nullptr);
     if (st != KM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (traces->n_traces == 0 && !accumulate)
         return zero_floats(image, static_cast<int64_t>(grid->n_bins) * grid->ny * grid->nx * grid->nz, s);
-    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s, tab);
+    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s, tab, aa);
 }
 
 km_status demigrate_impl(const float* image, const km_grid* grid, const km_traveltime* tt, const km_weight* weight,
-                         const km_traces* out, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab) {
+                         const km_traces* out, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab,
+                         const km_antialias* aa = nullptr) {
     km_status st = check_traces(out, true, "kirchhoff_demigrate");
     if (st != KM_OK) return st;
     if (out->dtype != KM_F32)
@@ -284,9 +301,19 @@ km_status demigrate_impl(const float* image, const km_grid* grid, const km_trave
     }
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_demigrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, tab != nullptr, &shape);
+    st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, tab != nullptr, &shape, aa != nullptr);
     if (st != KM_OK) return st;
-    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab);
+    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab, aa);
+}
+
+// Anti-alias filter options.
+km_status check_antialias(const km_antialias* aa, const char* who) {
+    if (!aa) return fail(KM_E_INVALID, "%s: anti-alias options are NULL", who);
+    if (!(aa->dx >= 0.0) || !(aa->dy >= 0.0) || !std::isfinite(aa->dx) || !std::isfinite(aa->dy))
+        return fail(KM_E_INVALID, "%s: dx and dy must be finite and >= 0", who);
+    if (aa->max_half < 1 || aa->max_half > km::kAAMaxHalf)
+        return fail(KM_E_INVALID, "%s: max_half must be in [1, %d]", who, km::kAAMaxHalf);
+    return KM_OK;
 }
 
 // Table traveltimes: validate the table, then run the shared path with the
@@ -342,6 +369,22 @@ km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, con
     const km_traveltime tt{tab->r2, tab->r2, tab->r2};
     const km_weight w{KM_W_UNIT};
     return demigrate_impl(image, grid, &tt, &w, out, accumulate, tile, stream, tab);
+}
+
+km_status kirchhoff_migrate_aa(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                               const km_weight* weight, const km_antialias* aa, float* image, int32_t accumulate,
+                               int32_t tile, void* stream) {
+    km_status st = check_antialias(aa, "kirchhoff_migrate_aa");
+    if (st != KM_OK) return st;
+    return migrate_impl(traces, grid, tt, weight, image, accumulate, tile, stream, nullptr, aa);
+}
+
+km_status kirchhoff_demigrate_aa(const float* image, const km_grid* grid, const km_traveltime* tt,
+                                 const km_weight* weight, const km_antialias* aa, const km_traces* out,
+                                 int32_t accumulate, int32_t tile, void* stream) {
+    km_status st = check_antialias(aa, "kirchhoff_demigrate_aa");
+    if (st != KM_OK) return st;
+    return demigrate_impl(image, grid, tt, weight, out, accumulate, tile, stream, nullptr, aa);
 }
 
 

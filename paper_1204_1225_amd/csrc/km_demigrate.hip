@@ -94,6 +94,28 @@ __device__ __forceinline__ void dem_pair_table(const Params& P, TLeg Ls, TLeg Lr
     }
 }
 
+// One slot with the anti-alias triangle filter: the transpose of the migrate
+// value alpha T_L + beta T_{L+1} (second differences of the double running
+// sum I2) interpolated between samples i and i + 1.  Each pair adds to the
+// dual row G at the eight positions whose I2 it read; the kernel turns G into
+// samples at the end (D[k] = sum_{n >= k} (n - k + 1) G[n]).
+template <bool TF, int WK>
+__device__ __forceinline__ void dem_slot_aa(const PairAA& p, float x, double* row) {
+    const float q = (WK == W_COSCOS) ? x * p.r : x;
+    const double a = static_cast<double>((1.0f - p.f) * q), b = static_cast<double>(p.f * q);
+    const double al = p.alpha, be = p.beta;
+    const int i = p.i, L = p.L;
+    const double m2 = -2.0 * (al + be);
+    atomicAdd(row + i - L - 2, a * be);
+    atomicAdd(row + i - L - 1, fma(a, al, b * be));
+    atomicAdd(row + i - L, b * al);
+    atomicAdd(row + i - 1, a * m2);
+    atomicAdd(row + i, b * m2);
+    atomicAdd(row + i + L - 1, a * al);
+    atomicAdd(row + i + L, fma(a, be, b * al));
+    atomicAdd(row + i + L + 1, b * be);
+}
+
 // Coordinates and image values (depth slots of this lane) of column (ix, iy).
 // Lanes past the last depth (only in the last chunk, TAIL) read the last
 // depth instead; they are never inside the aperture, so the value is unused.
@@ -121,12 +143,23 @@ __device__ __forceinline__ void fetch_column(const Params& P, const float* img, 
 template <int NW, int KS, int NQ, bool TF, int WK, bool TAIL, int TT>
 __device__ __forceinline__ void sweep_columns(const Params& P, const float* img, int z0, int d, int g, int wave, int t0,
                                               int nseg, int nq, int ix0, int ix1, int iy0, int iy1,
-                                              const ChunkTables<KS>& T, const float* S, const float4* G, double* sAcc) {
+                                              const ChunkTables<KS>& T, const float* S, const float4* G, double* sAcc,
+                                              const float* sInvSq) {
     constexpr uint32_t kMask = (KS >= 32) ? ~0u : ((1u << KS) - 1u);
+    constexpr bool AA = TT == TT_AA;
     float wlo, whi;
     clamp_bounds<TF>(P.lt, wlo, whi);
     const float tfo = P.tf_off;
-    const int rowoff = TF ? 0 : kLead;
+    int rowoff = TF ? 0 : kLead;
+    const int lmax = AA ? P.aa_max : 0;
+    if (AA) {
+        // samples -(lmax + 2) .. nt + lmax + 2 (beyond them every triangle misses
+        // the record); row index of sample n is aa_lead + n
+        const int koff = TF ? kLead : 0;
+        wlo = static_cast<float>(koff - lmax - 2);
+        whi = static_cast<float>(koff + P.nt + lmax + 2);
+        rowoff = P.aa_lead - koff;
+    }
     double* rows[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) rows[q] = sAcc + (t0 + min(kGroupsPerWave * q + g, nseg - 1)) * P.lt + rowoff;
@@ -159,6 +192,21 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
             const uint32_t any = fold_or(__builtin_amdgcn_ballot_w64(L.hmax <= T.rhi)) & kMask;
             if (!any) continue;
             double* row = rows[q];
+            if (AA) {
+                // column minus source / receiver of this group's trace
+                const float dxs = px - G[q].x, dys = py - G[q].y, dxr = px - G[q].z, dyr = py - G[q].w;
+#pragma unroll
+                for (int k = 0; k < KS; ++k) {
+                    if (!((any >> k) & 1u)) continue;
+                    if (L.hmax <= T.R[k]) {
+                        const PairAA pa = eval_pair_aa<TF, WK>(T.A[k], T.B[k], L.hs2, L.hr2, tfo, wlo, whi, dxs, dys,
+                                                               dxr, dyr, P.aa_dx, P.aa_dy, static_cast<float>(lmax),
+                                                               sInvSq);
+                        dem_slot_aa<TF, WK>(pa, x[k], row);
+                    }
+                }
+                continue;
+            }
             if (TT == TT_TABLE) {
                 const TLeg Ls = table_leg(P, L.hs2), Lr = table_leg(P, L.hr2);
 #pragma unroll
@@ -186,7 +234,7 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 // Traces t0..t1-1 of the block (one bin b, at most 4 NQ traces).
 template <int NW, int KS, int NQ, bool TF, int WK, int TT>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
-                                                  double* sAcc) {
+                                                  double* sAcc, const float* sInvSq) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     const int lane = threadIdx.x & (kLanes - 1);
     const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x / kLanes);
@@ -239,10 +287,10 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
         if (iy0 > iy1) continue;
         if (z0 + KS * kGroup > P.nz)
             sweep_columns<NW, KS, NQ, TF, WK, true, TT>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S,
-                                                        G, sAcc);
+                                                        G, sAcc, sInvSq);
         else
             sweep_columns<NW, KS, NQ, TF, WK, false, TT>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S,
-                                                         G, sAcc);
+                                                         G, sAcc, sInvSq);
     }
 }
 
@@ -251,7 +299,11 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
     extern __shared__ float lds[];
     double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
     float4* sGeo = reinterpret_cast<float4*>(lds + 2 * P.tb * P.lt);   // [tb]
+    float* sInvSq = lds + 2 * P.tb * P.lt + 4 * P.tb;                  // [kAAMaxHalf + 2]: 1 / n^2
     const int64_t j0 = static_cast<int64_t>(blockIdx.x) * P.tb;
+    if (TT == TT_AA)
+        for (int t = threadIdx.x; t < kAAMaxHalf + 2; t += blockDim.x)
+            sInvSq[t] = t > 0 ? 1.0f / static_cast<float>(t * t) : 0.0f;
     const int nb = static_cast<int>(min<int64_t>(P.tb, P.n_traces - j0));
 
     for (int t = threadIdx.x; t < P.tb; t += blockDim.x) {
@@ -271,15 +323,39 @@ __global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
         const int b = P.bin[j0 + t0];
         int t1 = t0 + 1;
         while (t1 < nb && P.bin[j0 + t1] == b) ++t1;
-        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK, TT>(P, b, t0, t1, sGeo, sAcc);
+        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK, TT>(P, b, t0, t1, sGeo, sAcc, sInvSq);
         t0 = t1;
     }
     __syncthreads();
 
+    if (TT == TT_AA) {
+        // D[k] = sum_{n >= k} (n - k + 1) G[n]: two suffix sums of each row, one
+        // wavefront per row, 64 positions at a time from the end.
+        const int lane = threadIdx.x & (kLanes - 1);
+        for (int t = threadIdx.x / kLanes; t < nb; t += NW) {
+            double* row = sAcc + t * P.lt;
+            for (int pass = 0; pass < 2; ++pass) {
+                double carry = 0.0;
+                for (int top = P.lt - 1; top >= 0; top -= kLanes) {
+                    const int e = top - lane;
+                    double v = e >= 0 ? row[e] : 0.0;
+#pragma unroll
+                    for (int off = 1; off < kLanes; off <<= 1) {
+                        const double u = __shfl_up(v, off, kLanes);
+                        if (lane >= off) v += u;
+                    }
+                    if (e >= 0) row[e] = carry + v;
+                    carry += __shfl(v, kLanes - 1, kLanes);
+                }
+            }
+        }
+        __syncthreads();
+    }
+
     float* out = static_cast<float*>(P.data);
     for (int t = 0; t < nb; ++t) {
         float* o = out + (j0 + t) * P.stride;
-        const double* row = sAcc + t * P.lt + kLead;
+        const double* row = sAcc + t * P.lt + (TT == TT_AA ? P.aa_lead : kLead);
         for (int k = threadIdx.x; k < P.nt; k += blockDim.x) {
             const float v = static_cast<float>(row[k]);
             o[k] = P.accumulate ? o[k] + v : v;
@@ -296,6 +372,16 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
         if (P.has_tf) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
         return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
+    }
+    if (P.aa_max > 0) {  // anti-alias triangle filter
+        if (P.has_tf) {
+            if (P.weight == W_COSCOS)
+                return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_COSCOS, TT_AA>, grid, block, lds, s, P);
+            return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_AA>, grid, block, lds, s, P);
+        }
+        if (P.weight == W_COSCOS)
+            return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_COSCOS, TT_AA>, grid, block, lds, s, P);
+        return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_AA>, grid, block, lds, s, P);
     }
     if (P.has_tf) {
         if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_COSCOS>, grid, block, lds, s, P);

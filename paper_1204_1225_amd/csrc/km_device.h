@@ -68,11 +68,17 @@ struct Params {
     float inv_dh;       // 1 / dh
     double inv_dt;      // 1 / dt
     double tf_off_d;    // kLead - t_first / dt in float64
+    // anti-alias triangle filter (the TT_AA kernels)
+    float aa_dx, aa_dy;  // image spacings the operator dip is measured over
+    int32_t aa_max;      // largest triangle half-width in samples (1 .. kAAMaxHalf)
+    int32_t aa_lead;     // demigrate: row index of sample 0 (rows hold samples -aa_lead .. lt - aa_lead - 1)
 };
 
 // Traveltime kinds of the kernels: the per-depth double-square-root form
 // (t0sq, s2) or a one-way time table T(h, z) interpolated linearly in h.
-enum TravelKind : int32_t { TT_DSR = 0, TT_TABLE = 1 };
+// TT_AA: the double-square-root form with the anti-alias triangle filter.
+enum TravelKind : int32_t { TT_DSR = 0, TT_TABLE = 1, TT_AA = 2 };
+constexpr int kAAMaxHalf = 32;  // largest anti-alias half-width the kernels accept
 
 // First index in sorted bin[0..n) whose value is >= key.
 __device__ __forceinline__ int64_t lower_bound_bin(const int32_t* __restrict__ bin, int64_t n, int32_t key) {
@@ -132,6 +138,45 @@ __device__ __forceinline__ Pair eval_pair(float A, float B, float hs2, float hr2
     p.i = static_cast<int32_t>(w);
     p.f = __builtin_amdgcn_fractf(w);
     p.r = (WK == W_COSCOS) ? __builtin_amdgcn_rcpf(as * ar) : 1.0f;
+    return p;
+}
+
+// One pair with the anti-alias triangle filter (Params::aa_*).  As eval_pair
+// (clamped), plus the half-width p = |du/dx| dx + |du/dy| dy in samples,
+// du/dx = B ((x - x_s) / sqrt(a_s) + (x - x_r) / sqrt(a_r)) (likewise y),
+// clamped to [1, aa_max]; L = floor(p) and the blend weights
+// alpha = (1 - phi) / L^2, beta = phi / (L + 1)^2 (phi = p - L) of the two
+// integer-width unit-area triangles (invsq[n] = 1 / n^2).  (dxs, dys), (dxr,
+// dyr): image column minus source / receiver.  Migrate and demigrate call
+// this, so both see the same (i, f, r, L, alpha, beta).
+struct PairAA {
+    int32_t i, L;
+    float f, r, alpha, beta;
+};
+
+template <bool TF, int WK>
+__device__ __forceinline__ PairAA eval_pair_aa(float A, float B, float hs2, float hr2, float tf_off, float wlo,
+                                               float whi, float dxs, float dys, float dxr, float dyr, float adx,
+                                               float ady, float lmax, const float* invsq) {
+    const float as = fmaf(B, hs2, A);
+    const float ar = fmaf(B, hr2, A);
+    const float ss = __builtin_amdgcn_sqrtf(as), sr = __builtin_amdgcn_sqrtf(ar);
+    float w = ss + sr;
+    if (TF) w = w + tf_off;
+    w = __builtin_amdgcn_fmed3f(w, wlo, whi);
+    PairAA p;
+    p.i = static_cast<int32_t>(w);
+    p.f = __builtin_amdgcn_fractf(w);
+    p.r = (WK == W_COSCOS) ? __builtin_amdgcn_rcpf(as * ar) : 1.0f;
+    const float is = __builtin_amdgcn_rcpf(ss), ir = __builtin_amdgcn_rcpf(sr);
+    const float ux = B * fmaf(dxs, is, dxr * ir);
+    const float uy = B * fmaf(dys, is, dyr * ir);
+    // a NaN (zero leg time) takes the lower bound: no smoothing
+    const float q = __builtin_amdgcn_fmed3f(fmaf(fabsf(ux), adx, fabsf(uy) * ady), 1.0f, lmax);
+    p.L = static_cast<int32_t>(q);
+    const float phi = q - static_cast<float>(p.L);
+    p.alpha = (1.0f - phi) * invsq[p.L];
+    p.beta = phi * invsq[p.L + 1];
     return p;
 }
 

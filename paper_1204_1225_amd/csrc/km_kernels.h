@@ -31,19 +31,21 @@ inline hipError_t launch_with_lds(Kernel kernel, dim3 grid, dim3 block, size_t l
 // LDS of a migrate workgroup: the staged time windows (cap floats), per
 // block slot the trace geometry and window record (8 words), the chunk's
 // aperture table (16 * ks floats), the column tile's bounding box (4 floats
-// per wavefront, at most 16 wavefronts) and one pass's candidates (6 words
-// each, at most 64).
+// per wavefront, at most 16 wavefronts), one pass's candidates (6 words
+// each, at most 64) and the anti-alias table 1 / n^2.
 constexpr int kBoxFloats = 64;
 constexpr int kCandMax = 64;
 inline size_t migrate_lds_words(int cap, int tb, int ks) {
     return static_cast<size_t>(cap) + static_cast<size_t>(8) * tb + static_cast<size_t>(16) * ks + kBoxFloats +
-           static_cast<size_t>(6) * kCandMax;
+           static_cast<size_t>(6) * kCandMax + ((kAAMaxHalf + 2 + 3) & ~3);
 }
 inline size_t lds_bytes(const Params& P, int ks) { return migrate_lds_words(P.cap, P.tb, ks) * sizeof(float); }
 
-// Demigrate workgroups keep their rows as float64 next to the staged geometry.
+// Demigrate workgroups keep their rows as float64 next to the staged geometry
+// (and the anti-alias table 1 / n^2).
 inline size_t lds_bytes_f64rows(const Params& P) {
-    return (static_cast<size_t>(4) * P.tb + static_cast<size_t>(2) * P.tb * P.lt) * sizeof(float);
+    return (static_cast<size_t>(4) * P.tb + static_cast<size_t>(2) * P.tb * P.lt + ((kAAMaxHalf + 2 + 3) & ~3)) *
+           sizeof(float);
 }
 
 // migrate (km_migrate.hip)

@@ -44,6 +44,35 @@ __device__ __forceinline__ void stage_window_f(const Params& P, int64_t j, int l
     }
 }
 
+// Stage, for positions lo .. lo + len - 1 of trace j, the double running sum
+// I2[n] = sum_{m <= n} sum_{k <= m} D[k] (float64, from position lo; D zero
+// outside [0, nt)): the anti-alias triangles are second differences of it.
+// One wavefront: running sums over 64 positions at a time.
+__device__ __forceinline__ void stage_window_i2(const Params& P, int64_t j, int lo, int len, double* dst, int lane) {
+    const float sc = (P.dtype != F32 && P.scale) ? P.scale[j] : 1.0f;
+    double c1 = 0.0, c2 = 0.0;  // I1 and I2 at the position before the chunk
+    for (int e0 = 0; e0 < len; e0 += kLanes) {
+        const int e = e0 + lane;
+        double v = e < len ? static_cast<double>(trace_sample(P, j, lo + e, sc)) : 0.0;
+#pragma unroll
+        for (int off = 1; off < kLanes; off <<= 1) {
+            const double t = __shfl_up(v, off, kLanes);
+            if (lane >= off) v += t;
+        }
+        const double i1 = c1 + v;
+        double w = i1;
+#pragma unroll
+        for (int off = 1; off < kLanes; off <<= 1) {
+            const double t = __shfl_up(w, off, kLanes);
+            if (lane >= off) w += t;
+        }
+        const double i2 = c2 + w;
+        if (e < len) dst[e] = i2;
+        c1 = __shfl(i1, kLanes - 1, kLanes);
+        c2 = __shfl(i2, kLanes - 1, kLanes);
+    }
+}
+
 // Stage the window of samples lo .. lo + len - 1 of trace j as len - 1 pairs
 // dst[e] = (D[lo + e], D[lo + e + 1] - D[lo + e]): the interpolation then
 // reads one pair and needs one FMA.  One wavefront.
@@ -112,6 +141,41 @@ __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr
     acc1 += v1;
 }
 
+// Two slots with the anti-alias triangle filter.  row[n] = I2 at window
+// position n (staged by stage_window_i2): the smoothed sample at c is
+// alpha T_L(c) + beta T_{L+1}(c), T_L(c) = I2[c+L-1] - 2 I2[c-1] + I2[c-L-1],
+// read as five (n, n + 1) pairs for c = i and c = i + 1.
+template <bool TF, int WK>
+__device__ __forceinline__ float aa_value(const PairAA& p, const double* row) {
+    const int i = p.i, L = p.L;
+    const double a1 = row[i + L - 1], b1 = row[i + L];
+    const double a2 = row[i - 1], b2 = row[i];
+    const double a3 = row[i - L - 1], b3 = row[i - L];
+    const double b4 = row[i + L + 1];
+    const double a5 = row[i - L - 2];
+    // a4 = b1, b5 = a3
+    const double tl0 = fma(-2.0, a2, a1 + a3), tl1 = fma(-2.0, b2, b1 + b3);   // T_L(i), T_L(i + 1)
+    const double tm0 = fma(-2.0, a2, b1 + a5), tm1 = fma(-2.0, b2, b4 + a3);   // T_{L+1}(i), T_{L+1}(i + 1)
+    const double al = p.alpha, be = p.beta;
+    const double v0 = fma(be, tm0, al * tl0), v1 = fma(be, tm1, al * tl1);
+    return static_cast<float>(fma(static_cast<double>(p.f), v1 - v0, v0));
+}
+
+template <bool TF, int WK>
+__device__ __forceinline__ void mig_pair_aa(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
+                                            const double* row, float tfo, float wlo, float whi, float R0, float R1,
+                                            float dxs, float dys, float dxr, float dyr, float adx, float ady,
+                                            float lmax, const float* invsq, float& acc0, float& acc1) {
+    const PairAA p0 = eval_pair_aa<TF, WK>(A0, B0, hs2, hr2, tfo, wlo, whi, dxs, dys, dxr, dyr, adx, ady, lmax, invsq);
+    const PairAA p1 = eval_pair_aa<TF, WK>(A1, B1, hs2, hr2, tfo, wlo, whi, dxs, dys, dxr, dyr, adx, ady, lmax, invsq);
+    float v0 = aa_value<TF, WK>(p0, row);
+    float v1 = aa_value<TF, WK>(p1, row);
+    v0 = (hm <= R0) ? v0 : 0.0f;
+    v1 = (hm <= R1) ? v1 : 0.0f;
+    acc0 = (WK == W_COSCOS) ? fmaf(v0, p0.r, acc0) : acc0 + v0;
+    acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
+}
+
 // RREG: the masked slots take the lanes' aperture values from registers
 // (else from the LDS copy, which costs fewer registers).
 // TT: traveltime kind (TT_TABLE: one-way time table, W = 1).
@@ -135,8 +199,13 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     const int koff = TF ? kLead : 0;
     // staged form: (sample, difference) pairs for the square-root times (windows
     // of a few hundred samples), plain samples for the whole-record windows of
-    // table times (half the LDS per trace)
+    // table times (half the LDS per trace), float64 double running sums with
+    // the anti-alias filter
     constexpr bool PAIRS = TT == TT_DSR;
+    constexpr bool AA = TT == TT_AA;
+    // anti-aliasing: largest half-width, and the reach of a pair's reads around
+    // its sample (L + 2 below, L + 2 above counting the pair's second sample)
+    const int lmax = AA ? P.aa_max : 0;
 
     float* sTr = lds;                                                    // [cap]
     float4* sGeo = reinterpret_cast<float4*>(lds + P.cap);               // [tb]
@@ -145,6 +214,10 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     float* sBox = sR + KS * kGroup;                                      // [kBoxFloats]
     int2* sCand = reinterpret_cast<int2*>(sBox + kBoxFloats);            // [kCandMax]
     float4* sCandGeo = reinterpret_cast<float4*>(sBox + kBoxFloats + 2 * kCandMax);  // [kCandMax]
+    float* sInvSq = sBox + kBoxFloats + 6 * kCandMax;                    // [kAAMaxHalf + 2]: 1 / n^2
+    if (AA)
+        for (int t = threadIdx.x; t < kAAMaxHalf + 2; t += blockDim.x)
+            sInvSq[t] = t > 0 ? 1.0f / static_cast<float>(t * t) : 0.0f;
 
     ChunkTables<KS> T;
     load_chunk_tables<KS, 1, TT>(P, z0, d, WK == W_COSCOS, T, sR);
@@ -245,6 +318,11 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                 if (m <= reach) {
                     wl = first_lo;
                     len = nt + 2 - first_lo;  // samples first_lo .. nt + 1
+                    if (AA) {
+                        // positions -(2 lmax + 4) .. nt + 2 lmax + 4: every clamped sample's reads
+                        wl = -(2 * lmax + 4);
+                        len = nt + 4 * lmax + 9;
+                    }
                     if (windows) {
                         const float ms = box_far2(sr.x, sr.y, bx0, bx1, by0, by1);
                         const float mr = box_far2(sr.z, sr.w, bx0, bx1, by0, by1);
@@ -279,14 +357,26 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 umax = umax + tfo;
                             }
                             // sample indices, clamped before conversion
-                            const float cl = static_cast<float>(nt + 8);
-                            const int s0 = static_cast<int>(floorf(fminf(fmaxf(umin, -8.0f), cl))) - koff - 2;
-                            const int s1 = static_cast<int>(floorf(fminf(fmaxf(umax, -8.0f), cl))) - koff + 3;
-                            if (s0 > nt - 1 || s1 < 0) {
+                            const float clo = -static_cast<float>(2 * lmax + 16);
+                            const float chi = static_cast<float>(nt + 2 * lmax + 16);
+                            const int fmin = static_cast<int>(floorf(fminf(fmaxf(umin, clo), chi))) - koff;
+                            const int fmax = static_cast<int>(floorf(fminf(fmaxf(umax, clo), chi))) - koff;
+                            if (AA) {
+                                // reads reach lmax + 2 around the sample; the clamp range
+                                // [wl + lmax + 2, wh - lmax - 2] must hold the pairs' samples
+                                const int a0 = max(fmin - lmax - 4, -(2 * lmax + 4));
+                                const int a1 = min(fmax + lmax + 4, nt + 2 * lmax + 4);
+                                if (a0 + lmax + 2 > a1 - lmax - 2) {
+                                    len = 0;  // every triangle lies outside the record
+                                } else {
+                                    wl = a0;
+                                    len = a1 - a0 + 1;
+                                }
+                            } else if (fmin - 2 > nt - 1 || fmax + 3 < 0) {
                                 len = 0;  // every such time reads zeros: nothing to add
                             } else {
-                                wl = max(s0, first_lo);
-                                len = max(min(s1, nt + 1) - wl + 1, 2);
+                                wl = max(fmin - 2, first_lo);
+                                len = max(min(fmax + 3, nt + 1) - wl + 1, 2);
                             }
                         }
                     }
@@ -304,7 +394,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             if (lane < NG) {
                 const int2 c = sCand[lane];
                 cwl = c.x;
-                clen = c.y > 0 ? (PAIRS ? 2 * (c.y - 1) : c.y) : 0;
+                clen = c.y > 0 ? (AA ? 2 * c.y : PAIRS ? 2 * (c.y - 1) : c.y) : 0;
             }
             int plen = clen, pcnt = clen > 0 ? 1 : 0;  // inclusive prefix sums
 #pragma unroll
@@ -321,7 +411,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             if (wave == 0 && lane < k && clen > 0) {
                 const int slot = nb + pcnt - 1;
                 sGeo[slot] = sCandGeo[lane];
-                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + (PAIRS ? clen / 2 : clen - 1),
+                sMeta[slot] = make_int4(used + plen - clen, cwl,
+                                        cwl + (AA ? clen / 2 - 1 : PAIRS ? clen / 2 : clen - 1),
                                         static_cast<int>(jn + lane - lo));
             }
             if (k > 0) {
@@ -335,7 +426,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         __syncthreads();        // the block's slots
         for (int t = wave; t < nb; t += NW) {
             const int4 mt = sMeta[t];
-            if (PAIRS) stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<float2*>(sTr + mt.x), lane);
+            if (AA) stage_window_i2(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<double*>(sTr + mt.x), lane);
+            else if (PAIRS) stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<float2*>(sTr + mt.x), lane);
             else stage_window_f(P, lo + mt.w, mt.y, mt.z - mt.y + 1, sTr + mt.x, lane);
         }
         __syncthreads();
@@ -347,9 +439,9 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             const int ts = min(t0 + d, nb - 1);
             const float4 sr = sGeo[ts];
             const int4 mt = sMeta[ts];
-            const int lrow = (PAIRS ? mt.x / 2 : mt.x) - mt.y - koff;  // in pairs / floats
-            const float lwlo = static_cast<float>(mt.y + koff);
-            const float lwhi = static_cast<float>(mt.z - 1 + koff);
+            const int lrow = (PAIRS || AA ? mt.x / 2 : mt.x) - mt.y - koff;  // in pairs / doubles / floats
+            const float lwlo = static_cast<float>(mt.y + koff + (AA ? lmax + 2 : 0));
+            const float lwhi = static_cast<float>(mt.z - 1 + koff - (AA ? lmax + 1 : 0));
 #pragma unroll
             for (int q = 0; q < CWQ; ++q) {
                 const Legs Lp = legs(px[q], py[q], sr);
@@ -405,6 +497,21 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
                                 mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, tfo, wlo, whi, R0, R1, acc[q][k],
                                                          acc[q][k + 1]);
+                            }
+                        }
+                    } else if (AA) {
+                        // column minus source / receiver of trace tc, for the operator dip
+                        const float dxs = px[q] - uniform_read(sr.x, tc), dys = py[q] - uniform_read(sr.y, tc);
+                        const float dxr = px[q] - uniform_read(sr.z, tc), dyr = py[q] - uniform_read(sr.w, tc);
+                        const double* rowd = reinterpret_cast<const double*>(sTr) + rb;
+#pragma unroll
+                        for (int k = 0; k < KS; k += 2) {
+                            if ((any >> k) & 3ull) {
+                                const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
+                                const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
+                                mig_pair_aa<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, rowd, tfo,
+                                                    wlo, whi, R0, R1, dxs, dys, dxr, dyr, P.aa_dx, P.aa_dy,
+                                                    static_cast<float>(lmax), sInvSq, acc[q][k], acc[q][k + 1]);
                             }
                         }
                     } else {
@@ -510,6 +617,16 @@ static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
     if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
         if (P.has_tf) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
         return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
+    }
+    if (P.aa_max > 0) {  // anti-alias triangle filter
+        if (P.has_tf) {
+            if (P.weight == W_COSCOS)
+                return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS, TT_AA>, grid, block, lds, s, P);
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_AA>, grid, block, lds, s, P);
+        }
+        if (P.weight == W_COSCOS)
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_COSCOS, TT_AA>, grid, block, lds, s, P);
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_AA>, grid, block, lds, s, P);
     }
     if (P.has_tf) {
         if (P.weight == W_COSCOS) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS>, grid, block, lds, s, P);

@@ -15,7 +15,7 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmTtable, KmWeight, check
+from ._lib import KmAntialias, KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmTtable, KmWeight, check
 
 _DTYPES = {"f32": _lib.KM_F32, "bf16": _lib.KM_BF16, "f16": _lib.KM_F16}
 
@@ -51,6 +51,7 @@ class DeviceProblem:
     dtype: str = "f32"
     ttab: Optional[torch.Tensor] = None   # float32 [n_h, nz] one-way times: table traveltimes (W = 1)
     tdh: float = 0.0
+    aa: Optional[tuple] = None            # (dx, dy, max half-width): anti-alias triangle filter
 
     @property
     def n_traces(self) -> int:
@@ -98,6 +99,10 @@ class DeviceProblem:
     def c_weight(self) -> KmWeight:
         return KmWeight(kind=int(self.weight))
 
+    def c_aa(self) -> KmAntialias:
+        assert self.aa is not None
+        return KmAntialias(dx=float(self.aa[0]), dy=float(self.aa[1]), max_half=int(self.aa[2]))
+
     def c_table(self) -> KmTtable:
         assert self.ttab is not None and self.ttab.shape[1] == self.nz and self.ttab.is_contiguous()
         return KmTtable(n_h=int(self.ttab.shape[0]), dh=float(self.tdh), t=_ptr(self.ttab), r2=_ptr(self.r2))
@@ -125,6 +130,8 @@ def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DevicePr
                        r2=f32(problem.r2))
     if getattr(problem, "ttab", None) is not None:
         dp = dataclasses.replace(dp, ttab=f32(problem.ttab), tdh=float(problem.tdh))
+    if getattr(problem, "aa", None) is not None:
+        dp = dataclasses.replace(dp, aa=tuple(problem.aa))
     d = problem.data if data is None else data
     if d is None:
         return dp
@@ -156,6 +163,11 @@ def migrate(dp: DeviceProblem, data: Optional[torch.Tensor] = None, image: Optio
                                           _ptr(image), int(accumulate), int(tile),
                                           ctypes.c_void_p(_stream(dp.device))))
         return image
+    if dp.aa is not None:
+        check(lib.kirchhoff_migrate_aa(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
+                                       ctypes.byref(dp.c_weight()), ctypes.byref(dp.c_aa()), _ptr(image),
+                                       int(accumulate), int(tile), ctypes.c_void_p(_stream(dp.device))))
+        return image
     check(lib.kirchhoff_migrate(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
                                 ctypes.byref(dp.c_weight()), _ptr(image), int(accumulate), int(tile),
                                 ctypes.c_void_p(_stream(dp.device))))
@@ -176,6 +188,11 @@ def demigrate(dp: DeviceProblem, image: torch.Tensor, out: Optional[torch.Tensor
         check(lib.kirchhoff_demigrate_table(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_table()),
                                             ctypes.byref(tr), int(accumulate), int(tile),
                                             ctypes.c_void_p(_stream(dp.device))))
+        return out
+    if dp.aa is not None:
+        check(lib.kirchhoff_demigrate_aa(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
+                                         ctypes.byref(dp.c_weight()), ctypes.byref(dp.c_aa()), ctypes.byref(tr),
+                                         int(accumulate), int(tile), ctypes.c_void_p(_stream(dp.device))))
         return out
     check(lib.kirchhoff_demigrate(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
                                   ctypes.byref(dp.c_weight()), ctypes.byref(tr), int(accumulate), int(tile),

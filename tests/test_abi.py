@@ -209,3 +209,28 @@ def test_table_entry_points_reject_bad_tables(lib):
     big = _lib.KmTtable(n_h=1 << 30, dh=1.0, t=p, r2=p)
     assert lib.kirchhoff_migrate_table(ctypes.byref(t), ctypes.byref(g), ctypes.byref(big), p, 0, -1, None) == \
         _lib.KM_E_UNSUPPORTED
+
+
+def test_antialias_entry_points_reject_bad_options(lib):
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib)
+    p = ctypes.c_void_p(0x1000)
+    for aa, msg in [(None, b"NULL"), (_lib.KmAntialias(dx=-1.0, dy=0.0, max_half=4), b"dx and dy"),
+                    (_lib.KmAntialias(dx=10.0, dy=float("inf"), max_half=4), b"dx and dy"),
+                    (_lib.KmAntialias(dx=10.0, dy=float("nan"), max_half=4), b"dx and dy"),
+                    (_lib.KmAntialias(dx=10.0, dy=10.0, max_half=0), b"max_half"),
+                    (_lib.KmAntialias(dx=10.0, dy=10.0, max_half=33), b"max_half")]:
+        ref = ctypes.byref(aa) if aa is not None else None
+        assert lib.kirchhoff_migrate_aa(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), ref, p,
+                                        0, -1, None) == _lib.KM_E_INVALID
+        assert msg in lib.km_last_error()
+        assert lib.kirchhoff_demigrate_aa(p, ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), ref,
+                                          ctypes.byref(t), 0, -1, None) == _lib.KM_E_INVALID
+        assert msg in lib.km_last_error()
+    # the ordinary argument checks still apply
+    ok = _lib.KmAntialias(dx=10.0, dy=10.0, max_half=8)
+    t2, g2, tt2, w2 = _args(_lib, t__dt=0.0)
+    assert lib.kirchhoff_migrate_aa(ctypes.byref(t2), ctypes.byref(g2), ctypes.byref(tt2), ctypes.byref(w2),
+                                    ctypes.byref(ok), p, 0, -1, None) == _lib.KM_E_INVALID
+    assert b"dt" in lib.km_last_error()
