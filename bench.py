@@ -77,7 +77,8 @@ def main():
                     help="run one 1 GiB device-to-device copy before the workload (reference kernel for "
                          "hardware byte counters)")
     ap.add_argument("--workload", default="survey3d",
-                    choices=["survey3d", "survey3d_bf16", "survey3d_f16", "line2d_vz", "batch", "cig", "filter", "table"],
+                    choices=["survey3d", "survey3d_bf16", "survey3d_f16", "line2d_vz", "batch", "cig", "filter", "table",
+                             "aa"],
                     help="survey3d (default) is the headline; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:

@@ -8,6 +8,8 @@ line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
 batch: 64 uneven 2D lines migrated by one persistent hipGraph-captured launch
     against 64 separate launches (same tile shape, chosen by the tuner on the
     largest line), images compared bit for bit.
+aa: the 3D survey migrated and demigrated with the anti-alias triangle filter:
+    throughput of both operators and a sampled parity against the oracle.
 table: the 3D survey migrated and demigrated with curved-ray traveltime
     tables (v = 1500 + 0.5 z, h every 10 m) instead of the RMS double square
     root: throughput of both operators next to the table-gather rate.
@@ -20,6 +22,7 @@ cig: the offset stack and the common-image-gather moveout of the migrated 3D
 """
 from __future__ import annotations
 
+import dataclasses
 import time
 
 import numpy as np
@@ -226,7 +229,58 @@ def _table(steps, warmup, dev):
                          "table_gather_TBps": round(n_ap * 16 / (dom * 1e-3) / 1e12, 3)}}
 
 
+def _aa(steps, warmup, dev):
+    """The 3D survey with the anti-alias triangle filter (dip over the 12.5 m
+    image spacing in x and y, half-widths up to 8 samples)."""
+    from oracle import migrate_points
+
+    p = survey.make_survey3d(seed=2, device=dev)
+    pa = dataclasses.replace(p, aa=(12.5, 12.5, 8))
+    dp = ops.to_device(pa, dev)
+    n_ap, _ = ops.count(dp)
+    img = torch.empty(dp.image_shape, device=dev)
+    out = torch.empty((dp.n_traces, dp.n_t), device=dev)
+    ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
+    ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
+    # full-rate lane-ops per pair: the square-root pair (9 plus 3 transcendentals)
+    # and the filter: the dip (12: two legs' x and y slopes, the weighted sum,
+    # clamp, floor and fraction), the blend weights (5), addresses (3), four
+    # float64 second differences (8), blend and interpolation with widening and
+    # narrowing (8), less the plain interpolation (1): 44 + 5 transcendentals
+    t_fma, t_sqrt, t_rcp = ops.probe_issue(0), ops.probe_issue(1), ops.probe_issue(2)
+    r = 0.5 * (t_sqrt + t_rcp) / t_fma
+    c_k = 44 + 5 * r
+    peak = 256 * 64 * 2.4e9
+    dom = max(ms_m, ms_d)
+    # sampled parity of the migrated image against the FP64 oracle
+    rng = np.random.default_rng(0)
+    host = dataclasses.replace(pa, data=dp.data.cpu().numpy())
+    pts = np.stack([rng.integers(0, pa.n_bins, 64), rng.integers(0, len(pa.y), 64),
+                    rng.integers(0, len(pa.x), 64), rng.integers(0, len(pa.z), 64)], 1).astype(np.int32)
+    t0 = time.perf_counter()
+    ref = migrate_points(host, pts)
+    t_cpu = time.perf_counter() - t0
+    got = img[pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3]].cpu().numpy().astype(np.float64)
+    err = float(np.linalg.norm(got - ref) / max(np.linalg.norm(ref), 1e-300))
+    from oracle import threads as oracle_threads
+    return {"workload": "aa", "metric": "G contributions/s (migrate, demigrate; anti-alias triangle filter)",
+            "pairs_in_aperture": n_ap, "aa": list(pa.aa),
+            "ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
+            "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
+            "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
+            "roofline": {"bound": "alu", "achieved": round(n_ap * c_k / (dom * 1e-3) / 1e12, 3),
+                         "peak": round(peak / 1e12, 3), "unit": "TFLOP/s",
+                         "frac": round(n_ap * c_k / (dom * 1e-3) / peak, 4), "ops_per_pair": round(c_k, 3),
+                         "kernel": "migrate" if ms_m >= ms_d else "demigrate"},
+            "cpu_baseline": {"value": round(64 / t_cpu, 2), "unit": "image points/s", "cores": oracle_threads(),
+                             "kind": "oracle", "sample": "64 random image points against all traces of their bins"},
+            "gpu_image_points_per_s": round(pa.n_bins * len(pa.y) * len(pa.x) * len(pa.z) / ms_m * 1e3, 1),
+            "parity_sample_rel_l2": err}
+
+
 def run(workload, steps, warmup, dev):
+    if workload == "aa":
+        return _aa(steps, warmup, dev)
     if workload == "table":
         return _table(steps, warmup, dev)
     if workload == "filter":
