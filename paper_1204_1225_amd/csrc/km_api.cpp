@@ -194,10 +194,13 @@ int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demig
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
 // 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 8 slots x 1
 // trace quad, and 16 waves x 8 slots x 3 quads with table traveltimes, whose
-// table gathers favour more traces per workgroup).
-int default_shape(int op, int nz, bool table) {
+// table gathers favour more traces per workgroup).  With the anti-alias
+// filter: migrate 16 waves x 4 column groups x 8 slots (the largest trace
+// blocks), demigrate 8 waves x 4 slots x 1 quad.
+int default_shape(int op, int nz, bool table, bool aa = false) {
     (void)nz;
-    if (op == 0) return 2;
+    if (op == 0) return aa ? 1 : 2;
+    if (aa) return 3;
     return table ? 1 : 0;
 }
 
@@ -218,7 +221,7 @@ km_status pick_shape(int op, int tile, int dtype, int nz, int nt, bool table, in
             return KM_OK;
         }
     }
-    *shape = default_shape(op, nz, table);
+    *shape = default_shape(op, nz, table, aa);
     return KM_OK;
 }
 
