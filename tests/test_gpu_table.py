@@ -3,6 +3,8 @@ kirchhoff_demigrate_table, curved rays of v(z) = v0 + k z) against the FP64
 oracle's table path: ragged random cases on every tile, t_first != 0, the
 float32 dot-product test, the curved-ray diffractor line, and sampled points of
 the full 3D survey in the launch configuration of the benchmark."""
+import dataclasses
+
 import numpy as np
 import pytest
 import torch
@@ -108,3 +110,19 @@ def dataclasses_replace_data(p, data):
     import dataclasses
 
     return dataclasses.replace(p, data=data)
+
+
+def test_table_not_increasing_in_h_falls_back(ops, oracle_lib):
+    # A table whose rows dip at some offsets and depths (times that fall with
+    # h) still matches the oracle on every tile: migrate stages whole records
+    # for tables and derives no window from the time's growth with h.
+    p = table_problem(CASES[1])
+    t = p.ttab.copy()
+    t[3:6, 10:30] -= 0.02  # rows 3..5 fall below row 2 on these depths
+    q = dataclasses.replace(p, ttab=t)
+    assert np.any(np.diff(t, axis=0) < 0)
+    ref = oracle_lib.migrate(q)
+    dp = ops.to_device(q)
+    for tile in range(ops.tile_count(0)):
+        img = ops.migrate(dp, tile=tile).cpu().numpy()
+        assert rel_l2(img, ref) <= 1e-5, tile
