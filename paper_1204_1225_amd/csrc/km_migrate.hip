@@ -161,19 +161,17 @@ __device__ __forceinline__ float aa_value(const PairAA& p, const double* row) {
     return static_cast<float>(fma(static_cast<double>(p.f), v1 - v0, v0));
 }
 
+// One slot at a time (two in flight need more registers than the eight
+// float64 reads leave).
 template <bool TF, int WK>
-__device__ __forceinline__ void mig_pair_aa(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
-                                            const double* row, float tfo, float wlo, float whi, float R0, float R1,
-                                            float dxs, float dys, float dxr, float dyr, float adx, float ady,
-                                            float lmax, const float* invsq, float& acc0, float& acc1) {
-    const PairAA p0 = eval_pair_aa<TF, WK>(A0, B0, hs2, hr2, tfo, wlo, whi, dxs, dys, dxr, dyr, adx, ady, lmax, invsq);
-    const PairAA p1 = eval_pair_aa<TF, WK>(A1, B1, hs2, hr2, tfo, wlo, whi, dxs, dys, dxr, dyr, adx, ady, lmax, invsq);
-    float v0 = aa_value<TF, WK>(p0, row);
-    float v1 = aa_value<TF, WK>(p1, row);
-    v0 = (hm <= R0) ? v0 : 0.0f;
-    v1 = (hm <= R1) ? v1 : 0.0f;
-    acc0 = (WK == W_COSCOS) ? fmaf(v0, p0.r, acc0) : acc0 + v0;
-    acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
+__device__ __forceinline__ void mig_slot_aa(float A, float B, float hs2, float hr2, float hm, const double* row,
+                                            float tfo, float wlo, float whi, float R, float dxs, float dys, float dxr,
+                                            float dyr, float adx, float ady, float lmax, const float* invsq,
+                                            float& acc) {
+    const PairAA p = eval_pair_aa<TF, WK>(A, B, hs2, hr2, tfo, wlo, whi, dxs, dys, dxr, dyr, adx, ady, lmax, invsq);
+    float v = aa_value<TF, WK>(p, row);
+    v = (hm <= R) ? v : 0.0f;
+    acc = (WK == W_COSCOS) ? fmaf(v, p.r, acc) : acc + v;
 }
 
 // RREG: the masked slots take the lanes' aperture values from registers
@@ -505,13 +503,12 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                         const float dxr = px[q] - uniform_read(sr.z, tc), dyr = py[q] - uniform_read(sr.w, tc);
                         const double* rowd = reinterpret_cast<const double*>(sTr) + rb;
 #pragma unroll
-                        for (int k = 0; k < KS; k += 2) {
-                            if ((any >> k) & 3ull) {
-                                const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
-                                const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair_aa<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm, rowd, tfo,
-                                                    wlo, whi, R0, R1, dxs, dys, dxr, dyr, P.aa_dx, P.aa_dy,
-                                                    static_cast<float>(lmax), sInvSq, acc[q][k], acc[q][k + 1]);
+                        for (int k = 0; k < KS; ++k) {
+                            if ((any >> k) & 1ull) {
+                                const float R = RREG ? T.R[k] : sR[k * kGroup + d];
+                                mig_slot_aa<TF, WK>(T.A[k], T.B[k], hs2, hr2, hm, rowd, tfo, wlo, whi, R, dxs, dys, dxr,
+                                                    dyr, P.aa_dx, P.aa_dy, static_cast<float>(lmax), sInvSq,
+                                                    acc[q][k]);
                             }
                         }
                     } else {
