@@ -43,9 +43,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "e7b7a46bd65135b08131a2746b6e7b5e6500ae874d3e8422c2dfd1816199c643",
-    "migrate": 9.1697e10,
-    "demigrate": 3.2723e12,
+    "sources_sha256": "ba57d31965b702b7e63c7654cfeab53f03e494cbd6e796c2adb91912f175cfc8",
+    "migrate": 9.1541e10,
+    "demigrate": 3.2707e12,
 }
 
 
