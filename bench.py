@@ -43,7 +43,7 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "ba57d31965b702b7e63c7654cfeab53f03e494cbd6e796c2adb91912f175cfc8",
+    "sources_sha256": "5b947101576e9119d265cbfa59fe6bd2f0654c717ae78b9b8320df80c51d14dd",
     "migrate": 9.1541e10,
     "demigrate": 3.2707e12,
 }

@@ -11,8 +11,11 @@
 // traces at once (lane = (column, trace)), hands them to the depth lanes
 // through the LDS crossbar, derives from a ballot which 16-depth slots can
 // hold a pair inside the aperture, and evaluates those slots two at a time:
-// per lane two square roots, the sample index and fraction, a two-sample LDS
-// gather, the interpolation, the weight and the lane's aperture mask.
+// per lane two square roots, the sample index and fraction, one 8-byte LDS
+// read of the staged (sample, difference) pair, the interpolation, the weight
+// and the lane's aperture mask.  Table times and the anti-alias filter use
+// the same blocks with their own staged forms (plain samples; float64 double
+// running sums, one slot at a time).
 #include "km_kernels.h"
 
 namespace km {
