@@ -12,7 +12,8 @@ pair inside the aperture (Eq. (2)), counted exactly by the counting kernel;
 value = 2 * pairs / step time.
 
 Also reported: a roofline object for the dominant kernel (VALU bound; the
-transcendental issue cost is measured live by the issue-rate probe) and the
+transcendental issue cost is measured live by the issue-rate probe; for the
+adjoint also its LDS float64 atomic rate against the measured issue rate) and the
 FP64 oracle timed on this host's cores on a bounded sample of image columns,
 whose GPU values are checked against the oracle on the way.
 """
@@ -169,6 +170,14 @@ def main():
                 "frac": round(achieved / peak, 4), "traffic": traffic, "kernel": dom,
                 "ops_per_pair": round(c_k, 3), "transcendental_cost_slots": round(r, 3),
                 "kernel_ms": round(dom_ms, 3)}
+    if dom == "demigrate":
+        # the adjoint's second resource: 2 float64 LDS atomic adds per pair against
+        # the measured issue rate of one wavefront ds_add_f64 per 8.3 clocks per CU
+        lds_peak = 256 * 64 / 8.3 * 2.4e9
+        lds_achieved = 2.0 * n_ap / (dom_ms * 1e-3)
+        roofline["co_bound"] = {"resource": "LDS float64 atomics", "per_pair": 2,
+                                "achieved": round(lds_achieved / 1e12, 3), "peak": round(lds_peak / 1e12, 3),
+                                "unit": "T lane-atomics/s", "frac": round(lds_achieved / lds_peak, 4)}
 
     cpu = None
     parity = None
