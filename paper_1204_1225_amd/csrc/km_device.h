@@ -164,11 +164,13 @@ __device__ __forceinline__ PairAA eval_pair_aa(float A, float B, float hs2, floa
     float w = ss + sr;
     if (TF) w = w + tf_off;
     w = __builtin_amdgcn_fmed3f(w, wlo, whi);
+    const float is = __builtin_amdgcn_rcpf(ss), ir = __builtin_amdgcn_rcpf(sr);
     PairAA p;
     p.i = static_cast<int32_t>(w);
     p.f = __builtin_amdgcn_fractf(w);
-    p.r = (WK == W_COSCOS) ? __builtin_amdgcn_rcpf(as * ar) : 1.0f;
-    const float is = __builtin_amdgcn_rcpf(ss), ir = __builtin_amdgcn_rcpf(sr);
+    // 1 / (a_s a_r) from the legs' reciprocals the dip needs anyway
+    const float g = is * ir;
+    p.r = (WK == W_COSCOS) ? g * g : 1.0f;
     const float ux = B * fmaf(dxs, is, dxr * ir);
     const float uy = B * fmaf(dys, is, dyr * ir);
     // a NaN (zero leg time) takes the lower bound: no smoothing

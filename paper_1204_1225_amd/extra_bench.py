@@ -242,14 +242,16 @@ def _aa(steps, warmup, dev):
     out = torch.empty((dp.n_traces, dp.n_t), device=dev)
     ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
     ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
-    # full-rate lane-ops per pair: the square-root pair (9 plus 3 transcendentals)
-    # and the filter: the dip (12: two legs' x and y slopes, the weighted sum,
-    # clamp, floor and fraction), the blend weights (5), addresses (3), four
-    # float64 second differences (8), blend and interpolation with widening and
-    # narrowing (8), less the plain interpolation (1): 44 + 5 transcendentals
+    # full-rate lane-ops per pair: the square-root pair (10 plus 2 square roots;
+    # its weight 1 / (a_s a_r) is the square of the product of the dip's two leg
+    # reciprocals) and the filter: the dip (12: two legs' x and y slopes, the
+    # weighted sum, clamp, floor and fraction, plus 2 reciprocals), the blend
+    # weights (5), addresses (3), four float64 second differences (8), blend and
+    # interpolation with widening and narrowing (8), less the plain
+    # interpolation (1): 45 + 4 transcendentals
     t_fma, t_sqrt, t_rcp = ops.probe_issue(0), ops.probe_issue(1), ops.probe_issue(2)
     r = 0.5 * (t_sqrt + t_rcp) / t_fma
-    c_k = 44 + 5 * r
+    c_k = 45 + 4 * r
     peak = 256 * 64 * 2.4e9
     dom = max(ms_m, ms_d)
     # sampled parity of the migrated image against the FP64 oracle
