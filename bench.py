@@ -44,9 +44,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "cf39681ad47e7332b4e230781d5c8f9256f76022d3c3c58842fc35e1519c71ac",
-    "migrate": 9.0867e10,
-    "demigrate": 3.2716e12,
+    "sources_sha256": "2b0d50ba83511fb47b80ee26aa83e1eef9c3fa424b69e05c2cde6442535472e7",
+    "migrate": 9.0419e10,
+    "demigrate": 3.1404e12,
 }
 
 

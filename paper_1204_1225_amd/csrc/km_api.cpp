@@ -192,7 +192,7 @@ std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
 int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
-// 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 8 slots x 1
+// 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 4 slots x 1
 // trace quad, and 16 waves x 8 slots x 3 quads with table traveltimes, whose
 // table gathers favour more traces per workgroup).  With the anti-alias
 // filter: migrate 16 waves x 4 column groups x 8 slots (the largest trace
@@ -201,7 +201,7 @@ int default_shape(int op, int nz, bool table, bool aa = false) {
     (void)nz;
     if (op == 0) return aa ? 1 : 2;
     if (aa) return 3;
-    return table ? 1 : 0;
+    return table ? 1 : 3;
 }
 
 // The tuning cache is keyed without the traveltime kind or the anti-alias

@@ -294,8 +294,12 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     }
 }
 
+// The 4-slot square-root kernel is held to 6 wavefronts per SIMD (80 VGPRs, no
+// spills): with 8-wavefront one-quad workgroups that is three workgroups per
+// CU, as many as their LDS rows allow.  The other kernels need more registers.
 template <int NW, int KS, int NQ, bool TF, int WK, int TT = TT_DSR>
-__global__ __launch_bounds__(NW * 64) void demigrate_kernel(Params P) {
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KS <= 4 && TT == TT_DSR ? 6 : 1)))
+void demigrate_kernel(Params P) {
     extern __shared__ float lds[];
     double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
     float4* sGeo = reinterpret_cast<float4*>(lds + 2 * P.tb * P.lt);   // [tb]
@@ -392,10 +396,11 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
 }
 
 // (waves, depth slots, trace quads per workgroup, LDS budget for the trace
-// accumulators).  The first is the default: one quad of traces per 8-wavefront
-// workgroup, so that two workgroups share a CU; measured faster than 12 traces
-// per 16-wavefront workgroup (one per CU), although each workgroup then reads
-// its box of image columns for 4 traces instead of 12.
+// accumulators).  The fourth is the default: one quad of traces per
+// 8-wavefront workgroup with 4 slots, so that three workgroups share a CU (the
+// first, with 8 slots, fits two); one-quad workgroups measured faster than 12
+// traces per 16-wavefront workgroup (one per CU), although each workgroup then
+// reads its box of image columns for 4 traces instead of 12.
 #define KM_DEMIGRATE_SHAPES(X) \
     X(8, 8, 1, 49152)          \
     X(16, 8, 3, 147456)        \
