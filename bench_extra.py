@@ -1,5 +1,12 @@
 """Measurements of the non-headline workloads (each returns one JSON-able dict).
 
+Imported by bench.py only (next to it, outside the library package: the
+cpu_baseline and parity legs here run the FP64 oracle).
+
+survey3d_ext: the 3D survey with the extended-precision total time
+    (KM_TIME_EXTENDED): both operators' throughput next to the float32 time on
+    the same GPU, and each one's sampled parity against the oracle.
+
 survey3d_bf16 / survey3d_f16: the 3D survey with 16-bit trace storage
     (per-trace scale), migrate-only throughput next to float32 on the same GPU.
 line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
@@ -23,12 +30,21 @@ cig: the offset stack and the common-image-gather moveout of the migrated 3D
 from __future__ import annotations
 
 import dataclasses
+import os
 import time
 
 import numpy as np
 import torch
 
-from . import ops, survey
+from paper_1204_1225_amd import ops, survey
+
+PEAK_VALU_LANE_OPS = 256 * 64 * 2.4e9  # unpacked VALU issue: 256 CUs x 64 lanes/clk x 2.4 GHz
+# L2 read bandwidth: 16 channels x 128 B/clk per XCD, 8 XCDs, 2.4 GHz
+PEAK_L2_BYTES = 16 * 128 * 8 * 2.4e9
+
+
+def host_cpus():
+    return len(os.sched_getaffinity(0))
 
 
 def _time(fn, steps, warmup):
@@ -117,8 +133,6 @@ HBM_PEAK = 8.0e12  # bytes/s
 
 
 def _cig(steps, warmup, dev, max_lag=12):
-    import os
-
     from oracle import cig as ocig
 
     p = survey.make_survey3d(seed=2, device=dev)
@@ -165,7 +179,7 @@ def _cig(steps, warmup, dev, max_lag=12):
                              "sample": f"moveout of {n_s} random columns x {nb} bins x {nz} depths, lag +-{max_lag}"},
             "gpu_columns_per_s": round(ny * nx / ms_cig * 1e3, 1),
             "parity_sample_max_shift_err": err, "parity_sample_clear_frac": round(float(clear.mean()), 4),
-            "cpu_count": os.cpu_count()}
+            "host_cpus": host_cpus()}
 
 
 def _filter(steps, warmup, dev):
@@ -205,28 +219,34 @@ def _table(steps, warmup, dev):
     p = survey.make_survey3d(seed=2, device=dev)
     pt = survey.with_curved_ray_table(p, dh=10.0)
     dp = ops.to_device(pt, dev)
-    n_ap, _ = ops.count(dp)
+    n_ap, _ = ops.count(dp, aperture_only=True)
     img = torch.empty(dp.image_shape, device=dev)
     out = torch.empty((dp.n_traces, dp.n_t), device=dev)
     ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
     ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
-    # minimal full-rate lane-ops per pair of the table evaluation once the legs are
-    # hoisted: per leg 2 widenings + 1 float64 FMA (6), sum + scale + 2 clamps (4),
-    # index, fraction and its narrowing (3), row address, interpolation (2) and
-    # accumulate (1) = 17; the pair also reads 4 table values (16 bytes) from L2
+    # Two resources per pair once the legs are hoisted.  The table gathers:
+    # 4 float32 values (16 bytes: two rows of each leg at the lane's depth), read
+    # through the L2 (the tables are 565 KB, resident in every XCD's 4 MB L2).
+    # The VALU: per leg 2 widenings + 1 float64 FMA (6), sum + scale + 2 clamps
+    # (4), index, fraction and its narrowing (3), row address, interpolation (2)
+    # and accumulate (1) = 17 full-rate lane-ops.
     c_k = 17
-    peak = 256 * 64 * 2.4e9
+    table_bytes = 16
     dom = max(ms_m, ms_d)
+    gather = n_ap * table_bytes / (dom * 1e-3)
+    valu = n_ap * c_k / (dom * 1e-3)
     return {"workload": "table", "metric": "G contributions/s (migrate, demigrate; curved-ray tables)",
             "pairs_in_aperture": n_ap, "table_shape": list(pt.ttab.shape),
             "ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
             "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
             "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
-            "roofline": {"bound": "alu", "achieved": round(n_ap * c_k / (dom * 1e-3) / 1e12, 3),
-                         "peak": round(peak / 1e12, 3), "unit": "TFLOP/s",
-                         "frac": round(n_ap * c_k / (dom * 1e-3) / peak, 4), "ops_per_pair": c_k,
+            "roofline": {"bound": "l2_gather", "achieved": round(gather / 1e12, 3),
+                         "peak": round(PEAK_L2_BYTES / 1e12, 3), "unit": "TB/s",
+                         "frac": round(gather / PEAK_L2_BYTES, 4), "bytes_per_pair": table_bytes,
                          "kernel": "migrate" if ms_m >= ms_d else "demigrate",
-                         "table_gather_TBps": round(n_ap * 16 / (dom * 1e-3) / 1e12, 3)}}
+                         "co_bound": {"resource": "VALU", "ops_per_pair": c_k, "achieved": round(valu / 1e12, 3),
+                                      "peak": round(PEAK_VALU_LANE_OPS / 1e12, 3), "unit": "T lane-ops/s",
+                                      "frac": round(valu / PEAK_VALU_LANE_OPS, 4)}}}
 
 
 def _aa(steps, warmup, dev):
@@ -237,7 +257,7 @@ def _aa(steps, warmup, dev):
     p = survey.make_survey3d(seed=2, device=dev)
     pa = dataclasses.replace(p, aa=(12.5, 12.5, 8))
     dp = ops.to_device(pa, dev)
-    n_ap, _ = ops.count(dp)
+    n_ap, _ = ops.count(dp, aperture_only=True)
     img = torch.empty(dp.image_shape, device=dev)
     out = torch.empty((dp.n_traces, dp.n_t), device=dev)
     ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
@@ -252,7 +272,7 @@ def _aa(steps, warmup, dev):
     t_fma, t_sqrt, t_rcp = ops.probe_issue(0), ops.probe_issue(1), ops.probe_issue(2)
     r = 0.5 * (t_sqrt + t_rcp) / t_fma
     c_k = 45 + 4 * r
-    peak = 256 * 64 * 2.4e9
+    peak = PEAK_VALU_LANE_OPS
     dom = max(ms_m, ms_d)
     # sampled parity of the migrated image against the FP64 oracle
     rng = np.random.default_rng(0)
@@ -271,16 +291,49 @@ def _aa(steps, warmup, dev):
             "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
             "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
             "roofline": {"bound": "alu", "achieved": round(n_ap * c_k / (dom * 1e-3) / 1e12, 3),
-                         "peak": round(peak / 1e12, 3), "unit": "TFLOP/s",
+                         "peak": round(peak / 1e12, 3), "unit": "T lane-ops/s",
                          "frac": round(n_ap * c_k / (dom * 1e-3) / peak, 4), "ops_per_pair": round(c_k, 3),
                          "kernel": "migrate" if ms_m >= ms_d else "demigrate"},
             "cpu_baseline": {"value": round(64 / t_cpu, 2), "unit": "image points/s", "cores": oracle_threads(),
-                             "kind": "oracle", "sample": "64 random image points against all traces of their bins"},
+                             "host_cpus": host_cpus(), "kind": "oracle",
+                             "sample": "64 random image points against all traces of their bins"},
             "gpu_image_points_per_s": round(pa.n_bins * len(pa.y) * len(pa.x) * len(pa.z) / ms_m * 1e3, 1),
             "parity_sample_rel_l2": err}
 
 
+def _ext(steps, warmup, dev):
+    """The 3D survey with the extended-precision total time against the float32
+    time: both operators, and 300 sampled image points of each against the
+    oracle."""
+    from oracle import migrate_points
+
+    p = survey.make_survey3d(seed=2, device=dev)
+    dp32 = ops.to_device(p, dev)
+    dpx = dp32.with_precision("extended")
+    n_ap, _ = ops.count(dp32)
+    img = torch.empty(dp32.image_shape, device=dev)
+    out = torch.empty((dp32.n_traces, dp32.n_t), device=dev)
+    rng = np.random.default_rng(5)
+    pts = np.stack([rng.integers(0, p.n_bins, 300), rng.integers(0, 256, 300), rng.integers(0, 256, 300),
+                    rng.integers(0, 400, 300)], 1).astype(np.int32)
+    host = dataclasses.replace(p, data=dp32.data.cpu().numpy())
+    ref = migrate_points(host, pts)
+    res = {}
+    for name, dp in [("fp32", dp32), ("extended", dpx)]:
+        ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
+        got = img[pts[:, 0], pts[:, 1], pts[:, 2], pts[:, 3]].double().cpu().numpy()
+        ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
+        res[name] = {"ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
+                     "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
+                     "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
+                     "parity_sample_rel_l2": float(np.linalg.norm(got - ref) / np.linalg.norm(ref))}
+    return {"workload": "survey3d_ext", "metric": "G contributions/s (migrate + adjoint), float32 vs extended time",
+            "pairs_in_aperture": n_ap, **res}
+
+
 def run(workload, steps, warmup, dev):
+    if workload == "survey3d_ext":
+        return _ext(steps, warmup, dev)
     if workload == "aa":
         return _aa(steps, warmup, dev)
     if workload == "table":

@@ -11,11 +11,12 @@ import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libkirchhoff.so")
-ABI_VERSION = 1
+ABI_VERSION = 2
 
 KM_OK, KM_E_INVALID, KM_E_UNSUPPORTED, KM_E_HIP, KM_E_NOMEM = range(5)
 KM_F32, KM_BF16, KM_F16 = 0, 1, 2
 KM_W_UNIT, KM_W_COSCOS_OVER_TT = 0, 1
+KM_TIME_FP32, KM_TIME_EXTENDED = 0, 1
 
 _vp = ctypes.c_void_p
 _i32, _i64, _f64 = ctypes.c_int32, ctypes.c_int64, ctypes.c_double
@@ -32,11 +33,11 @@ class KmGrid(ctypes.Structure):
 
 
 class KmTraveltime(ctypes.Structure):
-    _fields_ = [("t0sq", _vp), ("s2", _vp), ("r2", _vp)]
+    _fields_ = [("t0sq", _vp), ("s2", _vp), ("r2", _vp), ("time_precision", _i32)]
 
 
 class KmTtable(ctypes.Structure):
-    _fields_ = [("n_h", _i32), ("dh", _f64), ("t", _vp), ("r2", _vp)]
+    _fields_ = [("n_h", _i32), ("dh", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32)]
 
 
 class KmAntialias(ctypes.Structure):

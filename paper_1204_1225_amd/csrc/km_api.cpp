@@ -79,6 +79,8 @@ km_status check_grid(const km_grid* g, const km_traveltime* tt, const km_weight*
     if (g->n_bins > 65535) return fail(KM_E_UNSUPPORTED, "%s: n_bins > 65535", who);
     if (w->kind != KM_W_UNIT && w->kind != KM_W_COSCOS_OVER_TT)
         return fail(KM_E_INVALID, "%s: unknown weight kind %d", who, w->kind);
+    if (tt->time_precision != KM_TIME_FP32 && tt->time_precision != KM_TIME_EXTENDED)
+        return fail(KM_E_INVALID, "%s: unknown time precision %d", who, tt->time_precision);
     const bool empty = g->nx == 0 || g->ny == 0 || g->nz == 0 || g->n_bins == 0;
     if (!empty) {
         if (!g->x || !g->y) return fail(KM_E_INVALID, "%s: x and y must be non-NULL", who);
@@ -118,6 +120,9 @@ km::Params base_params(const km_traces* t, const km_grid* g, const km_traveltime
     P.wscale = P.inv_dt2 * P.inv_dt2;
     P.has_tf = t->t_first != 0.0 ? 1 : 0;
     P.tf_off = static_cast<float>(km::kLead - t->t_first / t->dt);
+    P.tf_off_d = km::kLead - t->t_first / t->dt;
+    P.inv_dt = 1.0 / t->dt;
+    P.prec = tt->time_precision == KM_TIME_EXTENDED ? 1 : 0;
     P.weight = w->kind;
     P.image = image;
     P.accumulate = accumulate ? 1 : 0;
@@ -242,8 +247,7 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         P.ttab = tab->t;
         P.n_h = tab->n_h;
         P.inv_dh = static_cast<float>(1.0 / tab->dh);
-        P.inv_dt = 1.0 / t->dt;
-        P.tf_off_d = km::kLead - t->t_first / t->dt;
+        P.inv_dh_d = 1.0 / tab->dh;
         P.t0sq = nullptr;
         P.s2 = nullptr;
         P.r2 = tab->r2;
@@ -319,6 +323,12 @@ km_status check_antialias(const km_antialias* aa, const char* who) {
     return KM_OK;
 }
 
+km_status check_antialias_tt(const km_traveltime* tt, const char* who) {
+    if (tt && tt->time_precision == KM_TIME_EXTENDED)
+        return fail(KM_E_UNSUPPORTED, "%s: the anti-alias operators evaluate float32 times only", who);
+    return KM_OK;
+}
+
 // Table traveltimes: validate the table, then run the shared path with the
 // table in place of t0sq / s2 (only r2 of the traveltime struct is read).
 km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who) {
@@ -360,7 +370,7 @@ km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, 
                                   int32_t accumulate, int32_t tile, void* stream) {
     km_status st = check_table(tab, grid, "kirchhoff_migrate_table");
     if (st != KM_OK) return st;
-    const km_traveltime tt{tab->r2, tab->r2, tab->r2};
+    const km_traveltime tt{tab->r2, tab->r2, tab->r2, tab->time_precision};
     const km_weight w{KM_W_UNIT};
     return migrate_impl(traces, grid, &tt, &w, image, accumulate, tile, stream, tab);
 }
@@ -369,7 +379,7 @@ km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, con
                                     const km_traces* out, int32_t accumulate, int32_t tile, void* stream) {
     km_status st = check_table(tab, grid, "kirchhoff_demigrate_table");
     if (st != KM_OK) return st;
-    const km_traveltime tt{tab->r2, tab->r2, tab->r2};
+    const km_traveltime tt{tab->r2, tab->r2, tab->r2, tab->time_precision};
     const km_weight w{KM_W_UNIT};
     return demigrate_impl(image, grid, &tt, &w, out, accumulate, tile, stream, tab);
 }
@@ -378,6 +388,7 @@ km_status kirchhoff_migrate_aa(const km_traces* traces, const km_grid* grid, con
                                const km_weight* weight, const km_antialias* aa, float* image, int32_t accumulate,
                                int32_t tile, void* stream) {
     km_status st = check_antialias(aa, "kirchhoff_migrate_aa");
+    if (st == KM_OK) st = check_antialias_tt(tt, "kirchhoff_migrate_aa");
     if (st != KM_OK) return st;
     return migrate_impl(traces, grid, tt, weight, image, accumulate, tile, stream, nullptr, aa);
 }
@@ -386,6 +397,7 @@ km_status kirchhoff_demigrate_aa(const float* image, const km_grid* grid, const 
                                  const km_weight* weight, const km_antialias* aa, const km_traces* out,
                                  int32_t accumulate, int32_t tile, void* stream) {
     km_status st = check_antialias(aa, "kirchhoff_demigrate_aa");
+    if (st == KM_OK) st = check_antialias_tt(tt, "kirchhoff_demigrate_aa");
     if (st != KM_OK) return st;
     return demigrate_impl(image, grid, tt, weight, out, accumulate, tile, stream, nullptr, aa);
 }
@@ -577,7 +589,7 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
 struct km_batch {
     int device = 0;
     int shape = 0;
-    int has_tf = 0, weight = 0;
+    int has_tf = 0, weight = 0, prec = 0;
     km::Params* d_probs = nullptr;
     int4* d_items = nullptr;
     unsigned int* d_counter = nullptr;
@@ -613,8 +625,10 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
         if (!probs[i].image || !aligned(probs[i].image, 4))
             return fail(KM_E_INVALID, "km_batch_create: problem %d image NULL/misaligned", i);
         if ((probs[i].traces.t_first != 0.0) != (probs[0].traces.t_first != 0.0) ||
-            probs[i].weight.kind != probs[0].weight.kind)
-            return fail(KM_E_UNSUPPORTED, "km_batch_create: all problems must share the weight kind and t_first == 0 or not");
+            probs[i].weight.kind != probs[0].weight.kind || probs[i].tt.time_precision != probs[0].tt.time_precision)
+            return fail(KM_E_UNSUPPORTED,
+                        "km_batch_create: all problems must share the weight kind, the time precision and "
+                        "t_first == 0 or not");
     }
     int max_nz = 0, max_nt = 0;
     for (int i = 0; i < n; ++i) {
@@ -632,6 +646,7 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
     B->shape = shape;
     B->has_tf = probs[0].traces.t_first != 0.0 ? 1 : 0;
     B->weight = probs[0].weight.kind;
+    B->prec = probs[0].tt.time_precision == KM_TIME_EXTENDED ? 1 : 0;
 
     std::vector<km::Params> P(n);
     struct Item {
@@ -700,7 +715,7 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
     }
 
     // Persistent grid: as many workgroups as can be resident at once.
-    const void* kfn = km::migrate_batch_kernel_ptr(shape, B->has_tf, B->weight);
+    const void* kfn = km::migrate_batch_kernel_ptr(shape, B->has_tf, B->weight, B->prec);
     if (B->lds > 65536) hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(B->lds));
     int per_cu = 0, n_cu = 0;
     e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S.waves * 64, B->lds);
@@ -720,7 +735,8 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void
     if (e == hipSuccess) {
         hipError_t e1 = km::launch_reset_counter(B->d_counter, cap);
         hipError_t e2 = e1 == hipSuccess ? km::launch_migrate_batch(shape, B->d_probs, B->d_items, B->n_items,
-                                                                      B->d_counter, B->has_tf, B->weight, B->n_wg,
+                                                                      B->d_counter, B->has_tf, B->weight, B->prec,
+                                                                      B->n_wg,
                                                                       B->lds, cap)
                                          : e1;
         e = hipStreamEndCapture(cap, &B->graph);

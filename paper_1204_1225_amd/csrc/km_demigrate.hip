@@ -74,6 +74,48 @@ __device__ __forceinline__ void dem_masked(float A0, float B0, float A1, float B
     }
 }
 
+// dem_masked with the extended-precision time (eval_pair_ext); the two taps
+// are formed in float64 from the float64 fraction.
+template <bool TF, int WK>
+__device__ __forceinline__ void dem_masked_ext(float A0, float B0, float A1, float B1, double Hs, double Hr,
+                                               double* row, double inv_dt, double tfo, int ilo, int ihi, double wlo,
+                                               double whi, float x0, float x1, bool act0, bool act1) {
+    if (act0) {
+        const PairX p0 = eval_pair_ext<TF, WK>(A0, B0, Hs, Hr, inv_dt, tfo, ilo, ihi, wlo, whi);
+        const double q0 = static_cast<double>((WK == W_COSCOS) ? x0 * p0.r : x0);
+        const double b0 = p0.fd * q0;
+        atomicAdd(row + p0.i, q0 - b0);
+        atomicAdd(row + p0.i + 1, b0);
+    }
+    if (act1) {
+        const PairX p1 = eval_pair_ext<TF, WK>(A1, B1, Hs, Hr, inv_dt, tfo, ilo, ihi, wlo, whi);
+        const double q1 = static_cast<double>((WK == W_COSCOS) ? x1 * p1.r : x1);
+        const double b1 = p1.fd * q1;
+        atomicAdd(row + p1.i, q1 - b1);
+        atomicAdd(row + p1.i + 1, b1);
+    }
+}
+
+// dem_pair_table with extended legs (table_leg_ext).
+template <bool TF>
+__device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, int iz0, int iz1, double* row,
+                                                   float wlo, float whi, float x0, float x1, bool act0, bool act1) {
+    if (act0) {
+        const PairX p0 = eval_pair_table_ext<TF>(P, Ls, Lr, iz0, wlo, whi);
+        const double q0 = static_cast<double>(x0);
+        const double b0 = p0.fd * q0;
+        atomicAdd(row + p0.i, q0 - b0);
+        atomicAdd(row + p0.i + 1, b0);
+    }
+    if (act1) {
+        const PairX p1 = eval_pair_table_ext<TF>(P, Ls, Lr, iz1, wlo, whi);
+        const double q1 = static_cast<double>(x1);
+        const double b1 = p1.fd * q1;
+        atomicAdd(row + p1.i, q1 - b1);
+        atomicAdd(row + p1.i + 1, b1);
+    }
+}
+
 // dem_masked with table traveltimes (W = 1); iz0, iz1 are the lane's depths
 // of the two slots, clamped into the table.
 template <bool TF, bool MASKED>
@@ -140,7 +182,7 @@ __device__ __forceinline__ void fetch_column(const Params& P, const float* img, 
 // One depth chunk of the segment: wavefront `wave` takes the box columns
 // wave, wave + NW, ... in row-major order and scatters every pairing of a
 // column with the segment's traces into their rows.
-template <int NW, int KS, int NQ, bool TF, int WK, bool TAIL, int TT>
+template <int NW, int KS, int NQ, bool TF, int WK, bool TAIL, int TT, bool PX>
 __device__ __forceinline__ void sweep_columns(const Params& P, const float* img, int z0, int d, int g, int wave, int t0,
                                               int nseg, int nq, int ix0, int ix1, int iy0, int iy1,
                                               const ChunkTables<KS>& T, const float* S, const float4* G, double* sAcc,
@@ -150,6 +192,9 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
     float wlo, whi;
     clamp_bounds<TF>(P.lt, wlo, whi);
     const float tfo = P.tf_off;
+    const double tfod = P.tf_off_d;
+    const int ilo = static_cast<int>(wlo), ihi = static_cast<int>(whi);
+    const double wlod = wlo, whid = whi;
     int rowoff = TF ? 0 : kLead;
     const int lmax = AA ? P.aa_max : 0;
     if (AA) {
@@ -192,6 +237,8 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
             const uint32_t any = fold_or(__builtin_amdgcn_ballot_w64(L.hmax <= T.rhi)) & kMask;
             if (!any) continue;
             double* row = rows[q];
+            LegsX Lx{0.0, 0.0};
+            if (PX) Lx = legs_ext(px, py, G[q]);
             if (AA) {
                 // column minus source / receiver of this group's trace
                 const float dxs = px - G[q].x, dys = py - G[q].y, dxr = px - G[q].z, dyr = py - G[q].w;
@@ -207,6 +254,18 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
                 }
                 continue;
             }
+            if (TT == TT_TABLE && PX) {
+                const TLegX Ls = table_leg_ext(P, Lx.hs2), Lr = table_leg_ext(P, Lx.hr2);
+#pragma unroll
+                for (int k = 0; k < KS; k += 2) {
+                    if (!((any >> k) & 3u)) continue;
+                    const int iz0 = min(slot_depth<kIL>(z0, k, d), P.nz - 1);
+                    const int iz1 = min(slot_depth<kIL>(z0, k + 1, d), P.nz - 1);
+                    dem_pair_table_ext<TF>(P, Ls, Lr, iz0, iz1, row, wlo, whi, x[k], x[k + 1], L.hmax <= T.R[k],
+                                           L.hmax <= T.R[k + 1]);
+                }
+                continue;
+            }
             if (TT == TT_TABLE) {
                 const TLeg Ls = table_leg(P, L.hs2), Lr = table_leg(P, L.hr2);
 #pragma unroll
@@ -216,6 +275,16 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
                     const int iz1 = min(slot_depth<kIL>(z0, k + 1, d), P.nz - 1);
                     dem_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1],
                                              L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
+                }
+                continue;
+            }
+            if (PX) {
+#pragma unroll
+                for (int k = 0; k < KS; k += 2) {
+                    if (!((any >> k) & 3u)) continue;
+                    dem_masked_ext<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], Lx.hs2, Lx.hr2, row, P.inv_dt,
+                                           tfod, ilo, ihi, wlod, whid, x[k], x[k + 1], L.hmax <= T.R[k],
+                                           L.hmax <= T.R[k + 1]);
                 }
                 continue;
             }
@@ -232,7 +301,7 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 }
 
 // Traces t0..t1-1 of the block (one bin b, at most 4 NQ traces).
-template <int NW, int KS, int NQ, bool TF, int WK, int TT>
+template <int NW, int KS, int NQ, bool TF, int WK, int TT, bool PX>
 __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0, int t1, const float4* sGeo,
                                                   double* sAcc, const float* sInvSq) {
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
@@ -269,13 +338,13 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     for (int zc = 0; zc < P.n_zchunks; ++zc) {
         const int z0 = zc * KS * kGroup;
         ChunkTables<KS> T;
-        load_chunk_tables<KS, kIL, TT>(P, z0, d, WK == W_COSCOS, T, nullptr);
+        load_chunk_tables<KS, kIL, TT, PX>(P, z0, d, WK == W_COSCOS, T, nullptr);
         if (!(T.rmax >= 0.0f)) continue;
         float S[KS];
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int iz = slot_depth<kIL>(z0, k, d);
-            S[k] = (iz < P.nz) ? depth_factor(P, iz) : 0.0f;
+            S[k] = (iz < P.nz) ? depth_factor<PX>(P, iz) : 0.0f;
         }
         // a float32 leg with |dx| > sqrt(r2) (1 + 2^-22) cannot pass the
         // float32 aperture test, so this radius keeps every column that can
@@ -286,20 +355,24 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
         index_range(P.y, P.ny, static_cast<double>(ay) - rho, static_cast<double>(by) + rho, iy0, iy1);
         if (iy0 > iy1) continue;
         if (z0 + KS * kGroup > P.nz)
-            sweep_columns<NW, KS, NQ, TF, WK, true, TT>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S,
-                                                        G, sAcc, sInvSq);
+            sweep_columns<NW, KS, NQ, TF, WK, true, TT, PX>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T,
+                                                            S, G, sAcc, sInvSq);
         else
-            sweep_columns<NW, KS, NQ, TF, WK, false, TT>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T, S,
-                                                         G, sAcc, sInvSq);
+            sweep_columns<NW, KS, NQ, TF, WK, false, TT, PX>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1,
+                                                             T, S, G, sAcc, sInvSq);
     }
 }
 
-// The 4-slot square-root kernel is held to 6 wavefronts per SIMD (80 VGPRs, no
-// spills): with 8-wavefront one-quad workgroups that is three workgroups per
-// CU, as many as their LDS rows allow.  The other kernels need more registers.
-template <int NW, int KS, int NQ, bool TF, int WK, int TT = TT_DSR>
+// The 4-slot square-root kernels are held to 6 wavefronts per SIMD (80 VGPRs;
+// no spills in the float32 kernel, about 20 registers spilled in the
+// extended-precision one, which ran 2.38 s against 2.56 s at its natural 108 on
+// the 3D survey): with 8-wavefront one-quad workgroups that is three workgroups
+// per CU, as many as their LDS rows allow.  The other kernels need more
+// registers.
+template <int NW, int KS, int NQ, bool TF, int WK, int TT = TT_DSR, bool PX = false>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KS <= 4 && TT == TT_DSR ? 6 : 1)))
 void demigrate_kernel(Params P) {
+    static_assert(!(PX && TT == TT_AA), "no extended-precision anti-alias kernels");
     extern __shared__ float lds[];
     double* sAcc = reinterpret_cast<double*>(lds);                     // [tb][lt]
     float4* sGeo = reinterpret_cast<float4*>(lds + 2 * P.tb * P.lt);   // [tb]
@@ -327,7 +400,7 @@ void demigrate_kernel(Params P) {
         const int b = P.bin[j0 + t0];
         int t1 = t0 + 1;
         while (t1 < nb && P.bin[j0 + t1] == b) ++t1;
-        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK, TT>(P, b, t0, t1, sGeo, sAcc, sInvSq);
+        if (b >= 0 && b < P.n_bins) demigrate_segment<NW, KS, NQ, TF, WK, TT, PX>(P, b, t0, t1, sGeo, sAcc, sInvSq);
         t0 = t1;
     }
     __syncthreads();
@@ -367,6 +440,19 @@ void demigrate_kernel(Params P) {
     }
 }
 
+// The plain kernels of one time precision (PX) for the weight and t_first cases.
+template <int NW, int KS, int NQ, bool PX>
+static hipError_t launch_demigrate_dsr(const Params& P, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    if (P.has_tf) {
+        if (P.weight == W_COSCOS)
+            return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_COSCOS, TT_DSR, PX>, grid, block, lds, s, P);
+        return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_DSR, PX>, grid, block, lds, s, P);
+    }
+    if (P.weight == W_COSCOS)
+        return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_COSCOS, TT_DSR, PX>, grid, block, lds, s, P);
+    return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_DSR, PX>, grid, block, lds, s, P);
+}
+
 template <int NW, int KS, int NQ>
 static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     if (P.tb < 1 || P.tb > kGroupsPerWave * NQ) return hipErrorInvalidValue;
@@ -374,6 +460,11 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     dim3 grid(static_cast<unsigned>(nblk)), block(NW * 64);
     const size_t lds = lds_bytes_f64rows(P);
     if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
+        if (P.prec) {
+            if (P.has_tf)
+                return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_TABLE, true>, grid, block, lds, s, P);
+            return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_TABLE, true>, grid, block, lds, s, P);
+        }
         if (P.has_tf) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
         return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
     }
@@ -387,12 +478,8 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
             return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_COSCOS, TT_AA>, grid, block, lds, s, P);
         return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_AA>, grid, block, lds, s, P);
     }
-    if (P.has_tf) {
-        if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_COSCOS>, grid, block, lds, s, P);
-        return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT>, grid, block, lds, s, P);
-    }
-    if (P.weight == W_COSCOS) return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_COSCOS>, grid, block, lds, s, P);
-    return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT>, grid, block, lds, s, P);
+    if (P.prec) return launch_demigrate_dsr<NW, KS, NQ, true>(P, grid, block, lds, s);
+    return launch_demigrate_dsr<NW, KS, NQ, false>(P, grid, block, lds, s);
 }
 
 // (waves, depth slots, trace quads per workgroup, LDS budget for the trace

@@ -72,6 +72,9 @@ struct Params {
     float aa_dx, aa_dy;  // image spacings the operator dip is measured over
     int32_t aa_max;      // largest triangle half-width in samples (1 .. kAAMaxHalf)
     int32_t aa_lead;     // demigrate: row index of sample 0 (rows hold samples -aa_lead .. lt - aa_lead - 1)
+    // time precision: 0 = float32 evaluation, 1 = extended (the PX kernels)
+    int32_t prec;
+    double inv_dh_d;     // 1 / dh in float64 (extended table legs)
 };
 
 // Traveltime kinds of the kernels: the per-depth double-square-root form
@@ -118,9 +121,8 @@ __device__ __forceinline__ Legs legs(float px, float py, float4 sr) {
 //         (plus kLead through the row pointer when t_first == 0),
 //   i   = floor(w), f = w - i, and r = 1 / (a_s a_r) for the weight.
 // Migrate and demigrate both call this, so the transpose pair sees
-// bit-identical (i, f, r) for every pair.  CLAMP = false is used only where
-// every evaluated pair is known to satisfy w <= whi (ChunkTables::wmax) and
-// w >= wlo (t_first == 0 gives w >= 0); the result is then identical.
+// bit-identical (i, f, r) for every pair.  CLAMP = false skips the clamp (for
+// callers that know every w lies in [wlo, whi]; the kernels all clamp).
 struct Pair {
     int32_t i;
     float f;
@@ -139,6 +141,76 @@ __device__ __forceinline__ Pair eval_pair(float A, float B, float hs2, float hr2
     p.f = __builtin_amdgcn_fractf(w);
     p.r = (WK == W_COSCOS) ? __builtin_amdgcn_rcpf(as * ar) : 1.0f;
     return p;
+}
+
+// Extended-precision form of eval_pair (the PX kernels).  A float32 total
+// time is rounded to 0.5 ulp of u (6e-5 samples at u = 1000, 1e-3 at 16000)
+// after the roundings of A, B, the two products and the two square roots, which
+// is a relative image error of about 1e-5 on data that change by O(1) between
+// samples.  Here the tables are the physical float32 inputs (A = t0sq in s^2,
+// B = s2 in s^2 / m^2, exact in float64), the squared leg lengths Hs, Hr are
+// float64 (exact for float32 coordinates), a = A + B H is one float64 FMA, and
+// each leg's square root is a float32 reciprocal square root q refined by one
+// residual step in float64: y = a q, sqrt(a) = y + (a - y^2) q / 2 to about
+// 2^-45 relative (Newton's step from a 2^-23 seed).  Both legs' steps are
+// summed in float64 and scaled by 1 / dt, so i = floor(u) and f = u - i come
+// from a total time good to about 1e-9 samples.  The weight 1 / (a_s a_r) is
+// (q_s q_r)^2 (in s^-4; depth_factor<true> supplies t0sq), from the same seeds,
+// with float32 precision.
+//   !TF: i = floor(w) clamped to [ilo, ihi] (the two row entries at a clamped
+//        index are zeros, or the pair is outside the aperture and masked);
+//   TF:  w clamped to [wlo, whi] first (as eval_pair; f = 0 at a bound).
+// a = 0 exactly (W = 1 and t0 = 0 at zero offset) would give rsq = inf: the
+// tables replace A = 0 by kTinyA (a time of 3e-19 s).
+struct PairX {
+    int32_t i;
+    float f;
+    double fd;  // f in float64 (the adjoint's tap weights)
+    float r;
+};
+
+constexpr float kTinyA = 1.0e-37f;
+
+template <bool TF, int WK>
+__device__ __forceinline__ PairX eval_pair_ext(float A, float B, double Hs, double Hr, double inv_dt, double tfo,
+                                               int ilo, int ihi, double wlo, double whi) {
+    const double Ad = static_cast<double>(A), Bd = static_cast<double>(B);
+    const double as = fma(Bd, Hs, Ad);
+    const double ar = fma(Bd, Hr, Ad);
+    const float qs = __builtin_amdgcn_rsqf(static_cast<float>(as));
+    const float qr = __builtin_amdgcn_rsqf(static_cast<float>(ar));
+    const double qsd = static_cast<double>(qs), qrd = static_cast<double>(qr);
+    const double ys = as * qsd, yr = ar * qrd;
+    const double es = fma(-ys, ys, as), er = fma(-yr, yr, ar);
+    double w = fma(fma(er, qrd, es * qsd), 0.5, ys + yr) * inv_dt;
+    PairX p;
+    if (TF) {
+        w = fmin(fmax(w + tfo, wlo), whi);
+        p.i = static_cast<int32_t>(w);
+    } else {
+        p.i = min(max(static_cast<int32_t>(w), ilo), ihi);
+    }
+    p.fd = __builtin_amdgcn_fract(w);
+    p.f = static_cast<float>(p.fd);
+    const float g = qs * qr;
+    p.r = (WK == W_COSCOS) ? g * g : 1.0f;
+    return p;
+}
+
+// Squared leg lengths in float64 from the float32 coordinates (the
+// differences and squares are exact; one rounding in the sum).
+struct LegsX {
+    double hs2, hr2;
+};
+
+__device__ __forceinline__ LegsX legs_ext(float px, float py, float4 sr) {
+    const double x = px, y = py;
+    const double dxs = x - static_cast<double>(sr.x), dys = y - static_cast<double>(sr.y);
+    const double dxr = x - static_cast<double>(sr.z), dyr = y - static_cast<double>(sr.w);
+    LegsX L;
+    L.hs2 = fma(dxs, dxs, dys * dys);
+    L.hr2 = fma(dxr, dxr, dyr * dyr);
+    return L;
 }
 
 // One pair with the anti-alias triangle filter (Params::aa_*).  As eval_pair
@@ -201,6 +273,49 @@ __device__ __forceinline__ TLeg table_leg(const Params& P, float h2) {
     return L;
 }
 
+// Extended table leg: h = sqrt(H) from the float64 squared length (float32
+// reciprocal square root seed and one float64 residual step), h / dh and the
+// fraction in float64.  H = 0 (a column above the source) is raised to 1e-30
+// so that the seed stays finite (h = 1e-15).
+struct TLegX {
+    int32_t off;
+    double f;
+};
+
+__device__ __forceinline__ TLegX table_leg_ext(const Params& P, double H) {
+    H = fmax(H, 1.0e-30);
+    const double q = static_cast<double>(__builtin_amdgcn_rsqf(static_cast<float>(H)));
+    const double y = H * q;
+    const double h = fma(fma(-y, y, H), 0.5 * q, y);
+    const double hf = fmin(h * P.inv_dh_d, static_cast<double>(P.n_h - 1));
+    const int ih = min(static_cast<int>(hf), P.n_h - 2);
+    TLegX L;
+    L.off = ih * P.nz;
+    L.f = hf - static_cast<double>(ih);
+    return L;
+}
+
+__device__ __forceinline__ double table_time_ext(const Params& P, TLegX L, int iz) {
+    const double a = P.ttab[L.off + iz], b = P.ttab[L.off + P.nz + iz];
+    return fma(L.f, b - a, a);
+}
+
+// eval_pair_table with extended legs (same clamp as eval_pair_table; the
+// fraction is returned in float32 and float64).
+template <bool TF>
+__device__ __forceinline__ PairX eval_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, int iz, float wlo,
+                                                     float whi) {
+    double w = (table_time_ext(P, Ls, iz) + table_time_ext(P, Lr, iz)) * P.inv_dt;
+    if (TF) w = w + P.tf_off_d;
+    w = fmin(fmax(w, static_cast<double>(wlo)), static_cast<double>(whi));
+    PairX p;
+    p.i = static_cast<int32_t>(w);
+    p.fd = w - static_cast<double>(p.i);
+    p.f = static_cast<float>(p.fd);
+    p.r = 1.0f;
+    return p;
+}
+
 // Interpolated one-way time in float64: b - a of two adjacent float32 table
 // values is exact, the interpolation and the sum are float64, so the time
 // keeps the table's own precision (float32 rounding of the time in seconds
@@ -254,21 +369,22 @@ __device__ __forceinline__ int slot_depth(int z0, int k, int d) {
 //            lanes of slot k of the aperture table (+inf / -inf when the slot
 //            has no valid lane)
 //   rmax     max over the chunk (wavefront-uniform)
-//   wmax     an upper bound of sqrt(a_s) + sqrt(a_r) over every pair inside the
-//            aperture in this chunk (wavefront-uniform; +inf when unknown)
+// PX (extended-precision kernels): A, B are the physical tables t0sq and s2
+// (exact float32 inputs; A = kTinyA where t0sq = 0), scaled by 1 / dt after
+// the square roots.
 // sR[16 k + d] (LDS) holds the aperture value of each lane, -1 where invalid.
 template <int KS>
 struct ChunkTables {
     float A[KS], B[KS], R[KS];
-    float rlo, rhi, rmax, wmax;
+    float rlo, rhi, rmax;
     uint32_t clean;  // bit k: every lane of slot k is valid (wavefront-uniform)
 };
 
-template <int KS, int IL = 1, int TT = TT_DSR>
+template <int KS, int IL = 1, int TT = TT_DSR, bool PX = false>
 __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d, bool zero_weight_guard,
                                                   ChunkTables<KS>& T, float* sR) {
     const int lane = threadIdx.x & (kLanes - 1);
-    float rmax = -1.0f, wmax = 0.0f;
+    float rmax = -1.0f;
     float rlo_mine = __builtin_inff(), rhi_mine = -__builtin_inff();
     uint32_t clean = 0;
 #pragma unroll
@@ -287,8 +403,13 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
                 const float t0 = P.t0sq[iz];
                 valid = !(zero_weight_guard && !(t0 > 0.0f));
                 if (valid) {
-                    A = static_cast<float>(static_cast<double>(t0) * P.inv_dt2);
-                    B = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);
+                    if (PX) {
+                        A = t0 == 0.0f ? kTinyA : t0;
+                        B = P.s2[iz];
+                    } else {
+                        A = static_cast<float>(static_cast<double>(t0) * P.inv_dt2);
+                        B = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);
+                    }
                     R = P.r2[iz];
                 }
             }
@@ -298,13 +419,6 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         T.R[k] = R;
         if (sR && lane < kGroup) sR[k * kGroup + d] = R;
         if ((__builtin_amdgcn_ballot_w64(valid) & 0xFFFFull) == 0xFFFFull) clean |= 1u << k;
-        // in aperture, a = A + B h^2 <= fma(B, R, A) (rounding is monotone);
-        // 2 sqrt of it with a relative margin for the approximate square root.
-        // A NaN (bad table) propagates and disables the unclamped path.
-        float wk = 2.0f * 1.00001f + 1.0f;
-        if (valid) wk = B >= 0.0f ? 2.0f * __builtin_amdgcn_sqrtf(fmaf(B, R, A)) * 1.00001f + 1.0f : __builtin_inff();
-        if (TT == TT_TABLE) wk = __builtin_inff();  // no bound known: always clamp
-        wmax = (wk > wmax || wk != wk) ? wk : wmax;
         // min / max over the 16 lanes of the group (all groups hold the same depths)
         float lo = valid ? R : __builtin_inff();
         float hi = valid ? R : -__builtin_inff();
@@ -319,18 +433,11 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         }
         rmax = fmaxf(rmax, hi);
     }
-    // wavefront max of wmax, NaN-preserving (any NaN lane makes it NaN)
-#pragma unroll
-    for (int off = 1; off < kLanes; off <<= 1) {
-        const float o = __shfl_xor(wmax, off, kLanes);
-        wmax = (o > wmax || o != o) ? o : wmax;
-    }
     T.rlo = rlo_mine;
     T.rhi = rhi_mine;
     T.clean = clean;
     // equal in every lane: make them scalar so that branches on them are uniform
     T.rmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(rmax)));
-    T.wmax = __int_as_float(__builtin_amdgcn_readfirstlane(__float_as_int(wmax)));
 }
 
 // Bit k (k < KS) set when slot k may hold a lane inside the aperture
@@ -345,10 +452,13 @@ __device__ __forceinline__ void slot_masks(const ChunkTables<KS>& T, float hmin,
 }
 
 // Final per-depth factor of the image: t0sq / dt^4 for the cos*cos weight
-// (so W = factor * r), 1 for the unit weight; 0 where W is defined as 0.
+// (so W = factor * r with r in samples^-4), t0sq for the extended kernels (r in
+// s^-4), 1 for the unit weight; 0 where W is defined as 0.
+template <bool PX = false>
 __device__ __forceinline__ float depth_factor(const Params& P, int iz) {
     if (P.weight != W_COSCOS) return 1.0f;
     const float t0 = P.t0sq[iz];
+    if (PX) return t0 > 0.0f ? t0 : 0.0f;
     return t0 > 0.0f ? static_cast<float>(static_cast<double>(t0) * P.wscale) : 0.0f;
 }
 
@@ -388,6 +498,13 @@ __device__ __forceinline__ float box_far2(float x, float y, float x0, float x1, 
 // v from lane `src` (any lane), through the LDS crossbar.
 __device__ __forceinline__ float lane_read(float v, int src) {
     return __int_as_float(__builtin_amdgcn_ds_bpermute(src << 2, __float_as_int(v)));
+}
+
+// A float64 value from lane `src` (two crossbar reads).
+__device__ __forceinline__ double lane_read_d(double v, int src) {
+    const int lo = __builtin_amdgcn_ds_bpermute(src << 2, __double2loint(v));
+    const int hi = __builtin_amdgcn_ds_bpermute(src << 2, __double2hiint(v));
+    return __hiloint2double(hi, lo);
 }
 
 __device__ __forceinline__ float uniform_read(float v, int src) {

@@ -53,9 +53,9 @@ int migrate_shape_count();
 const TileShape& migrate_shape(int i);
 hipError_t launch_migrate(int shape, const Params& P, hipStream_t s);
 hipError_t launch_migrate_batch(int shape, const Params* probs, const int4* items, int64_t n_items,
-                                unsigned int* counter, int has_tf, int weight, int n_wg, size_t lds,
+                                unsigned int* counter, int has_tf, int weight, int prec, int n_wg, size_t lds,
                                 hipStream_t s);
-const void* migrate_batch_kernel_ptr(int shape, int has_tf, int weight);
+const void* migrate_batch_kernel_ptr(int shape, int has_tf, int weight, int prec);
 
 // demigrate (km_demigrate.hip)
 int demigrate_shape_count();

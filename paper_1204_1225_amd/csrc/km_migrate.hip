@@ -144,6 +144,41 @@ __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr
     acc1 += v1;
 }
 
+// One slot with the extended-precision time (eval_pair_ext): leg lengths in
+// float64, the clamp as integer bounds [ilo, ihi] (or float64 [wlo, whi] with
+// t_first).  One slot at a time: the float64 temporaries of two slots in
+// flight would cost more registers than the latency they hide.
+template <bool TF, int WK>
+__device__ __forceinline__ void mig_slot_ext(float A, float B, double Hs, double Hr, float hm, const float2* row,
+                                             double inv_dt, double tfo, int ilo, int ihi, double wlo, double whi,
+                                             float R, float& acc) {
+    // keep the tables' float64 conversions inside the loop (hoisted, they
+    // would hold two more registers per slot)
+    asm volatile("" : "+v"(A), "+v"(B));
+    const PairX p = eval_pair_ext<TF, WK>(A, B, Hs, Hr, inv_dt, tfo, ilo, ihi, wlo, whi);
+    const float2 e = row[p.i];
+    float v = fmaf(p.f, e.y, e.x);
+    v = (hm <= R) ? v : 0.0f;
+    acc = (WK == W_COSCOS) ? fmaf(v, p.r, acc) : acc + v;
+}
+
+// mig_pair_table with extended legs (table_leg_ext).
+template <bool TF>
+__device__ __forceinline__ void mig_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, int iz0, int iz1, float hm,
+                                                   const float* row, float wlo, float whi, float R0, float R1,
+                                                   float& acc0, float& acc1) {
+    const PairX p0 = eval_pair_table_ext<TF>(P, Ls, Lr, iz0, wlo, whi);
+    const PairX p1 = eval_pair_table_ext<TF>(P, Ls, Lr, iz1, wlo, whi);
+    const float a0 = row[p0.i], b0 = row[p0.i + 1];
+    const float a1 = row[p1.i], b1 = row[p1.i + 1];
+    float v0 = fmaf(p0.f, b0 - a0, a0);
+    float v1 = fmaf(p1.f, b1 - a1, a1);
+    v0 = (hm <= R0) ? v0 : 0.0f;
+    v1 = (hm <= R1) ? v1 : 0.0f;
+    acc0 += v0;
+    acc1 += v1;
+}
+
 // Two slots with the anti-alias triangle filter.  row[n] = I2 at window
 // position n (staged by stage_window_i2): the smoothed sample at c is
 // alpha T_L(c) + beta T_{L+1}(c), T_L(c) = I2[c+L-1] - 2 I2[c-1] + I2[c-L-1],
@@ -180,13 +215,16 @@ __device__ __forceinline__ void mig_slot_aa(float A, float B, float hs2, float h
 // RREG: the masked slots take the lanes' aperture values from registers
 // (else from the LDS copy, which costs fewer registers).
 // TT: traveltime kind (TT_TABLE: one-way time table, W = 1).
+// PX: extended-precision times (eval_pair_ext, table_leg_ext); the squared
+// leg lengths then also reach the depth lanes in float64.
 //
 // LDS (lds_bytes): window storage [P.cap floats; a window of n samples takes
 // n - 1 pairs], per block slot the trace geometry (float4) and (float offset,
 // first sample, last sample, trace - bin start) (int4) [P.tb each], the aperture values [KS * 16], the tile box
 // [4 per wavefront] and the candidates of one pass [NW * 4 x (int2, float4)].
-template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR>
+template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR, bool PX = false>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
+    static_assert(!(PX && TT == TT_AA), "no extended-precision anti-alias kernels");
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     constexpr int NG = NW * kGroupsPerWave;  // candidate traces per pass: one per 16-lane group
     static_assert(NG <= kLanes && NW <= kBoxFloats / 4, "at most 16 wavefronts");
@@ -221,7 +259,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             sInvSq[t] = t > 0 ? 1.0f / static_cast<float>(t * t) : 0.0f;
 
     ChunkTables<KS> T;
-    load_chunk_tables<KS, 1, TT>(P, z0, d, WK == W_COSCOS, T, sR);
+    load_chunk_tables<KS, 1, TT, PX>(P, z0, d, WK == W_COSCOS, T, sR);
 
     float px[CWQ], py[CWQ];
     int colv[CWQ];
@@ -246,6 +284,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     const int64_t lo = lower_bound_bin(P.bin, P.n_traces, b);
     const int64_t hi = lower_bound_bin(P.bin, P.n_traces, b + 1);
     const float tfo = P.tf_off;
+    const double tfod = P.tf_off_d;
 
     // Bounding box of the tile's columns.  A leg longer than sqrt(r2)(1 + 2^-22)
     // from every column cannot pass the float32 aperture test, so a trace whose
@@ -348,6 +387,11 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                             umin = fminf(umin, __shfl_xor(umin, off, kLanes));
                             umax = fmaxf(umax, __shfl_xor(umax, off, kLanes));
                         }
+                        if (PX) {  // physical tables: seconds -> samples (a monotone rounding)
+                            const float sc = static_cast<float>(P.inv_dt);
+                            umin = umin * sc;
+                            umax = umax * sc;
+                        }
                         const uint32_t gany = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(any) >> (kGroup * g)) & 0xFFFFu;
                         const uint32_t gbad = static_cast<uint32_t>(__builtin_amdgcn_ballot_w64(bad) >> (kGroup * g)) & 0xFFFFu;
                         if (!gany) {
@@ -446,6 +490,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
 #pragma unroll
             for (int q = 0; q < CWQ; ++q) {
                 const Legs Lp = legs(px[q], py[q], sr);
+                LegsX Lx{0.0, 0.0};
+                if (PX) Lx = legs_ext(px[q], py[q], sr);
                 // extremes of hmax over the four columns, per trace (lanes d, 16 + d, 32 + d, 48 + d)
                 float hmin4 = fminf(Lp.hmax, __shfl_xor(Lp.hmax, 16, kLanes));
                 hmin4 = fminf(hmin4, __shfl_xor(hmin4, 32, kLanes));
@@ -462,9 +508,15 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                 float hs2n = lane_read(Lp.hs2, (lane & ~(kGroup - 1)) | t);
                 float hr2n = lane_read(Lp.hr2, (lane & ~(kGroup - 1)) | t);
                 float whin = lane_read(lwhi, t);
+                double Hsn = 0.0, Hrn = 0.0;
+                if (PX) {
+                    Hsn = lane_read_d(Lx.hs2, (lane & ~(kGroup - 1)) | t);
+                    Hrn = lane_read_d(Lx.hr2, (lane & ~(kGroup - 1)) | t);
+                }
                 for (;;) {
                     const int tc = t;
                     const float hs2 = hs2n, hr2 = hr2n, whi = whin;
+                    const double Hs = Hsn, Hr = Hrn;
                     const bool more = live != 0;
                     if (more) {
                         t = __builtin_ctzll(live);
@@ -472,6 +524,10 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                         hs2n = lane_read(Lp.hs2, (lane & ~(kGroup - 1)) | t);
                         hr2n = lane_read(Lp.hr2, (lane & ~(kGroup - 1)) | t);
                         whin = lane_read(lwhi, t);
+                        if (PX) {
+                            Hsn = lane_read_d(Lx.hs2, (lane & ~(kGroup - 1)) | t);
+                            Hrn = lane_read_d(Lx.hr2, (lane & ~(kGroup - 1)) | t);
+                        }
                     }
                     const float hmin = uniform_read(hmin4, tc);
                     const float hmaxw = uniform_read(hmax4, tc);
@@ -487,7 +543,20 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     // max(hs2, hr2): one v_max (fmaxf would first quiet both inputs)
                     float hm;
                     asm("v_max_f32 %0, %1, %2" : "=v"(hm) : "v"(hs2), "v"(hr2));
-                    if (TT == TT_TABLE) {
+                    if (TT == TT_TABLE && PX) {
+                        const TLegX Ls = table_leg_ext(P, Hs), Lr = table_leg_ext(P, Hr);
+#pragma unroll
+                        for (int k = 0; k < KS; k += 2) {
+                            if ((any >> k) & 3ull) {
+                                const int iz0 = min(z0 + k * kGroup + d, P.nz - 1);
+                                const int iz1 = min(z0 + (k + 1) * kGroup + d, P.nz - 1);
+                                const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
+                                const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
+                                mig_pair_table_ext<TF>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, wlo, whi, R0, R1, acc[q][k],
+                                                       acc[q][k + 1]);
+                            }
+                        }
+                    } else if (TT == TT_TABLE) {
                         const TLeg Ls = table_leg(P, hs2), Lr = table_leg(P, hr2);
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
@@ -512,6 +581,18 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 mig_slot_aa<TF, WK>(T.A[k], T.B[k], hs2, hr2, hm, rowd, tfo, wlo, whi, R, dxs, dys, dxr,
                                                     dyr, P.aa_dx, P.aa_dy, static_cast<float>(lmax), sInvSq,
                                                     acc[q][k]);
+                            }
+                        }
+                    } else if (PX) {
+                        const int ilo = static_cast<int>(wlo), ihi = static_cast<int>(whi);
+                        const double wlod = wlo, whid = whi;
+#pragma unroll
+                        for (int k = 0; k < KS; ++k) {
+                            if ((any >> k) & 1ull) {
+                                const float R = RREG ? T.R[k] : sR[k * kGroup + d];
+                                mig_slot_ext<TF, WK>(T.A[k], T.B[k], Hs, Hr, hm,
+                                                     reinterpret_cast<const float2*>(sTr) + rb, P.inv_dt, tfod, ilo,
+                                                     ihi, wlod, whid, R, acc[q][k]);
                             }
                         }
                     } else {
@@ -544,7 +625,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         for (int k = 0; k < KS; ++k) {
             const int iz = z0 + k * kGroup + d;
             if (iz < P.nz) {
-                const float fac = depth_factor(P, iz);
+                const float fac = depth_factor<PX>(P, iz);
                 const float val = fac != 0.0f ? acc[q][k] * fac : 0.0f;
                 colp[iz] = P.accumulate ? colp[iz] + val : val;
             }
@@ -575,10 +656,14 @@ __device__ __forceinline__ void zero_tile(const Params& P, int b, int tile, int 
     }
 }
 
-template <int NW, int CWQ, int KS, bool TF, int WK, int TT = TT_DSR>
-__global__ __launch_bounds__(NW * 64) void migrate_kernel(Params P) {
+// The extended-precision square-root kernels are held to 4 wavefronts per SIMD
+// (128 VGPRs, some spilled) so that two 8-wavefront workgroups share a CU:
+// 2.28 s against 3.29 s at their natural 165 VGPRs on the 3D survey.
+template <int NW, int CWQ, int KS, bool TF, int WK, int TT = TT_DSR, bool PX = false>
+__global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(PX && TT == TT_DSR && KS <= 8 ? 4 : 1)))
+void migrate_kernel(Params P) {
     extern __shared__ float lds[];
-    migrate_tile<NW, CWQ, KS, TF, WK, true, TT>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
+    migrate_tile<NW, CWQ, KS, TF, WK, true, TT, PX>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched persistent form: work items (problem, bin, column tile, depth
@@ -586,7 +671,7 @@ __global__ __launch_bounds__(NW * 64) void migrate_kernel(Params P) {
 // tile field -1 - tile marks an item with no pair in aperture: zero store.
 // At least 4 wavefronts per SIMD (<= 128 VGPRs) for the 8-slot shapes, so
 // that two 8-wavefront workgroups share a CU as they do in single launches.
-template <int NW, int CWQ, int KS, bool TF, int WK>
+template <int NW, int CWQ, int KS, bool TF, int WK, bool PX = false>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KS <= 8 ? 4 : 2)))
 void migrate_batch_kernel(const Params* __restrict__ probs,
                                                                 const int4* __restrict__ items,
@@ -602,7 +687,7 @@ void migrate_batch_kernel(const Params* __restrict__ probs,
         const int4 w = items[it];  // (problem, bin, tile, zchunk)
         const Params P = probs[w.x];
         if (w.z < 0) zero_tile<NW, CWQ, KS>(P, w.y, -1 - w.z, w.w);
-        else migrate_tile<NW, CWQ, KS, TF, WK, false>(P, w.y, w.z, w.w, lds);
+        else migrate_tile<NW, CWQ, KS, TF, WK, false, TT_DSR, PX>(P, w.y, w.z, w.w, lds);
     }
 }
 
@@ -610,11 +695,29 @@ void migrate_batch_kernel(const Params* __restrict__ probs,
 // Launch tables
 // ---------------------------------------------------------------------------
 
+// The plain kernels of one time precision (PX) for the weight and t_first cases.
+template <int NW, int CWQ, int KS, bool PX>
+static hipError_t launch_migrate_dsr(const Params& P, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    if (P.has_tf) {
+        if (P.weight == W_COSCOS)
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS, TT_DSR, PX>, grid, block, lds, s, P);
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_DSR, PX>, grid, block, lds, s, P);
+    }
+    if (P.weight == W_COSCOS)
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_COSCOS, TT_DSR, PX>, grid, block, lds, s, P);
+    return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_DSR, PX>, grid, block, lds, s, P);
+}
+
 template <int NW, int CWQ, int KS>
 static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
     dim3 grid(P.n_coltiles, P.n_zchunks, P.n_bins), block(NW * 64);
     const size_t lds = lds_bytes(P, KS);
     if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
+        if (P.prec) {
+            if (P.has_tf)
+                return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_TABLE, true>, grid, block, lds, s, P);
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_TABLE, true>, grid, block, lds, s, P);
+        }
         if (P.has_tf) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
         return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_TABLE>, grid, block, lds, s, P);
     }
@@ -628,27 +731,33 @@ static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
             return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_COSCOS, TT_AA>, grid, block, lds, s, P);
         return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_AA>, grid, block, lds, s, P);
     }
-    if (P.has_tf) {
-        if (P.weight == W_COSCOS) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS>, grid, block, lds, s, P);
-        return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT>, grid, block, lds, s, P);
+    if (P.prec) return launch_migrate_dsr<NW, CWQ, KS, true>(P, grid, block, lds, s);
+    return launch_migrate_dsr<NW, CWQ, KS, false>(P, grid, block, lds, s);
+}
+
+// The batch kernel of (shape, t_first, weight, precision).
+template <int NW, int CWQ, int KS>
+static const void* batch_kernel_of(int has_tf, int weight, int prec) {
+    if (prec) {
+        if (has_tf) return weight == W_COSCOS ? (const void*)migrate_batch_kernel<NW, CWQ, KS, true, W_COSCOS, true>
+                                              : (const void*)migrate_batch_kernel<NW, CWQ, KS, true, W_UNIT, true>;
+        return weight == W_COSCOS ? (const void*)migrate_batch_kernel<NW, CWQ, KS, false, W_COSCOS, true>
+                                  : (const void*)migrate_batch_kernel<NW, CWQ, KS, false, W_UNIT, true>;
     }
-    if (P.weight == W_COSCOS) return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_COSCOS>, grid, block, lds, s, P);
-    return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT>, grid, block, lds, s, P);
+    if (has_tf) return weight == W_COSCOS ? (const void*)migrate_batch_kernel<NW, CWQ, KS, true, W_COSCOS>
+                                          : (const void*)migrate_batch_kernel<NW, CWQ, KS, true, W_UNIT>;
+    return weight == W_COSCOS ? (const void*)migrate_batch_kernel<NW, CWQ, KS, false, W_COSCOS>
+                              : (const void*)migrate_batch_kernel<NW, CWQ, KS, false, W_UNIT>;
 }
 
 template <int NW, int CWQ, int KS>
 static hipError_t launch_migrate_batch_shape(const Params* probs, const int4* items, int64_t n_items,
-                                             unsigned int* counter, int has_tf, int weight, int n_wg, size_t lds,
-                                             hipStream_t s) {
+                                             unsigned int* counter, int has_tf, int weight, int prec, int n_wg,
+                                             size_t lds, hipStream_t s) {
     dim3 grid(n_wg), block(NW * 64);
-    if (has_tf) {
-        if (weight == W_COSCOS)
-            return launch_with_lds(migrate_batch_kernel<NW, CWQ, KS, true, W_COSCOS>, grid, block, lds, s, probs, items, n_items, counter);
-        return launch_with_lds(migrate_batch_kernel<NW, CWQ, KS, true, W_UNIT>, grid, block, lds, s, probs, items, n_items, counter);
-    }
-    if (weight == W_COSCOS)
-        return launch_with_lds(migrate_batch_kernel<NW, CWQ, KS, false, W_COSCOS>, grid, block, lds, s, probs, items, n_items, counter);
-    return launch_with_lds(migrate_batch_kernel<NW, CWQ, KS, false, W_UNIT>, grid, block, lds, s, probs, items, n_items, counter);
+    using K = void (*)(const Params*, const int4*, int64_t, unsigned int*);
+    const K kern = reinterpret_cast<K>(const_cast<void*>(batch_kernel_of<NW, CWQ, KS>(has_tf, weight, prec)));
+    return launch_with_lds(kern, grid, block, lds, s, probs, items, n_items, counter);
 }
 
 // (waves, column groups per wave, depth slots, LDS budget for the trace block)
@@ -679,26 +788,21 @@ hipError_t launch_migrate(int shape, const Params& P, hipStream_t s) {
 }
 
 hipError_t launch_migrate_batch(int shape, const Params* probs, const int4* items, int64_t n_items,
-                                unsigned int* counter, int has_tf, int weight, int n_wg, size_t lds,
+                                unsigned int* counter, int has_tf, int weight, int prec, int n_wg, size_t lds,
                                 hipStream_t s) {
     int i = 0;
 #define X(nw, cwq, ks, lb) \
-    if (shape == i) return launch_migrate_batch_shape<nw, cwq, ks>(probs, items, n_items, counter, has_tf, weight, n_wg, lds, s); \
+    if (shape == i) return launch_migrate_batch_shape<nw, cwq, ks>(probs, items, n_items, counter, has_tf, weight, prec, n_wg, lds, s); \
     ++i;
     KM_MIGRATE_SHAPES(X)
 #undef X
     return hipErrorInvalidValue;
 }
 
-const void* migrate_batch_kernel_ptr(int shape, int has_tf, int weight) {
+const void* migrate_batch_kernel_ptr(int shape, int has_tf, int weight, int prec) {
     int i = 0;
-#define X(nw, cwq, ks, lb)                                                                                   \
-    if (shape == i) {                                                                                      \
-        if (has_tf) return weight == W_COSCOS ? (const void*)migrate_batch_kernel<nw, cwq, ks, true, W_COSCOS> \
-                                              : (const void*)migrate_batch_kernel<nw, cwq, ks, true, W_UNIT>;  \
-        return weight == W_COSCOS ? (const void*)migrate_batch_kernel<nw, cwq, ks, false, W_COSCOS>          \
-                                  : (const void*)migrate_batch_kernel<nw, cwq, ks, false, W_UNIT>;           \
-    }                                                                                                      \
+#define X(nw, cwq, ks, lb) \
+    if (shape == i) return batch_kernel_of<nw, cwq, ks>(has_tf, weight, prec); \
     ++i;
     KM_MIGRATE_SHAPES(X)
 #undef X

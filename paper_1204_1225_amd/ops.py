@@ -18,6 +18,7 @@ from . import _lib
 from ._lib import KmAntialias, KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmTtable, KmWeight, check
 
 _DTYPES = {"f32": _lib.KM_F32, "bf16": _lib.KM_BF16, "f16": _lib.KM_F16}
+_PRECISIONS = {"fp32": _lib.KM_TIME_FP32, "extended": _lib.KM_TIME_EXTENDED}
 
 
 def _stream(device) -> int:
@@ -52,6 +53,7 @@ class DeviceProblem:
     ttab: Optional[torch.Tensor] = None   # float32 [n_h, nz] one-way times: table traveltimes (W = 1)
     tdh: float = 0.0
     aa: Optional[tuple] = None            # (dx, dy, max half-width): anti-alias triangle filter
+    prec: str = "fp32"                    # time arithmetic: "fp32" or "extended" (km_time_precision)
 
     @property
     def n_traces(self) -> int:
@@ -93,8 +95,16 @@ class DeviceProblem:
     def c_grid(self) -> KmGrid:
         return KmGrid(nx=self.nx, ny=self.ny, nz=self.nz, n_bins=self.n_bins, x=_ptr(self.x), y=_ptr(self.y))
 
+    @property
+    def c_prec(self) -> int:
+        return _PRECISIONS[self.prec]
+
+    def with_precision(self, prec: str):
+        assert prec in _PRECISIONS
+        return dataclasses.replace(self, prec=prec)
+
     def c_tt(self) -> KmTraveltime:
-        return KmTraveltime(t0sq=_ptr(self.t0sq), s2=_ptr(self.s2), r2=_ptr(self.r2))
+        return KmTraveltime(t0sq=_ptr(self.t0sq), s2=_ptr(self.s2), r2=_ptr(self.r2), time_precision=self.c_prec)
 
     def c_weight(self) -> KmWeight:
         return KmWeight(kind=int(self.weight))
@@ -105,10 +115,11 @@ class DeviceProblem:
 
     def c_table(self) -> KmTtable:
         assert self.ttab is not None and self.ttab.shape[1] == self.nz and self.ttab.is_contiguous()
-        return KmTtable(n_h=int(self.ttab.shape[0]), dh=float(self.tdh), t=_ptr(self.ttab), r2=_ptr(self.r2))
+        return KmTtable(n_h=int(self.ttab.shape[0]), dh=float(self.tdh), t=_ptr(self.ttab), r2=_ptr(self.r2),
+                        time_precision=self.c_prec)
 
 
-def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DeviceProblem:
+def to_device(problem, device="cuda", data=None, dtype: str = "f32", prec: str = "fp32") -> DeviceProblem:
     """Copy a survey problem's inputs to the GPU in the ABI layouts.
 
     Tables are converted to float32 (the ABI's table type).  dtype "bf16" /
@@ -127,7 +138,7 @@ def to_device(problem, device="cuda", data=None, dtype: str = "f32") -> DevicePr
                        rec=f32(problem.rec),
                        bin=torch.as_tensor(np.ascontiguousarray(problem.bin, dtype=np.int32), device=dev),
                        x=f32(problem.x), y=f32(problem.y), t0sq=f32(problem.t0sq), s2=f32(problem.s2),
-                       r2=f32(problem.r2))
+                       r2=f32(problem.r2), prec=prec)
     if getattr(problem, "ttab", None) is not None:
         dp = dataclasses.replace(dp, ttab=f32(problem.ttab), tdh=float(problem.tdh))
     if getattr(problem, "aa", None) is not None:
@@ -200,15 +211,27 @@ def demigrate(dp: DeviceProblem, image: torch.Tensor, out: Optional[torch.Tensor
     return out
 
 
-def count(dp: DeviceProblem):
-    """(n_aperture, n_effective) of Eq. (2) from the counting kernel."""
+def _plain_only(dp: DeviceProblem, what: str) -> None:
+    """Raise for problems whose operator the call does not implement."""
+    if dp.ttab is not None or dp.aa is not None:
+        raise _lib.KirchhoffError(_lib.KM_E_UNSUPPORTED,
+                                  f"{what}: table traveltimes and the anti-alias filter are not supported here")
+
+
+def count(dp: DeviceProblem, aperture_only: bool = False):
+    """(n_aperture, n_effective) of Eq. (2) from the counting kernel.  The
+    aperture test does not depend on the traveltime kind, so with
+    aperture_only=True any problem is accepted and (n_aperture, None) is
+    returned; n_effective needs the square-root times of a plain problem."""
+    if not aperture_only:
+        _plain_only(dp, "count")
     c = torch.empty(2, dtype=torch.int64, device=dp.device)
     tr = dp.c_traces()
     lib = _lib.load()
     check(lib.km_count_contributions(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
                                      _ptr(c), ctypes.c_void_p(_stream(dp.device))))
     v = c.cpu().tolist()
-    return int(v[0]), int(v[1])
+    return int(v[0]), (None if aperture_only else int(v[1]))
 
 
 def dot_f64(a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -298,6 +321,7 @@ def tune(op: int, dp: DeviceProblem, image: torch.Tensor, traces_out: Optional[t
     fastest for its shape class; returns (tile, ms).  For op 0 `image` is
     overwritten with the migration; for op 1 `image` is the input and
     `traces_out` (float32 [n_traces, n_t]) is overwritten."""
+    _plain_only(dp, "tune")
     best, ms = ctypes.c_int32(-1), ctypes.c_float(0.0)
     tr = dp.c_traces() if op == 0 else dp.c_traces(traces_out, "f32")
     check(_lib.load().km_tune(op, ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
@@ -322,6 +346,7 @@ class Batch:
         self._keep = (list(problems), list(images))
         arr = (KmProblem * len(problems))()
         for k, (dp, img) in enumerate(zip(problems, images)):
+            _plain_only(dp, "Batch")
             assert img.shape == dp.image_shape and img.dtype == torch.float32 and img.is_contiguous()
             arr[k] = KmProblem(traces=dp.c_traces(), grid=dp.c_grid(), tt=dp.c_tt(), weight=dp.c_weight(),
                                image=_ptr(img))

@@ -20,8 +20,9 @@ I(x, X).  Everything it is *given* is built here, and nothing more:
 * storage conversion of traces to bfloat16 / float16 with a per-trace scale.
 
 This module contains no migration arithmetic (no time-to-sample interpolation,
-no weighting of data, no summation into an image).  It is shared by the test
-oracle and by the GPU library's callers, and imports neither.
+no weighting of data, no summation into an image).  It is shared by the FP64
+reference checker of the tests and by the GPU library's callers, and imports
+neither.
 """
 from __future__ import annotations
 
@@ -338,6 +339,11 @@ def _finish(name, src, rec, n_t, dt, t_first, x, y, z, n_bins, dX, velocity, ape
     src, rec, bins = _sort_by_bin(src, rec, bins)
     t0sq, s2 = traveltime_tables(z, velocity)
     r2 = aperture_table(t0sq, s2, aperture_deg)
+    # The operator's model tables are float32 (the library's table type): the
+    # FP64 reference checker and the kernels both take these rounded values.  r2 is rounded from
+    # the FP64 tables (so that grid-aligned 45-degree ties stay exact).
+    t0sq = t0sq.astype(np.float32).astype(np.float64)
+    s2 = s2.astype(np.float32).astype(np.float64)
     return Problem(name=name, src=src, rec=rec, bin=bins, data=None, n_t=int(n_t), dt=float(dt),
                    t_first=float(t_first), x=np.asarray(x, np.float32), y=np.asarray(y, np.float32),
                    z=np.asarray(z, np.float64), n_bins=int(n_bins), t0sq=t0sq, s2=s2, r2=r2,

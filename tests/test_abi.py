@@ -40,7 +40,9 @@ def test_exports_every_declared_symbol(lib):
 
 
 def test_abi_version_and_limits(lib):
-    assert lib.km_abi_version() == 1
+    from paper_1204_1225_amd import _lib
+
+    assert lib.km_abi_version() == _lib.ABI_VERSION == 2
     assert lib.km_max_samples() >= 20000
     assert lib.km_tile_count(0) >= 2 and lib.km_tile_count(1) >= 2
     assert lib.km_tile_count(7) == 0
@@ -78,6 +80,7 @@ def _args(_lib, **over):
     ({"t__scale": ctypes.c_void_p(0x1000)}, 1, b"scale"),
     ({"t__n_samples": 10 ** 6, "t__trace_stride": 10 ** 6}, 2, b"km_max_samples"),
     ({"w__kind": 5}, 1, b"weight"),
+    ({"tt__time_precision": 7}, 1, b"time precision"),
     ({"g__x": None}, 1, b"x and y"),
     ({"tt__r2": None}, 1, b"r2"),
     ({"g__nx": -3}, 1, b"negative"),
@@ -234,3 +237,28 @@ def test_antialias_entry_points_reject_bad_options(lib):
     assert lib.kirchhoff_migrate_aa(ctypes.byref(t2), ctypes.byref(g2), ctypes.byref(tt2), ctypes.byref(w2),
                                     ctypes.byref(ok), p, 0, -1, None) == _lib.KM_E_INVALID
     assert b"dt" in lib.km_last_error()
+
+
+def test_plain_only_calls_reject_table_and_antialias_problems():
+    # count (with n_effective), tune and Batch evaluate the plain square-root
+    # operator; a table-traveltime or anti-aliased problem must raise instead
+    # of silently running it (checked before any library call: no GPU needed).
+    import dataclasses
+
+    import torch
+
+    from paper_1204_1225_amd import _lib, ops
+
+    z = torch.zeros(4)
+    base = ops.DeviceProblem(device=torch.device("cpu"), n_t=10, dt=0.004, t_first=0.0, n_bins=1, weight=1,
+                             src=torch.zeros(2, 2), rec=torch.zeros(2, 2), bin=torch.zeros(2, dtype=torch.int32),
+                             x=torch.zeros(3), y=torch.zeros(1), t0sq=z, s2=z, r2=z)
+    for dp in [dataclasses.replace(base, ttab=torch.zeros(2, 4), tdh=1.0),
+               dataclasses.replace(base, aa=(12.5, 12.5, 4))]:
+        with pytest.raises(_lib.KirchhoffError) as e1:
+            ops.count(dp)
+        with pytest.raises(_lib.KirchhoffError) as e2:
+            ops.tune(0, dp, torch.zeros(dp.image_shape))
+        with pytest.raises(_lib.KirchhoffError) as e3:
+            ops.Batch([dp], [torch.zeros(dp.image_shape)])
+        assert e1.value.status == e2.value.status == e3.value.status == _lib.KM_E_UNSUPPORTED
