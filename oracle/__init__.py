@@ -13,7 +13,11 @@ max half-width) for the anti-alias triangle filter) and, where samples are neede
 (default: the problem's own data widened to float64).
 
 Parity status: all functions are pinned by the CPU tests (closed forms,
-invariants, adjoint identity, focusing); none is unpinned.
+invariants, adjoint identity, focusing); none is unpinned.  The pair counts
+(count, count_columns) are pinned by hand counts of the 45-degree cone, per
+column and in total, by exact-time cases that put u exactly at -1 and N_t and
+strictly inside (-1, 0) and (N_t - 1, N_t), and by the identity between the
+per-column and the total counts.
 """
 from __future__ import annotations
 

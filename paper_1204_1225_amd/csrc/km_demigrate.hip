@@ -158,35 +158,73 @@ __device__ __forceinline__ void dem_slot_aa(const PairAA& p, float x, double* ro
     atomicAdd(row + i + L + 1, b * be);
 }
 
-// Coordinates and image values (depth slots of this lane) of column (ix, iy).
-// Lanes past the last depth (only in the last chunk, TAIL) read the last
-// depth instead; they are never inside the aperture, so the value is unused.
+// Raw buffer resources (gfx9 family: no format conversion, no swizzle).
+// Out-of-range offsets read 0.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRawBufferWord3);
+}
+
+// Image values (this lane's depth slots) and coordinates of one swept column.
+template <int KS>
+struct Column {
+    float x[KS];
+    float px, py;
+};
+
+// Coordinates and image values of column (ix, iy) through buffer loads: the
+// resources and offsets are scalar (one resource per column; the lane's depth
+// offsets are fixed per chunk), so no VALU instruction computes an address,
+// and the loads count on the vector memory counter, so a wait for them never
+// waits for the LDS atomics the wavefront has queued (a scalar load's would).
+// voff (bytes from the column start): full chunks, voff[m] for the depth pair
+// of slots 2m, 2m + 1 (two adjacent depths, one 8-byte load); TAIL (a chunk
+// reaching outside [0, nz)), voff[k] per slot, the depth clamped into the
+// column (those lanes never pass the aperture test, their value is unused).
 template <int KS, bool TAIL>
-__device__ __forceinline__ void fetch_column(const Params& P, const float* img, int z0, int d, int ix, int iy,
-                                             float* xv, float& px, float& py) {
-    // Vector (not scalar) loads for the coordinates: a scalar load's wait also
-    // waits for every LDS atomic the wavefront has queued, which would drain
-    // the atomics once per column.
-    int ixv = ix, iyv = iy;
-    asm volatile("" : "+v"(ixv), "+v"(iyv));
-    px = P.x[ixv];
-    py = P.y[iyv];
+__device__ __forceinline__ void fetch_column(const Params& P, __amdgpu_buffer_rsrc_t rx, __amdgpu_buffer_rsrc_t ry,
+                                             const float* img, int ix, int iy, const int* voff, Column<KS>& c) {
+    c.px = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rx, 0, ix * 4, 0));
+    c.py = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(ry, 0, iy * 4, 0));
     const float* colp = img + (static_cast<int64_t>(iy) * P.nx + ix) * P.nz;
+    const __amdgpu_buffer_rsrc_t rc = raw_buffer(colp, static_cast<uint32_t>(P.nz) * 4u);
+    if (TAIL) {
 #pragma unroll
-    for (int k = 0; k < KS; ++k) {
-        const int iz = slot_depth<kIL>(z0, k, d);
-        xv[k] = colp[TAIL ? min(iz, P.nz - 1) : iz];
+        for (int k = 0; k < KS; ++k) c.x[k] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rc, voff[k], 0, 0));
+    } else {
+#pragma unroll
+        for (int m = 0; m < KS / 2; ++m) {
+            const auto v = __builtin_amdgcn_raw_buffer_load_b64(rc, voff[m], 0, 0);
+            c.x[2 * m] = __uint_as_float(v[0]);
+            c.x[2 * m + 1] = __uint_as_float(v[1]);
+        }
     }
+}
+
+// Next column of a wavefront's walk: the box columns wave, wave + NW, ... in
+// row-major order.  Returns false past the box.
+template <int NW>
+__device__ __forceinline__ bool next_column(int& ix, int& iy, int ix1, int iy1, int nbx) {
+    ix += NW;
+    while (ix > ix1) {
+        ix -= nbx;
+        ++iy;
+    }
+    return iy <= iy1;
 }
 
 // One depth chunk of the segment: wavefront `wave` takes the box columns
 // wave, wave + NW, ... in row-major order and scatters every pairing of a
-// column with the segment's traces into their rows.
+// column with the segment's traces into their rows.  The loop is unrolled by
+// two over a pair of column buffers (the next column is loaded while the
+// current one is evaluated, with no register copies between them).
 template <int NW, int KS, int NQ, bool TF, int WK, bool TAIL, int TT, bool PX>
 __device__ __forceinline__ void sweep_columns(const Params& P, const float* img, int z0, int d, int g, int wave, int t0,
                                               int nseg, int nq, int ix0, int ix1, int iy0, int iy1,
                                               const ChunkTables<KS>& T, const float* S, const float4* G, double* sAcc,
                                               const float* sInvSq) {
+    static_assert(kIL == 2, "the 8-byte image loads take the two interleaved slots of a depth pair");
     constexpr uint32_t kMask = (KS >= 32) ? ~0u : ((1u << KS) - 1u);
     constexpr bool AA = TT == TT_AA;
     float wlo, whi;
@@ -208,27 +246,22 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
     double* rows[NQ];
 #pragma unroll
     for (int q = 0; q < NQ; ++q) rows[q] = sAcc + (t0 + min(kGroupsPerWave * q + g, nseg - 1)) * P.lt + rowoff;
-    const int nbx = ix1 - ix0 + 1;
-    int ix = ix0 + wave, iy = iy0;
-    while (ix > ix1) {
-        ix -= nbx;
-        ++iy;
+    int voff[KS];
+#pragma unroll
+    for (int k = 0; k < KS; ++k) {
+        const int iz = slot_depth<kIL>(z0, TAIL ? k : 2 * (k % (KS / 2)), d);
+        voff[k] = 4 * (TAIL ? min(max(iz, 0), P.nz - 1) : iz);
     }
-    float xv[KS], pxv = 0.0f, pyv = 0.0f;
-    if (iy <= iy1) fetch_column<KS, TAIL>(P, img, z0, d, ix, iy, xv, pxv, pyv);
-    while (iy <= iy1) {
-        float x[KS];
+    const __amdgpu_buffer_rsrc_t rx = raw_buffer(P.x, static_cast<uint32_t>(P.nx) * 4u);
+    const __amdgpu_buffer_rsrc_t ry = raw_buffer(P.y, static_cast<uint32_t>(P.ny) * 4u);
+    const int nbx = ix1 - ix0 + 1;
+
+    // every pairing of column c with the segment's traces
+    auto process = [&](Column<KS>& c) {
+        const float px = c.px, py = c.py;
 #pragma unroll
-        for (int k = 0; k < KS; ++k) x[k] = xv[k];
-        const float px = pxv, py = pyv;
-        ix += NW;
-        while (ix > ix1) {
-            ix -= nbx;
-            ++iy;
-        }
-        if (iy <= iy1) fetch_column<KS, TAIL>(P, img, z0, d, ix, iy, xv, pxv, pyv);
-#pragma unroll
-        for (int k = 0; k < KS; ++k) x[k] *= S[k];
+        for (int k = 0; k < KS; ++k) c.x[k] *= S[k];
+        const float* x = c.x;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
             if (q >= nq) break;
@@ -259,8 +292,8 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
                     if (!((any >> k) & 3u)) continue;
-                    const int iz0 = min(slot_depth<kIL>(z0, k, d), P.nz - 1);
-                    const int iz1 = min(slot_depth<kIL>(z0, k + 1, d), P.nz - 1);
+                    const int iz0 = min(max(slot_depth<kIL>(z0, k, d), 0), P.nz - 1);
+                    const int iz1 = min(max(slot_depth<kIL>(z0, k + 1, d), 0), P.nz - 1);
                     dem_pair_table_ext<TF>(P, Ls, Lr, iz0, iz1, row, wlo, whi, x[k], x[k + 1], L.hmax <= T.R[k],
                                            L.hmax <= T.R[k + 1]);
                 }
@@ -271,8 +304,8 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
                     if (!((any >> k) & 3u)) continue;
-                    const int iz0 = min(slot_depth<kIL>(z0, k, d), P.nz - 1);
-                    const int iz1 = min(slot_depth<kIL>(z0, k + 1, d), P.nz - 1);
+                    const int iz0 = min(max(slot_depth<kIL>(z0, k, d), 0), P.nz - 1);
+                    const int iz1 = min(max(slot_depth<kIL>(z0, k + 1, d), 0), P.nz - 1);
                     dem_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1],
                                              L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
                 }
@@ -297,6 +330,25 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
                                    x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
             }
         }
+    };
+
+    int ix = ix0 + wave, iy = iy0;
+    while (ix > ix1) {
+        ix -= nbx;
+        ++iy;
+    }
+    if (iy > iy1) return;
+    Column<KS> ca, cb;
+    fetch_column<KS, TAIL>(P, rx, ry, img, ix, iy, voff, ca);
+    for (;;) {
+        const bool more_b = next_column<NW>(ix, iy, ix1, iy1, nbx);
+        if (more_b) fetch_column<KS, TAIL>(P, rx, ry, img, ix, iy, voff, cb);
+        process(ca);
+        if (!more_b) break;
+        const bool more_a = next_column<NW>(ix, iy, ix1, iy1, nbx);
+        if (more_a) fetch_column<KS, TAIL>(P, rx, ry, img, ix, iy, voff, ca);
+        process(cb);
+        if (!more_a) break;
     }
 }
 
@@ -336,7 +388,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
     by = wave_max(by);
 
     for (int zc = 0; zc < P.n_zchunks; ++zc) {
-        const int z0 = zc * KS * kGroup;
+        const int z0 = chunk_z0<true>(P.nz, zc, P.n_zchunks, KS * kGroup);
         ChunkTables<KS> T;
         load_chunk_tables<KS, kIL, TT, PX>(P, z0, d, WK == W_COSCOS, T, nullptr);
         if (!(T.rmax >= 0.0f)) continue;
@@ -344,7 +396,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int iz = slot_depth<kIL>(z0, k, d);
-            S[k] = (iz < P.nz) ? depth_factor<PX>(P, iz) : 0.0f;
+            S[k] = (iz >= 0 && iz < P.nz) ? depth_factor<PX>(P, iz) : 0.0f;
         }
         // a float32 leg with |dx| > sqrt(r2) (1 + 2^-22) cannot pass the
         // float32 aperture test, so this radius keeps every column that can
@@ -354,7 +406,7 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
         if (ix0 > ix1) continue;
         index_range(P.y, P.ny, static_cast<double>(ay) - rho, static_cast<double>(by) + rho, iy0, iy1);
         if (iy0 > iy1) continue;
-        if (z0 + KS * kGroup > P.nz)
+        if (z0 < 0)  // the partial (shallowest) chunk
             sweep_columns<NW, KS, NQ, TF, WK, true, TT, PX>(P, img, z0, d, g, wave, t0, nseg, nq, ix0, ix1, iy0, iy1, T,
                                                             S, G, sAcc, sInvSq);
         else

@@ -232,7 +232,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     const int wave = threadIdx.x / kLanes;
     const int g = lane / kGroup, d = lane % kGroup;
     const int ncol = P.nx * P.ny;
-    const int z0 = zc * KS * kGroup;
+    const int z0 = chunk_z0<false>(P.nz, zc, P.n_zchunks, KS * kGroup);
     const int nt = P.nt;
     // staged-row index of sample k is k + koff (eval_pair adds kLead with t_first)
     const int koff = TF ? kLead : 0;
@@ -548,8 +548,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
                             if ((any >> k) & 3ull) {
-                                const int iz0 = min(z0 + k * kGroup + d, P.nz - 1);
-                                const int iz1 = min(z0 + (k + 1) * kGroup + d, P.nz - 1);
+                                const int iz0 = min(max(z0 + k * kGroup + d, 0), P.nz - 1);
+                                const int iz1 = min(max(z0 + (k + 1) * kGroup + d, 0), P.nz - 1);
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
                                 mig_pair_table_ext<TF>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, wlo, whi, R0, R1, acc[q][k],
@@ -561,8 +561,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
                             if ((any >> k) & 3ull) {
-                                const int iz0 = min(z0 + k * kGroup + d, P.nz - 1);
-                                const int iz1 = min(z0 + (k + 1) * kGroup + d, P.nz - 1);
+                                const int iz0 = min(max(z0 + k * kGroup + d, 0), P.nz - 1);
+                                const int iz1 = min(max(z0 + (k + 1) * kGroup + d, 0), P.nz - 1);
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
                                 mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, tfo, wlo, whi, R0, R1, acc[q][k],
@@ -624,7 +624,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int iz = z0 + k * kGroup + d;
-            if (iz < P.nz) {
+            if (iz >= 0 && iz < P.nz) {
                 const float fac = depth_factor<PX>(P, iz);
                 const float val = fac != 0.0f ? acc[q][k] * fac : 0.0f;
                 colp[iz] = P.accumulate ? colp[iz] + val : val;
@@ -642,7 +642,7 @@ __device__ __forceinline__ void zero_tile(const Params& P, int b, int tile, int 
     const int wave = threadIdx.x / kLanes;
     const int g = lane / kGroup, d = lane % kGroup;
     const int ncol = P.nx * P.ny;
-    const int z0 = zc * KS * kGroup;
+    const int z0 = chunk_z0<false>(P.nz, zc, P.n_zchunks, KS * kGroup);
     float* img = P.image + static_cast<int64_t>(b) * ncol * P.nz;
 #pragma unroll
     for (int q = 0; q < CWQ; ++q) {
@@ -651,7 +651,7 @@ __device__ __forceinline__ void zero_tile(const Params& P, int b, int tile, int 
 #pragma unroll
         for (int k = 0; k < KS; ++k) {
             const int iz = z0 + k * kGroup + d;
-            if (iz < P.nz) img[static_cast<int64_t>(col) * P.nz + iz] = 0.0f;
+            if (iz >= 0 && iz < P.nz) img[static_cast<int64_t>(col) * P.nz + iz] = 0.0f;
         }
     }
 }

@@ -21,7 +21,7 @@ __global__ __launch_bounds__(kCountWaves * 64) void count_kernel(Params P, int c
     const int g = lane / kGroup, d = lane % kGroup;
     const int b = blockIdx.z, zc = blockIdx.y, tile = blockIdx.x;
     const int ncol = P.nx * P.ny;
-    const int z0 = zc * ks * kGroup;
+    const int z0 = chunk_z0<false>(P.nz, zc, gridDim.y, ks * kGroup);
     const int64_t lo = lower_bound_bin(P.bin, P.n_traces, b);
     const int64_t hi = lower_bound_bin(P.bin, P.n_traces, b + 1);
     const float tfu = P.has_tf ? static_cast<float>(kLead) - P.tf_off : 0.0f;  // t_first / dt
@@ -34,7 +34,7 @@ __global__ __launch_bounds__(kCountWaves * 64) void count_kernel(Params P, int c
         Rk[k] = -1.0f;
         Ak[k] = 1.0f;
         Bk[k] = 0.0f;
-        if (k < ks && iz < P.nz) {
+        if (k < ks && iz >= 0 && iz < P.nz) {
             Rk[k] = P.r2[iz];
             Ak[k] = static_cast<float>(static_cast<double>(P.t0sq[iz]) * P.inv_dt2);
             Bk[k] = static_cast<float>(static_cast<double>(P.s2[iz]) * P.inv_dt2);

@@ -9,6 +9,7 @@ diffraction stack written with Euclidean distances, an integer count of the
 45-degree aperture cone, and the focusing of point diffractors by
 constructive interference (Section 3).
 """
+import dataclasses
 import math
 
 import numpy as np
@@ -277,6 +278,86 @@ def test_count_45_degree_cone(oracle_lib):
     p.data = np.zeros((1, 10), np.float32)
     na2, ne2 = oracle_lib.count(p)
     assert na2 == expect and ne2 < na2
+
+
+def exact_time_problem(n_t, t_first=0.0, n_depths=16):
+    # One zero-offset trace straight above one image column.  v = 1024 m/s,
+    # dt = 1/256 s and depths z = 512 + k m make every time exact in binary:
+    # t0 = z / 1024, T_s + T_r = 2 t0, u = (2 t0 - t_first) / dt = 256 + k/2 -
+    # t_first/dt, with no rounding anywhere (squares of dyadic rationals, exact
+    # square roots).  h = 0, so every depth is inside the aperture.
+    z = 512.0 + np.arange(n_depths)
+    return hand_problem([1000, 0], [1000, 0], [0], np.zeros(n_t, np.float32), [1000.0], [0.0], z, v=1024.0,
+                        dt=1.0 / 256.0, t_first=t_first)
+
+
+@pytest.mark.parametrize("n_t,t_first,expect_eff", [
+    # u_k = 256 + k/2 (k = 0..15)
+    (260, 0.0, 8),             # k = 8 gives u = 260 = N_t exactly: excluded; k = 0..7 inside
+    (261, 0.0, 10),            # k = 9 gives u = 260.5 in (N_t - 1, N_t): included
+    (257, 0.0, 2),             # u = 256 = N_t - 1 (the last sample, f = 0) and 256.5: included
+    (256, 0.0, 0),             # u = 256 = N_t: excluded
+    (1000, 258.0 / 256.0, 13),  # u_k = k/2 - 2: k = 2 gives u = -1 exactly (excluded), k = 3 gives -0.5
+    (1000, 257.5 / 256.0, 14),  # u_k = k/2 - 1.5: k = 1 gives -1 (excluded), k = 2 gives -0.5 (included)
+])
+def test_count_effective_at_record_ends(oracle_lib, n_t, t_first, expect_eff):
+    # n_effective counts the pairs with -1 < u < N_t (Eq. (2)'s traces whose
+    # time falls where the zero-extended record has a sample that can be
+    # nonzero); the aperture count does not depend on the record.
+    p = exact_time_problem(n_t, t_first)
+    na, ne = oracle_lib.count(p)
+    assert na == 16
+    assert ne == expect_eff
+    assert oracle_lib.count_columns(p, [[0, 0, 0]]) == (16, expect_eff)
+
+
+def test_count_effective_values_are_the_interpolated_ones(oracle_lib):
+    # The pairs counted as effective are exactly those whose migrated value can
+    # be nonzero: with D = 1 everywhere, the image at depth k is the weight
+    # times (1 - f) D[i] + f D[i + 1] on the zero-extended record, which is 0
+    # iff u <= -1 or u >= N_t.
+    p = exact_time_problem(261, 258.5 / 256.0)  # u_k = k/2 - 2.5: k = 3 gives -1, k = 4 gives -0.5
+    p.data = np.ones((1, 261), np.float32)
+    p.weight = survey.WEIGHT_UNIT
+    img = oracle_lib.migrate(p)[0, 0, 0]
+    _, ne = oracle_lib.count(p)
+    assert ne == int(np.count_nonzero(img)) == 12
+    assert img[3] == 0.0 and img[4] == pytest.approx(0.5, rel=REL)
+
+
+def test_count_columns_cone_by_hand(oracle_lib):
+    # The 45-degree cone of test_count_45_degree_cone split by image column:
+    # column x = 1000 + 10 k holds depth iz iff 10 |k| <= 10 (iz + 1), i.e.
+    # 200 - max(|k| - 1, 0) of the 200 depths; with N_t = 100 (u = 2.5
+    # sqrt((iz + 1)^2 + k^2) samples at v = 2000 m/s, dt = 4 ms) the pairs with
+    # (iz + 1)^2 + k^2 < 1600 are effective (integer arithmetic below).
+    x = 1000.0 + 10.0 * np.arange(-50, 51)
+    z = 10.0 * (np.arange(200) + 1)
+    p = hand_problem([1000, 0], [1000, 0], [0], np.zeros(100, np.float32), x, [0.0], z)
+    for k in [-50, -37, -3, -1, 0, 1, 2, 29, 50]:
+        ix = k + 50
+        exp_ap = 200 - max(abs(k) - 1, 0)
+        exp_eff = sum(1 for iz in range(200) if iz + 1 >= abs(k) and (iz + 1) ** 2 + k * k < 1600)
+        assert oracle_lib.count_columns(p, [[0, 0, ix]]) == (exp_ap, exp_eff), k
+    # a column of another bin holds none of this bin-0 trace's pairs
+    p.n_bins = 2
+    assert oracle_lib.count_columns(p, [[1, 0, 50]]) == (0, 0)
+
+
+def test_count_columns_sum_to_count(oracle_lib, small):
+    # Summed over every image column of every bin, the per-column counts are
+    # the total counts (one evaluation path per column against all traces of
+    # its bin versus one per trace against all columns of its bin).
+    p = dataclasses.replace(small, n_t=120, t_first=0.03)
+    cols = np.array([(b, iy, ix) for b in range(p.n_bins) for iy in range(len(p.y)) for ix in range(len(p.x))],
+                    dtype=np.int32)
+    na, ne = oracle_lib.count(p)
+    assert oracle_lib.count_columns(p, cols) == (na, ne)
+    assert 0 < ne < na
+    half = cols[: len(cols) // 2]
+    a = oracle_lib.count_columns(p, half)
+    b = oracle_lib.count_columns(p, cols[len(cols) // 2:])
+    assert (a[0] + b[0], a[1] + b[1]) == (na, ne)
 
 
 # --------------------------------------------------------------------------
