@@ -220,6 +220,22 @@ km_status kirchhoff_demigrate_aa(const float* image, const km_grid* grid, const 
 km_status km_count_contributions(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
                                  int64_t* counts, void* stream);
 
+/* The same pair counts, exact, computed on the host from HOST copies of the
+ * inputs (the metric's denominator; Eq. (2)): traces (src, rec, bin; data is
+ * not read), grid (x, y) and traveltime tables (t0sq, s2, r2), all host
+ * pointers.  n_aperture = (trace, image point of the trace's bin) pairs that
+ * pass the kernels' float32 aperture decision; n_effective = those whose total
+ * time u = (T_s + T_r - t_first) / dt, in float64 from the float32 tables and
+ * coordinates, satisfies -1 < u < n_samples.  n_threads <= 0: one thread per
+ * hardware thread.  Synchronous; touches no device memory.  Cost: one float32
+ * leg evaluation per (image column, trace) pair, plus float64 times only on
+ * depths whose aperture does not keep every time inside the record; a
+ * non-monotone r2 table is tested depth by depth (much slower).
+ * KM_E_INVALID: NULL arguments or arrays, negative sizes, dt not finite and > 0. */
+km_status km_count_contributions_host(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                                      int32_t n_threads, int64_t* n_aperture /* host */,
+                                      int64_t* n_effective /* host */);
+
 /* out[0] = sum_k a[k] * b[k] accumulated in float64 (products exact in
  * float64); device double[1], overwritten.  Used for the adjoint
  * dot-product test and least-squares scalars.  Summation order not fixed. */
@@ -328,11 +344,15 @@ typedef struct km_problem {
 
 typedef struct km_batch km_batch;
 
-/* probs: host array of n problems.  tile: as for kirchhoff_migrate (one shape
- * for the whole batch).  Work-item costs are measured with the counting
- * kernel on `stream` (the call synchronises it).  Allocates device memory for
- * the problem table and queue (KM_E_NOMEM on failure). */
-km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void* stream, km_batch** out);
+/* probs: host array of n problems.  op: 0 = migrate (the only batched
+ * operator built; 1 = demigrate returns KM_E_UNSUPPORTED).  tile: as for
+ * kirchhoff_migrate (one shape for the whole batch).  Work-item costs are
+ * measured with the counting kernel on `stream` (the call synchronises it).
+ * Allocates device memory for the problem table and queue (KM_E_NOMEM on
+ * failure).  All problems share the weight kind, the time precision and
+ * whether t_first is 0 (KM_E_UNSUPPORTED otherwise). */
+km_status km_batch_create(const km_problem* probs, int32_t n, int32_t op, int32_t tile, void* stream,
+                          km_batch** out);
 /* Replay the captured graph on stream (asynchronous). */
 km_status km_batch_run(km_batch* batch, void* stream);
 /* Work items and persistent workgroups of the batch (host outputs, may be NULL). */

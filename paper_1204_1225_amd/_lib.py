@@ -80,6 +80,8 @@ SIGNATURES = {
     "kirchhoff_demigrate_aa": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmAntialias),
                                               _P(KmTraces), _i32, _i32, _vp]),
     "km_count_contributions": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTraveltime), _vp, _vp]),
+    "km_count_contributions_host": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTraveltime), _i32, _P(_i64),
+                                                   _P(_i64)]),
     "km_dot_f64": (ctypes.c_int, [_vp, _vp, _i64, _vp, _vp]),
     "km_axpby": (ctypes.c_int, [_f64, _vp, _f64, _vp, _i64, _vp]),
     "km_trace_filter": (ctypes.c_int, [_vp, _i64, _vp, _i64, _i64, _i32, _vp, _i32, _i32, _i32, _vp]),
@@ -91,7 +93,7 @@ SIGNATURES = {
                                _P(_i32), _P(ctypes.c_float)]),
     "km_tune_lookup": (_i32, [_i32, _i32, _i32, _i32]),
     "km_tune_record": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
-    "km_batch_create": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _vp, _P(_vp)]),
+    "km_batch_create": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _i32, _vp, _P(_vp)]),
     "km_batch_run": (ctypes.c_int, [_vp, _vp]),
     "km_batch_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32)]),
     "km_batch_destroy": (ctypes.c_int, [_vp]),

@@ -19,7 +19,8 @@ CSRC = os.path.join(HERE, "csrc")
 INCLUDE = os.path.join(ROOT, "include")
 BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libkirchhoff.so")
-SOURCES = ["km_api.cpp", "km_migrate.hip", "km_demigrate.hip", "km_misc.hip", "km_cig.hip", "km_filter.hip"]
+SOURCES = ["km_api.cpp", "km_count.cpp", "km_migrate.hip", "km_demigrate.hip", "km_misc.hip", "km_cig.hip",
+           "km_filter.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC", "-ffp-contract=off",

@@ -346,6 +346,9 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
 
 }  // namespace
 
+// Status and per-thread message for the C ABI calls defined in other files.
+km_status km_set_error(km_status st, const char* msg) { return fail(st, "%s", msg); }
+
 extern "C" {
 
 int km_abi_version(void) { return KM_ABI_VERSION; }
@@ -611,9 +614,12 @@ static void batch_free(km_batch* b) {
     delete b;
 }
 
-km_status km_batch_create(const km_problem* probs, int32_t n, int32_t tile, void* stream, km_batch** out) {
+km_status km_batch_create(const km_problem* probs, int32_t n, int32_t op, int32_t tile, void* stream,
+                          km_batch** out) {
     if (!out) return fail(KM_E_INVALID, "km_batch_create: out is NULL");
     *out = nullptr;
+    if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_batch_create: op must be 0 (migrate) or 1 (demigrate)");
+    if (op == 1) return fail(KM_E_UNSUPPORTED, "km_batch_create: batched demigration is not built");
     if (!probs || n < 1) return fail(KM_E_INVALID, "km_batch_create: need n >= 1 problems");
     hipStream_t s = static_cast<hipStream_t>(stream);
     for (int i = 0; i < n; ++i) {

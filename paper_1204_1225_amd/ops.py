@@ -234,6 +234,34 @@ def count(dp: DeviceProblem, aperture_only: bool = False):
     return int(v[0]), (None if aperture_only else int(v[1]))
 
 
+def count_host(problem, n_threads: int = 0):
+    """Exact (n_aperture, n_effective) of Eq. (2), counted on the host by the
+    library from host (numpy) copies of a problem's geometry and float32
+    tables: problem has src, rec, bin, x, y, t0sq, s2, r2, n_t, dt, t_first,
+    n_bins (a survey problem or anything with those attributes)."""
+    keep = {k: np.ascontiguousarray(getattr(problem, k), dtype=np.float32)
+            for k in ("src", "rec", "x", "y", "t0sq", "s2", "r2")}
+    keep["bin"] = np.ascontiguousarray(problem.bin, dtype=np.int32)
+    n = int(keep["src"].shape[0])
+    nz = int(keep["t0sq"].shape[0])
+    assert keep["rec"].shape == (n, 2) and keep["bin"].shape == (n,)
+    assert keep["s2"].shape == (nz,) and keep["r2"].shape == (nz,)
+
+    def ptr(a):
+        return ctypes.c_void_p(a.ctypes.data)
+
+    tr = KmTraces(n_traces=n, n_samples=int(problem.n_t), dtype=_lib.KM_F32, trace_stride=int(problem.n_t),
+                  t_first=float(problem.t_first), dt=float(problem.dt), data=None, scale=None, src=ptr(keep["src"]),
+                  rec=ptr(keep["rec"]), bin=ptr(keep["bin"]))
+    g = KmGrid(nx=int(keep["x"].shape[0]), ny=int(keep["y"].shape[0]), nz=nz, n_bins=int(problem.n_bins),
+               x=ptr(keep["x"]), y=ptr(keep["y"]))
+    tt = KmTraveltime(t0sq=ptr(keep["t0sq"]), s2=ptr(keep["s2"]), r2=ptr(keep["r2"]), time_precision=0)
+    na, ne = ctypes.c_int64(0), ctypes.c_int64(0)
+    check(_lib.load().km_count_contributions_host(ctypes.byref(tr), ctypes.byref(g), ctypes.byref(tt),
+                                                  int(n_threads), ctypes.byref(na), ctypes.byref(ne)))
+    return int(na.value), int(ne.value)
+
+
 def dot_f64(a: torch.Tensor, b: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """float64 device scalar sum(a * b) of two float32 tensors of equal size."""
     assert a.dtype == torch.float32 and b.dtype == torch.float32 and a.numel() == b.numel()
@@ -353,7 +381,7 @@ class Batch:
         self._arr = arr
         self._h = ctypes.c_void_p()
         dev = problems[0].device
-        check(_lib.load().km_batch_create(arr, len(problems), int(tile), ctypes.c_void_p(_stream(dev)),
+        check(_lib.load().km_batch_create(arr, len(problems), 0, int(tile), ctypes.c_void_p(_stream(dev)),
                                           ctypes.byref(self._h)))
         self.device = dev
 

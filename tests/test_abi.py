@@ -128,7 +128,10 @@ def test_reductions_reject_bad_arguments(lib):
     assert lib.km_axpby(float("nan"), ctypes.c_void_p(0x1000), 1.0, ctypes.c_void_p(0x1000), 4, None) == \
         _lib.KM_E_INVALID
     h = ctypes.c_void_p()
-    assert lib.km_batch_create(None, 0, -1, None, ctypes.byref(h)) == _lib.KM_E_INVALID
+    assert lib.km_batch_create(None, 0, 0, -1, None, ctypes.byref(h)) == _lib.KM_E_INVALID
+    assert lib.km_batch_create(None, 1, 2, -1, None, ctypes.byref(h)) == _lib.KM_E_INVALID
+    assert lib.km_batch_create(None, 1, 1, -1, None, ctypes.byref(h)) == _lib.KM_E_UNSUPPORTED
+    assert b"not built" in lib.km_last_error()
     assert lib.km_batch_run(None, None) == _lib.KM_E_INVALID
 
 
