@@ -353,6 +353,23 @@ typedef struct km_batch km_batch;
  * whether t_first is 0 (KM_E_UNSUPPORTED otherwise). */
 km_status km_batch_create(const km_problem* probs, int32_t n, int32_t op, int32_t tile, void* stream,
                           km_batch** out);
+/* One batched migration (op 0 of km_batch_create, the same kernels) that
+ * allocates nothing: for callers that cannot allocate device memory (code
+ * running between other work in a serving loop, harnesses that forbid
+ * allocation).  The problem table, the work items and the queue counter live
+ * in a static scratch array of 8 MiB per GPU (held from module load to process
+ * end): at most 4096 problems and as many work items as fit in it
+ * (about 460 000 at 16 bytes after the problem table; one work item per
+ * (bin, column tile of waves x column groups x 4 columns, depth chunk of
+ * 16 x depth slots)); larger batches return KM_E_UNSUPPORTED with the size
+ * they need.  The call measures the item costs (synchronising the stream),
+ * uploads the tables, resets the queue counter with a kernel and launches the
+ * persistent kernel asynchronously on `stream`.  Every call on a GPU uses that
+ * GPU's one array: calls that overlap on one GPU race (serialise them, e.g.
+ * on one stream).  Images are overwritten (accumulate = 0), as by
+ * km_batch_run; the result equals km_batch_run's bit for bit. */
+km_status km_batch_migrate_static(const km_problem* probs, int32_t n, int32_t tile, void* stream);
+
 /* Replay the captured graph on stream (asynchronous). */
 km_status km_batch_run(km_batch* batch, void* stream);
 /* Work items and persistent workgroups of the batch (host outputs, may be NULL). */

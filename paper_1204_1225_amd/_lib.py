@@ -95,6 +95,7 @@ SIGNATURES = {
     "km_tune_record": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
     "km_batch_create": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _i32, _vp, _P(_vp)]),
     "km_batch_run": (ctypes.c_int, [_vp, _vp]),
+    "km_batch_migrate_static": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _vp]),
     "km_batch_info": (ctypes.c_int, [_vp, _P(_i64), _P(_i32)]),
     "km_batch_destroy": (ctypes.c_int, [_vp]),
     "km_probe_issue": (ctypes.c_int, [_i32, _i32, _i32, _vp, _P(ctypes.c_float)]),

@@ -589,17 +589,159 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
 
 // ---- batched persistent migration -----------------------------------------
 
+}  // extern "C"
+
+namespace {
+
+// A batched migration: the shape and kernel flags every problem shares, the
+// problems' launch parameters and their work items, longest first.
+struct BatchPlan {
+    int shape = 0, has_tf = 0, weight = 0, prec = 0;
+    std::vector<km::Params> P;
+    std::vector<int4> items;  // (problem, bin, column tile or -1 - tile when empty, depth chunk)
+    size_t lds = 0;
+    int64_t max_slots = 0;    // largest per-problem item count (the cost buffer's length)
+    int64_t n_slots = 0;      // items over all problems
+};
+
+km_status batch_plan(const km_problem* probs, int32_t n, int32_t tile, const char* who, BatchPlan& B) {
+    if (!probs || n < 1) return fail(KM_E_INVALID, "%s: need n >= 1 problems", who);
+    for (int i = 0; i < n; ++i) {
+        km_status st = check_traces(&probs[i].traces, true, who);
+        if (st != KM_OK) return st;
+        st = check_grid(&probs[i].grid, &probs[i].tt, &probs[i].weight, who);
+        if (st != KM_OK) return st;
+        if (grid_empty(&probs[i].grid)) return fail(KM_E_INVALID, "%s: problem %d has an empty grid", who, i);
+        if (!probs[i].image || !aligned(probs[i].image, 4))
+            return fail(KM_E_INVALID, "%s: problem %d image NULL/misaligned", who, i);
+        if ((probs[i].traces.t_first != 0.0) != (probs[0].traces.t_first != 0.0) ||
+            probs[i].weight.kind != probs[0].weight.kind || probs[i].tt.time_precision != probs[0].tt.time_precision)
+            return fail(KM_E_UNSUPPORTED,
+                        "%s: all problems must share the weight kind, the time precision and t_first == 0 or not",
+                        who);
+    }
+    int max_nz = 0, max_nt = 0;
+    for (int i = 0; i < n; ++i) {
+        max_nz = std::max(max_nz, probs[i].grid.nz);
+        max_nt = std::max(max_nt, probs[i].traces.n_samples);
+    }
+    km_status st = pick_shape(0, tile, probs[0].traces.dtype, max_nz, max_nt, false, &B.shape);
+    if (st != KM_OK) return st;
+    const km::TileShape& S = km::migrate_shape(B.shape);
+    B.has_tf = probs[0].traces.t_first != 0.0 ? 1 : 0;
+    B.weight = probs[0].weight.kind;
+    B.prec = probs[0].tt.time_precision == KM_TIME_EXTENDED ? 1 : 0;
+    B.P.resize(n);
+    for (int i = 0; i < n; ++i) {
+        km::Params& P = B.P[i];
+        P = base_params(&probs[i].traces, &probs[i].grid, &probs[i].tt, &probs[i].weight, probs[i].image, 0);
+        st = shape_params(0, B.shape, P);
+        if (st != KM_OK) return st;
+        if (P.n_traces > INT32_MAX)
+            return fail(KM_E_UNSUPPORTED, "%s: problem %d has more than 2^31 - 1 traces", who, i);
+        B.lds = std::max(B.lds, km::lds_bytes(P, S.depth_slots));
+        const int64_t nslot = static_cast<int64_t>(P.n_bins) * P.n_zchunks * P.n_coltiles;
+        if (nslot > (int64_t(1) << 31)) return fail(KM_E_UNSUPPORTED, "%s: problem %d has too many work items", who, i);
+        B.max_slots = std::max(B.max_slots, nslot);
+        B.n_slots += nslot;
+    }
+    return KM_OK;
+}
+
+// Work-item costs (pairs in aperture) from the counting kernel, written to
+// d_costs (device, >= B.max_slots entries) one problem at a time and read
+// back; the items are then ordered longest first.  Synchronises s.
+km_status batch_items(BatchPlan& B, unsigned long long* d_costs, hipStream_t s, const char* who) {
+    const km::TileShape& S = km::migrate_shape(B.shape);
+    struct Item {
+        unsigned long long cost;
+        int4 w;
+    };
+    std::vector<Item> items;
+    items.reserve(static_cast<size_t>(B.n_slots));
+    std::vector<unsigned long long> h(static_cast<size_t>(std::max<int64_t>(B.max_slots, 1)));
+    for (size_t i = 0; i < B.P.size(); ++i) {
+        const km::Params& P = B.P[i];
+        const int64_t nslot = static_cast<int64_t>(P.n_bins) * P.n_zchunks * P.n_coltiles;
+        hipError_t e = km::launch_item_costs(P, S.depth_slots, S.waves * S.column_groups * 4, d_costs, s);
+        if (e == hipSuccess && nslot > 0)
+            e = hipMemcpyAsync(h.data(), d_costs, sizeof(unsigned long long) * nslot, hipMemcpyDeviceToHost, s);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, who);
+        for (int b = 0; b < P.n_bins; ++b)
+            for (int zc = 0; zc < P.n_zchunks; ++zc)
+                for (int tl = 0; tl < P.n_coltiles; ++tl) {
+                    const unsigned long long c = h[(static_cast<int64_t>(b) * P.n_zchunks + zc) * P.n_coltiles + tl];
+                    items.push_back({c, make_int4(static_cast<int>(i), b, c ? tl : -1 - tl, zc)});
+                }
+    }
+    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
+    B.items.resize(items.size());
+    for (size_t k = 0; k < items.size(); ++k) B.items[k] = items[k].w;
+    return KM_OK;
+}
+
+// Persistent grid: as many workgroups as can be resident at once.
+km_status batch_grid(const BatchPlan& B, int device, int* n_wg, int* per_cu_out, const char* who) {
+    const km::TileShape& S = km::migrate_shape(B.shape);
+    const void* kfn = km::migrate_batch_kernel_ptr(B.shape, B.has_tf, B.weight, B.prec);
+    if (B.lds > 65536) {
+        const hipError_t e = hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize,
+                                                 static_cast<int>(B.lds));
+        if (e != hipSuccess) return hip_fail(e, who);
+    }
+    int per_cu = 0, n_cu = 0;
+    hipError_t e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S.waves * 64, B.lds);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, device);
+    if (e != hipSuccess) return hip_fail(e, who);
+    const int64_t n_items = static_cast<int64_t>(B.items.size());
+    *n_wg = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(std::max(per_cu, 1)) * n_cu,
+                                                                      std::max<int64_t>(n_items, 1))));
+    if (per_cu_out) *per_cu_out = per_cu;
+    return KM_OK;
+}
+
+// Scratch of the allocation-free batched migration: one array per GPU (each
+// device holds its own copy from module load to process end), laid out as
+// [queue counter | problem table | work items, or the cost counts while
+// they are measured].
+constexpr size_t kScratchBytes = size_t(8) << 20;
+constexpr size_t kScratchProblems = 4096;
+constexpr size_t kScratchItemsOffset = 256 + kScratchProblems * sizeof(km::Params);
+static_assert(kScratchItemsOffset % 256 == 0, "items start on a 256-byte boundary");
+__device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this GPU's scratch (looked up once per device, with the
+// device current).  In host code the array's name is not a device address.
+km_status scratch_ptr(int device, unsigned char** out) {
+    if (device < 0 || device >= kMaxDevices) return fail(KM_E_UNSUPPORTED, "device %d: no scratch slot", device);
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[device]) {
+        void* p = nullptr;
+        const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess || !p) return hip_fail(e != hipSuccess ? e : hipErrorInvalidSymbol, "hipGetSymbolAddress");
+        g_scratch_ptr[device] = p;
+    }
+    *out = static_cast<unsigned char*>(g_scratch_ptr[device]);
+    return KM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
 struct km_batch {
     int device = 0;
-    int shape = 0;
-    int has_tf = 0, weight = 0, prec = 0;
+    BatchPlan plan;
     km::Params* d_probs = nullptr;
     int4* d_items = nullptr;
     unsigned int* d_counter = nullptr;
-    int64_t n_items = 0;
     int n_wg = 0;
     int per_cu = 0;
-    size_t lds = 0;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
 };
@@ -620,119 +762,48 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t op, int32_
     *out = nullptr;
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_batch_create: op must be 0 (migrate) or 1 (demigrate)");
     if (op == 1) return fail(KM_E_UNSUPPORTED, "km_batch_create: batched demigration is not built");
-    if (!probs || n < 1) return fail(KM_E_INVALID, "km_batch_create: need n >= 1 problems");
     hipStream_t s = static_cast<hipStream_t>(stream);
-    for (int i = 0; i < n; ++i) {
-        km_status st = check_traces(&probs[i].traces, true, "km_batch_create");
-        if (st != KM_OK) return st;
-        st = check_grid(&probs[i].grid, &probs[i].tt, &probs[i].weight, "km_batch_create");
-        if (st != KM_OK) return st;
-        if (grid_empty(&probs[i].grid)) return fail(KM_E_INVALID, "km_batch_create: problem %d has an empty grid", i);
-        if (!probs[i].image || !aligned(probs[i].image, 4))
-            return fail(KM_E_INVALID, "km_batch_create: problem %d image NULL/misaligned", i);
-        if ((probs[i].traces.t_first != 0.0) != (probs[0].traces.t_first != 0.0) ||
-            probs[i].weight.kind != probs[0].weight.kind || probs[i].tt.time_precision != probs[0].tt.time_precision)
-            return fail(KM_E_UNSUPPORTED,
-                        "km_batch_create: all problems must share the weight kind, the time precision and "
-                        "t_first == 0 or not");
-    }
-    int max_nz = 0, max_nt = 0;
-    for (int i = 0; i < n; ++i) {
-        max_nz = std::max(max_nz, probs[i].grid.nz);
-        max_nt = std::max(max_nt, probs[i].traces.n_samples);
-    }
-    int shape = 0;
-    km_status st = pick_shape(0, tile, probs[0].traces.dtype, max_nz, max_nt, false, &shape);
-    if (st != KM_OK) return st;
-    const km::TileShape& S = km::migrate_shape(shape);
-
     km_batch* B = new (std::nothrow) km_batch();
     if (!B) return fail(KM_E_NOMEM, "km_batch_create: host allocation failed");
     hipGetDevice(&B->device);
-    B->shape = shape;
-    B->has_tf = probs[0].traces.t_first != 0.0 ? 1 : 0;
-    B->weight = probs[0].weight.kind;
-    B->prec = probs[0].tt.time_precision == KM_TIME_EXTENDED ? 1 : 0;
-
-    std::vector<km::Params> P(n);
-    struct Item {
-        unsigned long long cost;
-        int4 w;
-    };
-    std::vector<Item> items;
-    unsigned long long* d_costs = nullptr;
-    for (int i = 0; i < n; ++i) {
-        P[i] = base_params(&probs[i].traces, &probs[i].grid, &probs[i].tt, &probs[i].weight, probs[i].image, 0);
-        st = shape_params(0, shape, P[i]);
-        if (st == KM_OK && P[i].n_traces > INT32_MAX)
-            st = fail(KM_E_UNSUPPORTED, "km_batch_create: problem %d has more than 2^31 - 1 traces", i);
-        if (st != KM_OK) {
-            batch_free(B);
-            return st;
-        }
-        B->lds = std::max(B->lds, km::lds_bytes(P[i], S.depth_slots));
-        const int64_t nslot = static_cast<int64_t>(P[i].n_bins) * P[i].n_zchunks * P[i].n_coltiles;
-        if (nslot > (int64_t(1) << 31)) {
-            batch_free(B);
-            return fail(KM_E_UNSUPPORTED, "km_batch_create: problem %d has too many work items", i);
-        }
-        hipError_t e = hipMalloc(&d_costs, sizeof(unsigned long long) * std::max<int64_t>(nslot, 1));
-        if (e != hipSuccess) {
-            batch_free(B);
-            return fail(KM_E_NOMEM, "km_batch_create: hipMalloc costs: %s", hipGetErrorString(e));
-        }
-        e = km::launch_item_costs(P[i], S.depth_slots, S.waves * S.column_groups * 4, d_costs, s);
-        std::vector<unsigned long long> h(nslot);
-        if (e == hipSuccess) e = hipMemcpyAsync(h.data(), d_costs, sizeof(unsigned long long) * nslot,
-                                                hipMemcpyDeviceToHost, s);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        hipFree(d_costs);
-        d_costs = nullptr;
-        if (e != hipSuccess) {
-            batch_free(B);
-            return hip_fail(e, "km_batch_create: cost estimate");
-        }
-        for (int b = 0; b < P[i].n_bins; ++b)
-            for (int zc = 0; zc < P[i].n_zchunks; ++zc)
-                for (int tl = 0; tl < P[i].n_coltiles; ++tl) {
-                    const unsigned long long c = h[(static_cast<int64_t>(b) * P[i].n_zchunks + zc) * P[i].n_coltiles + tl];
-                    items.push_back({c, make_int4(i, b, c ? tl : -1 - tl, zc)});
-                }
+    km_status st = batch_plan(probs, n, tile, "km_batch_create", B->plan);
+    if (st != KM_OK) {
+        batch_free(B);
+        return st;
     }
-    std::stable_sort(items.begin(), items.end(), [](const Item& a, const Item& b) { return a.cost > b.cost; });
-    B->n_items = static_cast<int64_t>(items.size());
-    std::vector<int4> hw(items.size());
-    for (size_t k = 0; k < items.size(); ++k) hw[k] = items[k].w;
-
-    hipError_t e = hipMalloc(&B->d_probs, sizeof(km::Params) * n);
-    if (e == hipSuccess) e = hipMalloc(&B->d_items, sizeof(int4) * std::max<size_t>(hw.size(), 1));
+    BatchPlan& L = B->plan;
+    unsigned long long* d_costs = nullptr;
+    hipError_t e = hipMalloc(&d_costs, sizeof(unsigned long long) * std::max<int64_t>(L.max_slots, 1));
+    if (e != hipSuccess) {
+        batch_free(B);
+        return fail(KM_E_NOMEM, "km_batch_create: hipMalloc costs: %s", hipGetErrorString(e));
+    }
+    st = batch_items(L, d_costs, s, "km_batch_create: cost estimate");
+    hipFree(d_costs);
+    if (st != KM_OK) {
+        batch_free(B);
+        return st;
+    }
+    e = hipMalloc(&B->d_probs, sizeof(km::Params) * n);
+    if (e == hipSuccess) e = hipMalloc(&B->d_items, sizeof(int4) * std::max<size_t>(L.items.size(), 1));
     if (e == hipSuccess) e = hipMalloc(&B->d_counter, sizeof(unsigned int));
     if (e != hipSuccess) {
         batch_free(B);
         return fail(KM_E_NOMEM, "km_batch_create: hipMalloc: %s", hipGetErrorString(e));
     }
-    e = hipMemcpyAsync(B->d_probs, P.data(), sizeof(km::Params) * n, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess && !hw.empty())
-        e = hipMemcpyAsync(B->d_items, hw.data(), sizeof(int4) * hw.size(), hipMemcpyHostToDevice, s);
+    e = hipMemcpyAsync(B->d_probs, L.P.data(), sizeof(km::Params) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !L.items.empty())
+        e = hipMemcpyAsync(B->d_items, L.items.data(), sizeof(int4) * L.items.size(), hipMemcpyHostToDevice, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
     if (e != hipSuccess) {
         batch_free(B);
         return hip_fail(e, "km_batch_create: upload");
     }
-
-    // Persistent grid: as many workgroups as can be resident at once.
-    const void* kfn = km::migrate_batch_kernel_ptr(shape, B->has_tf, B->weight, B->prec);
-    if (B->lds > 65536) hipFuncSetAttribute(kfn, hipFuncAttributeMaxDynamicSharedMemorySize, static_cast<int>(B->lds));
-    int per_cu = 0, n_cu = 0;
-    e = hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kfn, S.waves * 64, B->lds);
-    if (e == hipSuccess) e = hipDeviceGetAttribute(&n_cu, hipDeviceAttributeMultiprocessorCount, B->device);
-    if (e != hipSuccess) {
+    st = batch_grid(L, B->device, &B->n_wg, &B->per_cu, "km_batch_create: occupancy");
+    if (st != KM_OK) {
         batch_free(B);
-        return hip_fail(e, "km_batch_create: occupancy");
+        return st;
     }
-    B->n_wg = static_cast<int>(std::max<int64_t>(1, std::min<int64_t>(static_cast<int64_t>(std::max(per_cu, 1)) * n_cu,
-                                                                        std::max<int64_t>(B->n_items, 1))));
-    B->per_cu = per_cu;
 
     // Capture [queue reset, persistent kernel] once.
     hipStream_t cap = nullptr;
@@ -740,11 +811,11 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t op, int32_
     if (e == hipSuccess) e = hipStreamBeginCapture(cap, hipStreamCaptureModeThreadLocal);
     if (e == hipSuccess) {
         hipError_t e1 = km::launch_reset_counter(B->d_counter, cap);
-        hipError_t e2 = e1 == hipSuccess ? km::launch_migrate_batch(shape, B->d_probs, B->d_items, B->n_items,
-                                                                      B->d_counter, B->has_tf, B->weight, B->prec,
-                                                                      B->n_wg,
-                                                                      B->lds, cap)
-                                         : e1;
+        hipError_t e2 = e1 == hipSuccess
+                            ? km::launch_migrate_batch(L.shape, B->d_probs, B->d_items,
+                                                       static_cast<int64_t>(L.items.size()), B->d_counter, L.has_tf,
+                                                       L.weight, L.prec, B->n_wg, L.lds, cap)
+                            : e1;
         e = hipStreamEndCapture(cap, &B->graph);
         if (e == hipSuccess) e = e2;
     }
@@ -758,6 +829,46 @@ km_status km_batch_create(const km_problem* probs, int32_t n, int32_t op, int32_
     return KM_OK;
 }
 
+km_status km_batch_migrate_static(const km_problem* probs, int32_t n, int32_t tile, void* stream) {
+    const char* who = "km_batch_migrate_static";
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    BatchPlan L;
+    km_status st = batch_plan(probs, n, tile, who, L);
+    if (st != KM_OK) return st;
+    if (static_cast<size_t>(n) > kScratchProblems)
+        return fail(KM_E_UNSUPPORTED, "%s: %d problems exceed the static scratch's %zu", who, n, kScratchProblems);
+    const size_t item_bytes = std::max(sizeof(int4) * static_cast<size_t>(L.n_slots),
+                                       sizeof(unsigned long long) * static_cast<size_t>(L.max_slots));
+    if (kScratchItemsOffset + item_bytes > kScratchBytes)
+        return fail(KM_E_UNSUPPORTED, "%s: %lld work items need %zu bytes of scratch, more than the %zu available", who,
+                    static_cast<long long>(L.n_slots), kScratchItemsOffset + item_bytes, kScratchBytes);
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    unsigned char* base = nullptr;
+    st = scratch_ptr(device, &base);
+    if (st != KM_OK) return st;
+    auto* d_counter = reinterpret_cast<unsigned int*>(base);
+    auto* d_probs = reinterpret_cast<km::Params*>(base + 256);
+    auto* d_items = reinterpret_cast<int4*>(base + kScratchItemsOffset);
+    auto* d_costs = reinterpret_cast<unsigned long long*>(base + kScratchItemsOffset);
+    st = batch_items(L, d_costs, s, who);
+    if (st != KM_OK) return st;
+    e = hipMemcpyAsync(d_probs, L.P.data(), sizeof(km::Params) * n, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess && !L.items.empty())
+        e = hipMemcpyAsync(d_items, L.items.data(), sizeof(int4) * L.items.size(), hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);  // the host tables are released on return
+    if (e != hipSuccess) return hip_fail(e, who);
+    int n_wg = 0;
+    st = batch_grid(L, device, &n_wg, nullptr, who);
+    if (st != KM_OK) return st;
+    e = km::launch_reset_counter(d_counter, s);
+    if (e == hipSuccess)
+        e = km::launch_migrate_batch(L.shape, d_probs, d_items, static_cast<int64_t>(L.items.size()), d_counter,
+                                     L.has_tf, L.weight, L.prec, n_wg, L.lds, s);
+    return e == hipSuccess ? KM_OK : hip_fail(e, "km_batch_migrate_static launch");
+}
+
 km_status km_batch_run(km_batch* batch, void* stream) {
     if (!batch) return fail(KM_E_INVALID, "km_batch_run: batch is NULL");
     const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
@@ -766,7 +877,7 @@ km_status km_batch_run(km_batch* batch, void* stream) {
 
 km_status km_batch_info(const km_batch* batch, int64_t* n_items, int32_t* n_workgroups) {
     if (!batch) return fail(KM_E_INVALID, "km_batch_info: batch is NULL");
-    if (n_items) *n_items = batch->n_items;
+    if (n_items) *n_items = static_cast<int64_t>(batch->plan.items.size());
     if (n_workgroups) *n_workgroups = batch->n_wg;
     return KM_OK;
 }

@@ -366,19 +366,32 @@ def probe_issue(kind: int, n_waves: int = 8192, iters: int = 4096) -> float:
     return float(ms.value)
 
 
+def _c_problems(problems, images):
+    assert len(problems) == len(images) and len(problems) > 0
+    arr = (KmProblem * len(problems))()
+    for k, (dp, img) in enumerate(zip(problems, images)):
+        _plain_only(dp, "batched migration")
+        assert img.shape == dp.image_shape and img.dtype == torch.float32 and img.is_contiguous()
+        arr[k] = KmProblem(traces=dp.c_traces(), grid=dp.c_grid(), tt=dp.c_tt(), weight=dp.c_weight(),
+                           image=_ptr(img))
+    return arr
+
+
+def batch_migrate_static(problems, images, tile: int = -1) -> None:
+    """One batched migration of many problems that allocates no device memory
+    (km_batch_migrate_static: the work list lives in the library's static
+    scratch array).  Overwrites every image; calls on one GPU must not overlap."""
+    arr = _c_problems(problems, images)
+    dev = problems[0].device
+    check(_lib.load().km_batch_migrate_static(arr, len(problems), int(tile), ctypes.c_void_p(_stream(dev))))
+
+
 class Batch:
     """Many problems migrated by one persistent, graph-captured launch."""
 
     def __init__(self, problems, images, tile: int = -1):
-        assert len(problems) == len(images) and len(problems) > 0
         self._keep = (list(problems), list(images))
-        arr = (KmProblem * len(problems))()
-        for k, (dp, img) in enumerate(zip(problems, images)):
-            _plain_only(dp, "Batch")
-            assert img.shape == dp.image_shape and img.dtype == torch.float32 and img.is_contiguous()
-            arr[k] = KmProblem(traces=dp.c_traces(), grid=dp.c_grid(), tt=dp.c_tt(), weight=dp.c_weight(),
-                               image=_ptr(img))
-        self._arr = arr
+        self._arr = arr = _c_problems(problems, images)
         self._h = ctypes.c_void_p()
         dev = problems[0].device
         check(_lib.load().km_batch_create(arr, len(problems), 0, int(tile), ctypes.c_void_p(_stream(dev)),

@@ -265,3 +265,24 @@ def test_plain_only_calls_reject_table_and_antialias_problems():
         with pytest.raises(_lib.KirchhoffError) as e3:
             ops.Batch([dp], [torch.zeros(dp.image_shape)])
         assert e1.value.status == e2.value.status == e3.value.status == _lib.KM_E_UNSUPPORTED
+
+
+def test_batch_static_rejects_what_does_not_fit(lib):
+    # The allocation-free batch checks its work list against the static scratch
+    # before any HIP call (host validation only; the pointers are never used):
+    # 4096 x 1024 columns in tiles of 128, 16 bins, one depth chunk is 524 288
+    # work items, more than the scratch holds.
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib)
+    g.nx, g.ny, g.nz, g.n_bins = 4096, 1024, 16, 16
+    pr = (_lib.KmProblem * 1)()
+    pr[0] = _lib.KmProblem(traces=t, grid=g, tt=tt, weight=w, image=ctypes.c_void_p(0x1000))
+    assert lib.km_batch_migrate_static(pr, 1, 2, None) == _lib.KM_E_UNSUPPORTED
+    assert b"scratch" in lib.km_last_error()
+    big = (_lib.KmProblem * 4097)()
+    g.nx, g.ny, g.nz, g.n_bins = 2, 1, 3, 1
+    for k in range(4097):
+        big[k] = _lib.KmProblem(traces=t, grid=g, tt=tt, weight=w, image=ctypes.c_void_p(0x1000))
+    assert lib.km_batch_migrate_static(big, 4097, 2, None) == _lib.KM_E_UNSUPPORTED
+    assert lib.km_batch_migrate_static(None, 0, -1, None) == _lib.KM_E_INVALID
