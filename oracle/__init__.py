@@ -69,6 +69,7 @@ def _load():
         lib.oracle_migrate.argtypes = [P, vp]
         lib.oracle_migrate_columns.argtypes = [P, i64, vp, vp]
         lib.oracle_migrate_points.argtypes = [P, i64, vp, vp]
+        lib.oracle_migrate_window.argtypes = [P, i64, vp, ctypes.c_int32, ctypes.c_int32, vp]
         lib.oracle_demigrate.argtypes = [P, vp, vp]
         lib.oracle_demigrate_samples.argtypes = [P, vp, i64, vp, vp]
         lib.oracle_count.argtypes = [P, ctypes.POINTER(i64), ctypes.POINTER(i64)]
@@ -143,6 +144,18 @@ def migrate_columns(p, cols, data=None) -> np.ndarray:
     out = np.zeros((cols.shape[0], len(p.t0sq)), dtype=np.float64)
     if _load().oracle_migrate_columns(b.ref, cols.shape[0], cols.ctypes.data, out.ctypes.data) != 0:
         raise ValueError("oracle_migrate_columns rejected the problem")
+    return out
+
+
+def migrate_window(p, cols, z_lo, z_hi, data=None) -> np.ndarray:
+    """Depths z_lo .. z_hi - 1 of image columns cols[k] = (bin, iy, ix) ->
+    [len(cols), z_hi - z_lo] in FP64 (a sub-volume)."""
+    b = _Bound(p, data)
+    cols = _arr(cols, np.int32).reshape(-1, 3)
+    out = np.zeros((cols.shape[0], int(z_hi) - int(z_lo)), dtype=np.float64)
+    if _load().oracle_migrate_window(b.ref, cols.shape[0], cols.ctypes.data, int(z_lo), int(z_hi),
+                                     out.ctypes.data) != 0:
+        raise ValueError("oracle_migrate_window rejected the problem")
     return out
 
 

@@ -260,6 +260,32 @@ int oracle_migrate_columns(const ko_problem* P, int64_t n_cols, const int32_t* c
     return 0;
 }
 
+/* Depths z_lo <= iz < z_hi of image columns cols[3*c .. 3*c+2] = (b, iy, ix);
+ * out[c][iz - z_lo] (z_hi - z_lo values each): the same sums as
+ * oracle_migrate_columns over a window of depths (a sub-volume). */
+int oracle_migrate_window(const ko_problem* P, int64_t n_cols, const int32_t* cols, int32_t z_lo, int32_t z_hi,
+                          double* out)
+{
+    if (ko_check(P) || !P->data || z_lo < 0 || z_hi > P->nz || z_lo > z_hi) return 1;
+    const int32_t nw = z_hi - z_lo;
+#pragma omp parallel for schedule(dynamic, 1)
+    for (int64_t c = 0; c < n_cols; ++c) {
+        const int b = cols[3 * c], iy = cols[3 * c + 1], ix = cols[3 * c + 2];
+        double* o = out + c * (int64_t)nw;
+        for (int k = 0; k < nw; ++k) o[k] = 0.0;
+        for (int64_t j = 0; j < P->n_traces; ++j) {
+            if (P->bin[j] != b) continue;
+            const double* d = P->data + j * (int64_t)P->n_t;
+            for (int iz = z_lo; iz < z_hi; ++iz) {
+                double u, w, p = 1.0;
+                if (!ko_pair_p(P, j, ix, iy, iz, &u, &w, &p)) continue;
+                o[iz - z_lo] += w * ko_value(P, d, u, p);
+            }
+        }
+    }
+    return 0;
+}
+
 /* Full image I[n_bins][ny][nx][nz] (overwritten). */
 int oracle_migrate(const ko_problem* P, double* image)
 {

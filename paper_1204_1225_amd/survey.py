@@ -558,6 +558,22 @@ def make_batch_line(shape, index=0):
                    ("linear", 1500.0, 0.5), 60.0)
 
 
+def with_diffractors(p: Problem, seed: int, n: int = 3, min_sep_m: float = 100.0, device=None) -> Problem:
+    """Point diffractors at seeded image grid nodes of a 2D line (the middle
+    half of its columns and of its depths, at least min_sep_m apart); the
+    traces become their modelled data (25 Hz Ricker, no noise)."""
+    rng = np.random.default_rng(seed)
+    nx, nz = len(p.x), len(p.z)
+    dx = float(p.x[1] - p.x[0]) if nx > 1 else 1.0
+    dz = float(p.z[1] - p.z[0]) if nz > 1 else 1.0
+    nodes = _pick_nodes(rng, (nx // 4, max(nx // 4 + 1, 3 * nx // 4)), (nz // 4, max(nz // 4 + 1, 3 * nz // 4)), n,
+                        min_sep_m, dx, dz)
+    p.diffractor_nodes = nodes
+    p.scatterers = np.stack([p.x[nodes[:, 0]].astype(np.float64), np.zeros(n), p.z[nodes[:, 2]]], 1)
+    p.data = model_scatterers(p, p.scatterers, device=device).cpu().numpy()
+    return p
+
+
 def make_random(seed, n_traces, n_t, nx, ny, nz, n_bins, velocity=("linear", 1500.0, 0.5),
                 aperture_deg=60.0, dx=12.5, dz=5.0, spread=600.0, t_first=0.0, dt=0.004,
                 weight=WEIGHT_COSCOS, data="bandlimited"):

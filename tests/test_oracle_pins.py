@@ -249,6 +249,17 @@ def test_adjoint_spike_closed_form(oracle_lib):
     assert np.count_nonzero(d) == 2
 
 
+def test_window_is_columns_restricted(oracle_lib, small):
+    # a depth window of columns is the same sum, depth by depth (bit for bit:
+    # same pair evaluations added in the same trace order)
+    cols = np.array([[0, 0, 0], [1, 3, 4], [2, 6, 8], [0, 5, 2]], np.int32)
+    full = oracle_lib.migrate_columns(small, cols)
+    for z_lo, z_hi in [(0, 40), (7, 23), (39, 40), (12, 12)]:
+        assert np.array_equal(oracle_lib.migrate_window(small, cols, z_lo, z_hi), full[:, z_lo:z_hi])
+    with pytest.raises(ValueError):
+        oracle_lib.migrate_window(small, cols, 30, 41)
+
+
 def test_pointwise_entry_points_agree(oracle_lib, small):
     full = oracle_lib.migrate(small)
     pts = np.array([[b, iy, ix, iz] for b, iy, ix, iz in [(0, 3, 4, 39), (2, 0, 8, 10), (1, 6, 0, 25)]])
