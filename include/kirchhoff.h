@@ -133,8 +133,8 @@ int32_t km_max_samples(void);
 /* Migration, Eq. (1): image[n_bins][ny][nx][nz] (float32) from traces.
  * accumulate = 0 overwrites the image; 1 adds into it (Reduce = sum,
  * Section 4, so migrating trace subsets with accumulate = 1 sums them).
- * tile: -1 = library choice (tuned shape if km_tune_migrate recorded one for
- * this shape class, else a default); otherwise an index < km_tile_count(0).
+ * tile: -1 = library choice (the tile km_tune recorded for this problem's
+ * class, else a default); otherwise a tile (see km_tile_describe).
  * Work: one float32 evaluation per (trace, image point of its bin) pair that
  * passes the aperture test. */
 km_status kirchhoff_migrate(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
@@ -302,30 +302,48 @@ km_status km_cig_moveout(const float* image, const km_grid* grid, const float* o
                          void* stream);
 
 /* ---- tile shapes and tuning ------------------------------------------------
- * op: 0 = migrate, 1 = demigrate. */
+ * op: 0 = migrate, 1 = demigrate.  A tile is a compiled shape (waves, column
+ * groups, depth slots, LDS budget; km_tile_count(op) of them) and a runtime
+ * level of it, passed as tile = shape + 64 * level, level < km_tile_levels(op):
+ * migrate levels scale the trace block's LDS budget (traces per block) by 1,
+ * 0.5, 1.5 and 2 (at most 160 KiB); demigrate level 0 takes as many trace quads
+ * per workgroup as the shape allows, level L >= 1 takes L quads (L at most the
+ * shape's trace_quads). */
 typedef struct km_tile_info {
     int32_t waves;            /* wavefronts (64 lanes) per workgroup */
-    int32_t column_groups;    /* groups of 4 image columns per wavefront */
+    int32_t column_groups;    /* groups of 4 image columns per wavefront (migrate) */
     int32_t depth_slots;      /* 16-depth slots held per lane (depth chunk = 16 * depth_slots) */
-    int32_t lds_budget;       /* bytes of LDS the trace block may use */
+    int32_t lds_budget;       /* bytes of LDS the trace block (migrate) or trace rows (demigrate) may use */
+    int32_t trace_quads;      /* demigrate: most groups of 4 traces per workgroup at this level; 0 for migrate */
+    int32_t shape, level;     /* the decoded tile */
 } km_tile_info;
 
 int32_t km_tile_count(int32_t op);
+int32_t km_tile_levels(int32_t op);
 km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out /* host */);
 
-/* Time every tile shape of op on this problem (each run once untimed, then
- * `reps` times), keep the fastest for its shape class
- * (op, dtype, depth-count bucket, sample-count bucket) and return it.
- * Synchronises the stream.  Writes the output buffer (image for op 0,
- * out->data for op 1) with accumulate = 0 semantics.  best_ms: host, may be NULL. */
+/* Autotuner: time every tile (compiled shape x level) of op on this problem
+ * (each run once untimed, then `reps` times), keep the fastest for the
+ * problem's class (GPU architecture, op, dtype, traveltime kind, time
+ * precision, nz / 128, n_samples / 512) and return it; calls with tile = -1
+ * then use it.  table (table traveltimes; tt is then ignored and W = 1) or aa
+ * (anti-alias filter) may be NULL, not both non-NULL.  Synchronises the
+ * stream.  Writes the output buffer (image for op 0, traces->data for op 1)
+ * with accumulate = 0 semantics.  best_tile, best_ms: host, may be NULL.
+ * The class cache is kept per process and, when the environment variable
+ * KM_TUNE_CACHE names a file, read from it at first use and rewritten (JSON)
+ * after every record, so a later process starts tuned. */
 km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
-                  const km_weight* weight, float* image, int32_t reps, void* stream,
-                  int32_t* best_tile /* host */, float* best_ms /* host */);
+                  const km_weight* weight, const km_ttable* table, const km_antialias* aa, float* image,
+                  int32_t reps, void* stream, int32_t* best_tile /* host */, float* best_ms /* host */);
 
-/* Shape-class cache of km_tune (so callers can persist it).  km_tune_lookup
- * returns -1 when no shape is recorded. */
-int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples);
-km_status km_tune_record(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples, int32_t tile);
+/* The class cache of km_tune.  kind: 0 = square-root times, 1 = table times,
+ * 2 = anti-alias filter.  km_tune_lookup returns -1 when nothing is recorded;
+ * km_tune_record stores (and persists) a tile with its time. */
+int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
+                       int32_t n_samples);
+km_status km_tune_record(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
+                         int32_t n_samples, int32_t tile, float ms);
 
 /* ---- batched migration ------------------------------------------------------
  * Many independent problems (e.g. uneven 2D lines) migrated by ONE persistent

@@ -49,7 +49,8 @@ class KmWeight(ctypes.Structure):
 
 
 class KmTileInfo(ctypes.Structure):
-    _fields_ = [("waves", _i32), ("column_groups", _i32), ("depth_slots", _i32), ("lds_budget", _i32)]
+    _fields_ = [("waves", _i32), ("column_groups", _i32), ("depth_slots", _i32), ("lds_budget", _i32),
+                ("trace_quads", _i32), ("shape", _i32), ("level", _i32)]
 
 
 class KmProblem(ctypes.Structure):
@@ -88,11 +89,12 @@ SIGNATURES = {
     "km_stack_offsets": (ctypes.c_int, [_vp, _i32, _i64, _vp, _vp]),
     "km_cig_moveout": (ctypes.c_int, [_vp, _P(KmGrid), _vp, _i32, _i32, _i32, _vp, _vp, _vp, _vp, _vp]),
     "km_tile_count": (_i32, [_i32]),
+    "km_tile_levels": (_i32, [_i32]),
     "km_tile_describe": (ctypes.c_int, [_i32, _i32, _P(KmTileInfo)]),
-    "km_tune": (ctypes.c_int, [_i32, _P(KmTraces), _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _vp, _i32, _vp,
-                               _P(_i32), _P(ctypes.c_float)]),
-    "km_tune_lookup": (_i32, [_i32, _i32, _i32, _i32]),
-    "km_tune_record": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32]),
+    "km_tune": (ctypes.c_int, [_i32, _P(KmTraces), _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmTtable),
+                               _P(KmAntialias), _vp, _i32, _vp, _P(_i32), _P(ctypes.c_float)]),
+    "km_tune_lookup": (_i32, [_i32, _i32, _i32, _i32, _i32, _i32]),
+    "km_tune_record": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_float]),
     "km_batch_create": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _i32, _vp, _P(_vp)]),
     "km_batch_run": (ctypes.c_int, [_vp, _vp]),
     "km_batch_migrate_static": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _vp]),

@@ -163,10 +163,33 @@ bool migrate_block_params(km::Params& P, int budget, int ks) {
     return false;
 }
 
-km_status shape_params(int op, int shape, km::Params& P) {
+int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
+
+// A tile is a compiled shape and a runtime variant of it, encoded as
+// shape + kTileLevelStride * level.  Migrate levels scale the LDS budget of the
+// trace block (traces per block): 1, 0.5, 1.5, 2 times the shape's.  Demigrate
+// level 0 takes as many trace quads per workgroup as the shape's budget and
+// template allow; level L >= 1 takes L quads (L <= the shape's quads).
+constexpr int kTileLevelStride = 64;
+constexpr int kTileLevels = 4;
+constexpr double kMigrateBudgetScale[kTileLevels] = {1.0, 0.5, 1.5, 2.0};
+
+bool decode_tile(int op, int tile, int* shape, int* level) {
+    if (tile < 0) return false;
+    *shape = tile % kTileLevelStride;
+    *level = tile / kTileLevelStride;
+    if (*shape >= shape_count(op) || *level >= kTileLevels) return false;
+    if (op == 1 && *level > 0 && *level > km::demigrate_shape(*shape).max_quads) return false;
+    return true;
+}
+
+km_status shape_params(int op, int tile, km::Params& P) {
+    int shape = 0, level = 0;
+    if (!decode_tile(op, tile, &shape, &level)) return fail(KM_E_INVALID, "tile %d is not a tile of op %d", tile, op);
     const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
     if (op == 0) {
-        if (!migrate_block_params(P, S.lds_budget, S.depth_slots)) P.tb = 0;
+        const int budget = static_cast<int>(std::min<double>(kMaxLds, S.lds_budget * kMigrateBudgetScale[level]));
+        if (!migrate_block_params(P, budget, S.depth_slots)) P.tb = 0;
     } else {
         // float64 rows; the four groups of a wavefront take four traces, so
         // whole quads of traces keep every group busy
@@ -174,6 +197,7 @@ km_status shape_params(int op, int shape, km::Params& P) {
         const int extra = P.aa_max > 0 ? 4 * 8 * (P.lt - (P.nt + km::kLead + kTailPad + 3) / 4 * 4) : 0;
         P.tb = traces_per_block(P.lt, S.lds_budget + extra, 0, 8);
         if (S.max_quads > 0) P.tb = std::min(P.tb, 4 * S.max_quads);
+        if (level > 0) P.tb = std::min(P.tb, 4 * level);
         if (P.tb >= 4) P.tb &= ~3;
     }
     if (P.tb < 1) return fail(KM_E_UNSUPPORTED, "record of %d samples does not fit in LDS", P.nt);
@@ -187,14 +211,129 @@ km_status shape_params(int op, int shape, km::Params& P) {
 }
 
 // ---- tuning cache ----------------------------------------------------------
-std::mutex g_tune_mu;
-std::map<std::tuple<int, int, int, int>, int> g_tune;
+// Keyed by (GPU architecture, op, dtype, traveltime kind, time precision,
+// depth bucket nz / 128, sample bucket n_samples / 512); persisted as JSON to
+// the file named by the KM_TUNE_CACHE environment variable (read on first
+// use, rewritten after every record).
+struct TuneKey {
+    std::string arch;
+    int op, dtype, kind, prec, nzb, ntb;
+    bool operator<(const TuneKey& o) const {
+        return std::tie(arch, op, dtype, kind, prec, nzb, ntb) <
+               std::tie(o.arch, o.op, o.dtype, o.kind, o.prec, o.nzb, o.ntb);
+    }
+};
 
-std::tuple<int, int, int, int> tune_key(int op, int dtype, int nz, int nt) {
-    return std::make_tuple(op, dtype, (nz + 127) / 128, (nt + 511) / 512);
+struct TuneEntry {
+    int tile;
+    float ms;
+};
+
+std::mutex g_tune_mu;
+std::map<TuneKey, TuneEntry> g_tune;
+bool g_tune_loaded = false;
+
+// Architecture of the current device ("gfx950"), or "unknown" without one.
+std::string device_arch() {
+    int dev = 0;
+    hipDeviceProp_t prop;
+    if (hipGetDevice(&dev) != hipSuccess || hipGetDeviceProperties(&prop, dev) != hipSuccess) {
+        (void)hipGetLastError();
+        return "unknown";
+    }
+    std::string a = prop.gcnArchName;
+    const size_t c = a.find(':');
+    return c == std::string::npos ? a : a.substr(0, c);
 }
 
-int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demigrate_shape_count(); }
+TuneKey tune_key(int op, int dtype, int kind, int prec, int nz, int nt) {
+    return TuneKey{device_arch(), op, dtype, kind, prec, (nz + 127) / 128, (nt + 511) / 512};
+}
+
+const char* tune_cache_path() {
+    const char* p = std::getenv("KM_TUNE_CACHE");
+    return (p && *p) ? p : nullptr;
+}
+
+// The value of "name": in one JSON object's text (our own flat format).
+bool json_field(const std::string& obj, const char* name, std::string* out) {
+    const std::string k = std::string("\"") + name + "\"";
+    size_t i = obj.find(k);
+    if (i == std::string::npos) return false;
+    i = obj.find(':', i + k.size());
+    if (i == std::string::npos) return false;
+    ++i;
+    while (i < obj.size() && (obj[i] == ' ' || obj[i] == '\t' || obj[i] == '\n')) ++i;
+    if (i < obj.size() && obj[i] == '"') {
+        const size_t j = obj.find('"', i + 1);
+        if (j == std::string::npos) return false;
+        *out = obj.substr(i + 1, j - i - 1);
+        return true;
+    }
+    size_t j = i;
+    while (j < obj.size() && obj[j] != ',' && obj[j] != '}' && obj[j] != '\n') ++j;
+    *out = obj.substr(i, j - i);
+    return !out->empty();
+}
+
+void tune_load_locked() {
+    if (g_tune_loaded) return;
+    g_tune_loaded = true;
+    const char* path = tune_cache_path();
+    if (!path) return;
+    FILE* f = std::fopen(path, "rb");
+    if (!f) return;
+    std::string text;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof(buf), f)) > 0) text.append(buf, n);
+    std::fclose(f);
+    size_t pos = text.find("\"entries\"");
+    while (pos != std::string::npos) {
+        const size_t a = text.find('{', pos);
+        if (a == std::string::npos) break;
+        const size_t b = text.find('}', a);
+        if (b == std::string::npos) break;
+        const std::string obj = text.substr(a, b - a + 1);
+        pos = b + 1;
+        std::string v[9];
+        const char* names[9] = {"arch", "op", "dtype", "kind", "precision", "nz_bucket", "nt_bucket", "tile", "ms"};
+        bool ok = true;
+        for (int k = 0; k < 9 && ok; ++k) ok = json_field(obj, names[k], &v[k]);
+        if (!ok) continue;
+        TuneKey key{v[0], std::atoi(v[1].c_str()), std::atoi(v[2].c_str()), std::atoi(v[3].c_str()),
+                    std::atoi(v[4].c_str()), std::atoi(v[5].c_str()), std::atoi(v[6].c_str())};
+        int shape = 0, level = 0;
+        const int tile = std::atoi(v[7].c_str());
+        if ((key.op == 0 || key.op == 1) && decode_tile(key.op, tile, &shape, &level))
+            g_tune[key] = TuneEntry{tile, static_cast<float>(std::atof(v[8].c_str()))};
+    }
+}
+
+void tune_save_locked() {
+    const char* path = tune_cache_path();
+    if (!path) return;
+    const std::string tmp = std::string(path) + ".tmp";
+    FILE* f = std::fopen(tmp.c_str(), "wb");
+    if (!f) return;
+    std::fprintf(f, "{\n  \"format\": \"km_tune_cache\",\n  \"version\": 1,\n  \"entries\": [");
+    bool first = true;
+    for (const auto& kv : g_tune) {
+        const TuneKey& k = kv.first;
+        std::fprintf(f,
+                     "%s\n    {\"arch\": \"%s\", \"op\": %d, \"dtype\": %d, \"kind\": %d, \"precision\": %d, "
+                     "\"nz_bucket\": %d, \"nt_bucket\": %d, \"tile\": %d, \"ms\": %.4f}",
+                     first ? "" : ",", k.arch.c_str(), k.op, k.dtype, k.kind, k.prec, k.nzb, k.ntb, kv.second.tile,
+                     static_cast<double>(kv.second.ms));
+        first = false;
+    }
+    std::fprintf(f, "\n  ]\n}\n");
+    const bool ok = std::fclose(f) == 0;
+    if (ok) std::rename(tmp.c_str(), path);
+}
+
+// Traveltime kinds of the cache key.
+enum { KIND_DSR = 0, KIND_TABLE = 1, KIND_AA = 2 };
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
 // 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 4 slots x 1
@@ -202,36 +341,38 @@ int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demig
 // table gathers favour more traces per workgroup).  With the anti-alias
 // filter: migrate 16 waves x 4 column groups x 8 slots (the largest trace
 // blocks), demigrate 8 waves x 4 slots x 1 quad.
-int default_shape(int op, int nz, bool table, bool aa = false) {
-    (void)nz;
-    if (op == 0) return aa ? 1 : 2;
-    if (aa) return 3;
-    return table ? 1 : 3;
+int default_tile(int op, int kind) {
+    if (op == 0) return kind == KIND_AA ? 1 : 2;
+    if (kind == KIND_AA) return 3;
+    return kind == KIND_TABLE ? 1 : 3;
 }
 
-// The tuning cache is keyed without the traveltime kind or the anti-alias
-// filter, so table and anti-aliased calls use the untuned choice unless a
-// tile is given.
-km_status pick_shape(int op, int tile, int dtype, int nz, int nt, bool table, int* shape, bool aa = false) {
+// The caller's tile, else the tuned tile of this problem's class, else the default.
+km_status pick_tile(int op, int tile, int dtype, int kind, int prec, int nz, int nt, int* out) {
     if (tile >= 0) {
-        if (tile >= shape_count(op)) return fail(KM_E_INVALID, "tile %d out of range [0, %d)", tile, shape_count(op));
-        *shape = tile;
+        int shape = 0, level = 0;
+        if (!decode_tile(op, tile, &shape, &level))
+            return fail(KM_E_INVALID, "tile %d out of range (shape < %d, level < %d)", tile, shape_count(op),
+                        kTileLevels);
+        *out = tile;
         return KM_OK;
     }
-    if (!table && !aa) {
+    {
+        const TuneKey key = tune_key(op, dtype, kind, prec, nz, nt);
         std::lock_guard<std::mutex> lk(g_tune_mu);
-        auto it = g_tune.find(tune_key(op, dtype, nz, nt));
+        tune_load_locked();
+        auto it = g_tune.find(key);
         if (it != g_tune.end()) {
-            *shape = it->second;
+            *out = it->second.tile;
             return KM_OK;
         }
     }
-    *shape = default_shape(op, nz, table, aa);
+    *out = default_tile(op, kind);
     return KM_OK;
 }
 
 km_status run_op(int op, const km_traces* t, const km_grid* g, const km_traveltime* tt, const km_weight* w,
-                 float* image, int accumulate, int shape, hipStream_t s, const km_ttable* tab = nullptr,
+                 float* image, int accumulate, int tile, hipStream_t s, const km_ttable* tab = nullptr,
                  const km_antialias* aa = nullptr) {
     km::Params P = base_params(t, g, tt, w, image, accumulate);
     if (aa) {
@@ -253,8 +394,9 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         P.r2 = tab->r2;
         P.weight = KM_W_UNIT;
     }
-    km_status st = shape_params(op, shape, P);
+    km_status st = shape_params(op, tile, P);
     if (st != KM_OK) return st;
+    const int shape = tile % kTileLevelStride;
     if (op == 1 && (P.n_traces + P.tb - 1) / P.tb > INT32_MAX)
         return fail(KM_E_UNSUPPORTED, "kirchhoff_demigrate: too many trace blocks");
     if (op == 0 && P.n_traces > INT32_MAX)  // block slots record trace indices within a bin as int32
@@ -281,7 +423,8 @@ km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_tr
     if (grid_empty(grid)) return KM_OK;
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_migrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_shape(0, tile, traces->dtype, grid->nz, traces->n_samples, tab != nullptr, &shape, aa != nullptr);
+    st = pick_tile(0, tile, traces->dtype, tab ? KIND_TABLE : aa ? KIND_AA : KIND_DSR, tt->time_precision, grid->nz,
+                   traces->n_samples, &shape);
     if (st != KM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (traces->n_traces == 0 && !accumulate)
@@ -308,7 +451,8 @@ km_status demigrate_impl(const float* image, const km_grid* grid, const km_trave
     }
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_demigrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_shape(1, tile, out->dtype, grid->nz, out->n_samples, tab != nullptr, &shape, aa != nullptr);
+    st = pick_tile(1, tile, out->dtype, tab ? KIND_TABLE : aa ? KIND_AA : KIND_DSR, tt->time_precision, grid->nz,
+                   out->n_samples, &shape);
     if (st != KM_OK) return st;
     return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab, aa);
 }
@@ -506,44 +650,80 @@ km_status km_cig_moveout(const float* image, const km_grid* grid, const float* o
 
 int32_t km_tile_count(int32_t op) { return (op == 0 || op == 1) ? shape_count(op) : 0; }
 
+int32_t km_tile_levels(int32_t op) {
+    if (op == 0) return kTileLevels;
+    if (op == 1) return kTileLevels;
+    return 0;
+}
+
 km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out) {
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tile_describe: op must be 0 or 1");
-    if (tile < 0 || tile >= shape_count(op)) return fail(KM_E_INVALID, "km_tile_describe: tile out of range");
+    int shape = 0, level = 0;
+    if (!decode_tile(op, tile, &shape, &level)) return fail(KM_E_INVALID, "km_tile_describe: tile out of range");
     if (!out) return fail(KM_E_INVALID, "km_tile_describe: out is NULL");
-    const km::TileShape& S = op == 0 ? km::migrate_shape(tile) : km::demigrate_shape(tile);
+    const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
     out->waves = S.waves;
     out->column_groups = S.column_groups;
     out->depth_slots = S.depth_slots;
-    out->lds_budget = S.lds_budget;
+    out->lds_budget = op == 0 ? static_cast<int>(std::min<double>(kMaxLds, S.lds_budget * kMigrateBudgetScale[level]))
+                              : S.lds_budget;
+    out->trace_quads = op == 0 ? 0 : (level > 0 ? level : S.max_quads);
+    out->shape = shape;
+    out->level = level;
     return KM_OK;
 }
 
-int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples) {
+int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
+                       int32_t n_samples) {
+    const TuneKey key = tune_key(op, dtype, kind, time_precision, nz, n_samples);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    auto it = g_tune.find(tune_key(op, dtype, nz, n_samples));
-    return it == g_tune.end() ? -1 : it->second;
+    tune_load_locked();
+    auto it = g_tune.find(key);
+    return it == g_tune.end() ? -1 : it->second.tile;
 }
 
-km_status km_tune_record(int32_t op, int32_t dtype, int32_t nz, int32_t n_samples, int32_t tile) {
+km_status km_tune_record(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
+                         int32_t n_samples, int32_t tile, float ms) {
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tune_record: op must be 0 or 1");
-    if (tile < 0 || tile >= shape_count(op)) return fail(KM_E_INVALID, "km_tune_record: tile out of range");
+    if (kind < KIND_DSR || kind > KIND_AA) return fail(KM_E_INVALID, "km_tune_record: unknown kind %d", kind);
+    int shape = 0, level = 0;
+    if (!decode_tile(op, tile, &shape, &level)) return fail(KM_E_INVALID, "km_tune_record: tile out of range");
+    const TuneKey key = tune_key(op, dtype, kind, time_precision, nz, n_samples);
     std::lock_guard<std::mutex> lk(g_tune_mu);
-    g_tune[tune_key(op, dtype, nz, n_samples)] = tile;
+    tune_load_locked();
+    g_tune[key] = TuneEntry{tile, ms};
+    tune_save_locked();
     return KM_OK;
 }
 
 km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
-                  const km_weight* weight, float* image, int32_t reps, void* stream, int32_t* best_tile,
-                  float* best_ms) {
+                  const km_weight* weight, const km_ttable* table, const km_antialias* aa, float* image,
+                  int32_t reps, void* stream, int32_t* best_tile, float* best_ms) {
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tune: op must be 0 or 1");
     if (reps < 1) return fail(KM_E_INVALID, "km_tune: reps < 1");
+    if (table && aa) return fail(KM_E_INVALID, "km_tune: table traveltimes and the anti-alias filter exclude each other");
     km_status st = check_traces(traces, true, "km_tune");
     if (st != KM_OK) return st;
+    km_traveltime ttab_tt{};
+    km_weight unit{KM_W_UNIT};
+    if (table) {
+        st = check_table(table, grid, "km_tune");
+        if (st != KM_OK) return st;
+        ttab_tt = km_traveltime{table->r2, table->r2, table->r2, table->time_precision};
+        tt = &ttab_tt;
+        weight = &unit;
+    }
+    if (aa) {
+        st = check_antialias(aa, "km_tune");
+        if (st == KM_OK) st = check_antialias_tt(tt, "km_tune");
+        if (st != KM_OK) return st;
+    }
     st = check_grid(grid, tt, weight, "km_tune");
     if (st != KM_OK) return st;
     if (op == 1 && traces->dtype != KM_F32) return fail(KM_E_UNSUPPORTED, "km_tune: demigrate output must be KM_F32");
     if (grid_empty(grid) || traces->n_traces == 0) return fail(KM_E_INVALID, "km_tune: empty problem");
     if (!image) return fail(KM_E_INVALID, "km_tune: image is NULL");
+    const int kind = table ? KIND_TABLE : aa ? KIND_AA : KIND_DSR;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     hipError_t he = hipEventCreate(&e0);
@@ -556,32 +736,46 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
     int best = -1;
     float best_t = 0.0f;
     st = KM_OK;
+    // every compiled shape at every variant level that applies to it
     for (int sh = 0; sh < shape_count(op) && st == KM_OK; ++sh) {
-        km::Params P = base_params(traces, grid, tt, weight, image, 0);
-        if (shape_params(op, sh, P) != KM_OK) continue;
-        st = run_op(op, traces, grid, tt, weight, image, 0, sh, s);
-        if (st != KM_OK) break;
-        hipEventRecord(e0, s);
-        for (int r = 0; r < reps && st == KM_OK; ++r) st = run_op(op, traces, grid, tt, weight, image, 0, sh, s);
-        hipEventRecord(e1, s);
-        he = hipEventSynchronize(e1);
-        if (he != hipSuccess) {
-            st = hip_fail(he, "km_tune synchronise");
-            break;
-        }
-        float ms = 0.0f;
-        hipEventElapsedTime(&ms, e0, e1);
-        ms /= reps;
-        if (best < 0 || ms < best_t) {
-            best = sh;
-            best_t = ms;
+        for (int lv = 0; lv < kTileLevels && st == KM_OK; ++lv) {
+            int d_shape = 0, d_level = 0;
+            const int tile = sh + kTileLevelStride * lv;
+            if (!decode_tile(op, tile, &d_shape, &d_level)) continue;
+            km::Params P = base_params(traces, grid, tt, weight, image, 0);
+            if (aa) {
+                P.aa_max = aa->max_half;
+                P.lt = (traces->n_samples + 2 * (2 * aa->max_half + 5) + 3) / 4 * 4;
+            }
+            if (table) P.ttab = table->t;
+            if (shape_params(op, tile, P) != KM_OK) continue;
+            if (op == 1 && lv > 0 && P.tb < 4 * lv) continue;  // the level's quads do not fit: same as a lower one
+            st = run_op(op, traces, grid, tt, weight, image, 0, tile, s, table, aa);
+            if (st != KM_OK) break;
+            hipEventRecord(e0, s);
+            for (int r = 0; r < reps && st == KM_OK; ++r)
+                st = run_op(op, traces, grid, tt, weight, image, 0, tile, s, table, aa);
+            hipEventRecord(e1, s);
+            he = hipEventSynchronize(e1);
+            if (he != hipSuccess) {
+                st = hip_fail(he, "km_tune synchronise");
+                break;
+            }
+            float ms = 0.0f;
+            hipEventElapsedTime(&ms, e0, e1);
+            ms /= reps;
+            if (best < 0 || ms < best_t) {
+                best = tile;
+                best_t = ms;
+            }
         }
     }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (st != KM_OK) return st;
-    if (best < 0) return fail(KM_E_UNSUPPORTED, "km_tune: no tile shape fits this problem");
-    km_tune_record(op, traces->dtype, grid->nz, traces->n_samples, best);
+    if (best < 0) return fail(KM_E_UNSUPPORTED, "km_tune: no tile fits this problem");
+    st = km_tune_record(op, traces->dtype, kind, tt->time_precision, grid->nz, traces->n_samples, best, best_t);
+    if (st != KM_OK) return st;
     if (best_tile) *best_tile = best;
     if (best_ms) *best_ms = best_t;
     return KM_OK;
@@ -596,7 +790,7 @@ namespace {
 // A batched migration: the shape and kernel flags every problem shares, the
 // problems' launch parameters and their work items, longest first.
 struct BatchPlan {
-    int shape = 0, has_tf = 0, weight = 0, prec = 0;
+    int tile = 0, shape = 0, has_tf = 0, weight = 0, prec = 0;
     std::vector<km::Params> P;
     std::vector<int4> items;  // (problem, bin, column tile or -1 - tile when empty, depth chunk)
     size_t lds = 0;
@@ -625,8 +819,10 @@ km_status batch_plan(const km_problem* probs, int32_t n, int32_t tile, const cha
         max_nz = std::max(max_nz, probs[i].grid.nz);
         max_nt = std::max(max_nt, probs[i].traces.n_samples);
     }
-    km_status st = pick_shape(0, tile, probs[0].traces.dtype, max_nz, max_nt, false, &B.shape);
+    km_status st = pick_tile(0, tile, probs[0].traces.dtype, KIND_DSR, probs[0].tt.time_precision, max_nz, max_nt,
+                             &B.tile);
     if (st != KM_OK) return st;
+    B.shape = B.tile % kTileLevelStride;
     const km::TileShape& S = km::migrate_shape(B.shape);
     B.has_tf = probs[0].traces.t_first != 0.0 ? 1 : 0;
     B.weight = probs[0].weight.kind;
@@ -635,7 +831,7 @@ km_status batch_plan(const km_problem* probs, int32_t n, int32_t tile, const cha
     for (int i = 0; i < n; ++i) {
         km::Params& P = B.P[i];
         P = base_params(&probs[i].traces, &probs[i].grid, &probs[i].tt, &probs[i].weight, probs[i].image, 0);
-        st = shape_params(0, B.shape, P);
+        st = shape_params(0, B.tile, P);
         if (st != KM_OK) return st;
         if (P.n_traces > INT32_MAX)
             return fail(KM_E_UNSUPPORTED, "%s: problem %d has more than 2^31 - 1 traces", who, i);

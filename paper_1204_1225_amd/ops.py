@@ -343,19 +343,47 @@ def tile_describe(op: int, tile: int) -> dict:
     return {f: int(getattr(info, f)) for f, _ in KmTileInfo._fields_}
 
 
+def tile_levels(op: int) -> int:
+    return int(_lib.load().km_tile_levels(op))
+
+
+def tiles(op: int):
+    """Every valid tile of op: compiled shape + 64 * level."""
+    out = []
+    for lv in range(tile_levels(op)):
+        for sh in range(tile_count(op)):
+            t = sh + 64 * lv
+            if _lib.load().km_tile_describe(op, t, ctypes.byref(KmTileInfo())) == _lib.KM_OK:
+                out.append(t)
+    return out
+
+
+KIND_DSR, KIND_TABLE, KIND_AA = 0, 1, 2
+
+
+def problem_kind(dp: DeviceProblem) -> int:
+    return KIND_TABLE if dp.ttab is not None else KIND_AA if dp.aa is not None else KIND_DSR
+
+
 def tune(op: int, dp: DeviceProblem, image: torch.Tensor, traces_out: Optional[torch.Tensor] = None,
          reps: int = 2):
-    """Time every tile shape of op (0 migrate, 1 demigrate) on dp and record the
-    fastest for its shape class; returns (tile, ms).  For op 0 `image` is
-    overwritten with the migration; for op 1 `image` is the input and
-    `traces_out` (float32 [n_traces, n_t]) is overwritten."""
-    _plain_only(dp, "tune")
+    """Time every tile of op (0 migrate, 1 demigrate) on dp (any traveltime
+    kind) and record the fastest for its class; returns (tile, ms).  For op 0
+    `image` is overwritten with the migration; for op 1 `image` is the input
+    and `traces_out` (float32 [n_traces, n_t]) is overwritten."""
     best, ms = ctypes.c_int32(-1), ctypes.c_float(0.0)
     tr = dp.c_traces() if op == 0 else dp.c_traces(traces_out, "f32")
+    tab = ctypes.byref(dp.c_table()) if dp.ttab is not None else None
+    aa = ctypes.byref(dp.c_aa()) if dp.aa is not None else None
     check(_lib.load().km_tune(op, ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),
-                              ctypes.byref(dp.c_weight()), _ptr(image), int(reps),
+                              ctypes.byref(dp.c_weight()), tab, aa, _ptr(image), int(reps),
                               ctypes.c_void_p(_stream(dp.device)), ctypes.byref(best), ctypes.byref(ms)))
     return int(best.value), float(ms.value)
+
+
+def tune_lookup(op: int, dp: DeviceProblem) -> int:
+    """The tile recorded for dp's class (-1 if none)."""
+    return int(_lib.load().km_tune_lookup(op, _DTYPES[dp.dtype], problem_kind(dp), dp.c_prec, dp.nz, dp.n_t))
 
 
 def probe_issue(kind: int, n_waves: int = 8192, iters: int = 4096) -> float:

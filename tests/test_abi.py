@@ -138,11 +138,65 @@ def test_reductions_reject_bad_arguments(lib):
 def test_tune_cache_roundtrip(lib):
     from paper_1204_1225_amd import _lib
 
-    assert lib.km_tune_lookup(0, 0, 4000, 7000) == -1
-    assert lib.km_tune_record(0, 0, 4000, 7000, 1) == _lib.KM_OK
-    assert lib.km_tune_lookup(0, 0, 4000, 7000) == 1
-    assert lib.km_tune_lookup(0, 0, 4010, 7100) == 1  # same shape class
-    assert lib.km_tune_record(0, 0, 4000, 7000, 99) == _lib.KM_E_INVALID
+    # class key: (arch, op, dtype, kind, precision, nz / 128, n_samples / 512)
+    assert lib.km_tune_lookup(0, 0, 0, 0, 4000, 7000) == -1
+    assert lib.km_tune_record(0, 0, 0, 0, 4000, 7000, 1, 3.5) == _lib.KM_OK
+    assert lib.km_tune_lookup(0, 0, 0, 0, 4000, 7000) == 1
+    assert lib.km_tune_lookup(0, 0, 0, 0, 4010, 7100) == 1  # same class
+    assert lib.km_tune_lookup(0, 0, 1, 0, 4000, 7000) == -1  # table times: another class
+    assert lib.km_tune_lookup(0, 0, 0, 1, 4000, 7000) == -1  # extended time: another class
+    assert lib.km_tune_record(0, 0, 0, 0, 4000, 7000, 99, 1.0) == _lib.KM_E_INVALID
+    assert lib.km_tune_record(0, 0, 7, 0, 4000, 7000, 1, 1.0) == _lib.KM_E_INVALID
+    assert lib.km_tune_record(1, 0, 0, 0, 4000, 7000, 1 + 64 * 3, 1.0) == _lib.KM_OK  # 16 waves x 8 slots x 3 quads
+
+
+def test_tiles_encode_shape_and_level(lib):
+    from paper_1204_1225_amd import _lib
+
+    info = _lib.KmTileInfo()
+    for op in (0, 1):
+        assert lib.km_tile_levels(op) == 4
+        for sh in range(lib.km_tile_count(op)):
+            assert lib.km_tile_describe(op, sh, ctypes.byref(info)) == _lib.KM_OK
+            assert (info.shape, info.level) == (sh, 0)
+    # migrate levels scale the trace block's budget (at most 160 KiB)
+    assert lib.km_tile_describe(0, 2, ctypes.byref(info)) == _lib.KM_OK
+    base = info.lds_budget
+    assert lib.km_tile_describe(0, 2 + 64, ctypes.byref(info)) == _lib.KM_OK and info.lds_budget == base // 2
+    assert lib.km_tile_describe(0, 2 + 192, ctypes.byref(info)) == _lib.KM_OK and info.lds_budget == 2 * base
+    assert lib.km_tile_describe(0, 2 + 256, ctypes.byref(info)) == _lib.KM_E_INVALID
+    # demigrate levels pick the trace quads per workgroup, up to the shape's
+    assert lib.km_tile_describe(1, 3 + 64, ctypes.byref(info)) == _lib.KM_OK and info.trace_quads == 1
+    assert lib.km_tile_describe(1, 3 + 128, ctypes.byref(info)) == _lib.KM_E_INVALID  # one-quad shape
+
+
+def test_tune_cache_persists_across_processes(tmp_path):
+    # KM_TUNE_CACHE: a record written by one process is read by the next
+    # (host calls only: no GPU; the class key then carries arch "unknown").
+    import json
+    import os
+    import subprocess
+    import sys
+
+    path = tmp_path / "tune.json"
+    code = ("import sys; sys.path.insert(0, {root!r})\n"
+            "from paper_1204_1225_amd import _lib\n"
+            "lib = _lib.load()\n"
+            "{body}\n")
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    env = dict(os.environ, KM_TUNE_CACHE=str(path), HIP_VISIBLE_DEVICES="")
+    write = "assert lib.km_tune_record(1, 0, 2, 0, 900, 3000, 3, 12.5) == 0\n" \
+            "assert lib.km_tune_record(0, 1, 0, 1, 300, 1500, 2 + 64, 7.25) == 0"
+    subprocess.run([sys.executable, "-c", code.format(root=root, body=write)], env=env, check=True)
+    doc = json.loads(path.read_text())
+    assert doc["format"] == "km_tune_cache" and len(doc["entries"]) == 2
+    e = {(x["op"], x["kind"]): x for x in doc["entries"]}
+    assert e[(1, 2)]["tile"] == 3 and e[(1, 2)]["nz_bucket"] == 8 and e[(1, 2)]["nt_bucket"] == 6
+    assert e[(0, 0)]["tile"] == 66 and e[(0, 0)]["precision"] == 1 and e[(0, 0)]["dtype"] == 1
+    read = "assert lib.km_tune_lookup(1, 0, 2, 0, 900, 3000) == 3\n" \
+           "assert lib.km_tune_lookup(0, 1, 0, 1, 300, 1500) == 66\n" \
+           "assert lib.km_tune_lookup(0, 0, 0, 1, 300, 1500) == -1"
+    subprocess.run([sys.executable, "-c", code.format(root=root, body=read)], env=env, check=True)
 
 
 def test_stack_and_moveout_reject_bad_arguments(lib):
@@ -243,7 +297,7 @@ def test_antialias_entry_points_reject_bad_options(lib):
 
 
 def test_plain_only_calls_reject_table_and_antialias_problems():
-    # count (with n_effective), tune and Batch evaluate the plain square-root
+    # count (with n_effective) and Batch evaluate the plain square-root
     # operator; a table-traveltime or anti-aliased problem must raise instead
     # of silently running it (checked before any library call: no GPU needed).
     import dataclasses
@@ -260,11 +314,9 @@ def test_plain_only_calls_reject_table_and_antialias_problems():
                dataclasses.replace(base, aa=(12.5, 12.5, 4))]:
         with pytest.raises(_lib.KirchhoffError) as e1:
             ops.count(dp)
-        with pytest.raises(_lib.KirchhoffError) as e2:
-            ops.tune(0, dp, torch.zeros(dp.image_shape))
         with pytest.raises(_lib.KirchhoffError) as e3:
             ops.Batch([dp], [torch.zeros(dp.image_shape)])
-        assert e1.value.status == e2.value.status == e3.value.status == _lib.KM_E_UNSUPPORTED
+        assert e1.value.status == e3.value.status == _lib.KM_E_UNSUPPORTED
 
 
 def test_batch_static_rejects_what_does_not_fit(lib):
