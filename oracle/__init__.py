@@ -29,7 +29,8 @@ import numpy as np
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
 _SRC = os.path.join(_HERE, "kirchhoff_oracle.c")
-_LIB = os.path.join(_HERE, "liboracle.so")
+# KM_ORACLE_LIBRARY names another build of the oracle (its sanitizer build)
+_LIB = os.environ.get("KM_ORACLE_LIBRARY") or os.path.join(_HERE, "liboracle.so")
 _lib = None
 
 
@@ -41,6 +42,17 @@ def build(force: bool = True) -> str:
         subprocess.run(cmd, check=True)
         os.replace(_LIB + ".tmp", _LIB)
     return _LIB
+
+
+def build_sanitized(out: str) -> str:
+    """The oracle with AddressSanitizer and UndefinedBehaviorSanitizer checks
+    (clang, the same arithmetic flags); load it into a process that preloads
+    clang's shared AddressSanitizer runtime."""
+    cmd = ["/opt/rocm/llvm/bin/clang", "-O1", "-g", "-std=c11", "-fopenmp", "-ffp-contract=off", "-fno-fast-math",
+           "-fsanitize=address,undefined", "-fno-sanitize-recover=undefined", "-shared-libasan",
+           "-fno-omit-frame-pointer", "-shared", "-fPIC", _SRC, "-o", out, "-lm"]
+    subprocess.run(cmd, check=True)
+    return out
 
 
 class _Problem(ctypes.Structure):

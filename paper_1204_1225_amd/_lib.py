@@ -10,7 +10,9 @@ import ctypes
 import os
 
 HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(HERE, "libkirchhoff.so")
+# KM_LIBRARY names another build of this library (the sanitizer build of its
+# host code, for instance); by default the in-tree one
+LIB_PATH = os.environ.get("KM_LIBRARY") or os.path.join(HERE, "libkirchhoff.so")
 ABI_VERSION = 2
 
 KM_OK, KM_E_INVALID, KM_E_UNSUPPORTED, KM_E_HIP, KM_E_NOMEM = range(5)

@@ -55,6 +55,50 @@ def build(verbose: bool = True) -> str:
     return LIB
 
 
+# Host sources (no device code): the ones the sanitizer build instruments.
+HOST_SOURCES = ["km_api.cpp", "km_count.cpp"]
+SANITIZE_FLAGS = ["-O1", "-g", "-Xarch_host", "-fsanitize=address", "-Xarch_host", "-fsanitize=undefined",
+                  "-Xarch_host", "-fno-sanitize-recover=undefined", "-Xarch_host", "-fno-omit-frame-pointer"]
+
+
+def asan_runtime() -> str:
+    """clang's shared AddressSanitizer runtime (to preload into the process
+    that loads a sanitizer build)."""
+    import glob
+
+    found = sorted(glob.glob("/opt/rocm/llvm/lib/clang/*/lib/linux/libclang_rt.asan-x86_64.so"))
+    if not found:
+        raise RuntimeError("clang's shared AddressSanitizer runtime is not installed")
+    return found[-1]
+
+
+def build_sanitized(out: str) -> str:
+    """A build of the library whose host code (argument validation, tiles,
+    the tuning cache, the host pair counter) carries AddressSanitizer and
+    UndefinedBehaviorSanitizer checks; the device code is the normal one.  The
+    sanitizer runtime is not linked in: load the library into a process that
+    preloads asan_runtime()."""
+    objs = [os.path.join(BUILD, os.path.splitext(f)[0] + ".o") for f in SOURCES if f not in HOST_SOURCES]
+    if not all(os.path.exists(o) for o in objs):
+        build(verbose=False)
+    work = os.path.join(BUILD, "sanitize")
+    os.makedirs(work, exist_ok=True)
+    host_objs = []
+    for src in HOST_SOURCES:
+        obj = os.path.join(work, os.path.splitext(src)[0] + ".o")
+        cmd = [HIPCC, *[f for f in FLAGS if f != "-O3"], *SANITIZE_FLAGS, "-x", "hip", "-c",
+               os.path.join(CSRC, src), "-o", obj]
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        if r.returncode != 0:
+            raise RuntimeError(f"sanitizer build of {src} failed:\n{r.stdout}{r.stderr}")
+        host_objs.append(obj)
+    r = subprocess.run([HIPCC, "--offload-arch=gfx950", "-shared", "-fPIC", *host_objs, *objs, "-o", out],
+                       capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError(f"sanitizer link failed:\n{r.stdout}{r.stderr}")
+    return out
+
+
 if __name__ == "__main__":
     build()
     sys.exit(0)
