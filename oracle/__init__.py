@@ -8,9 +8,12 @@ columns or traces); this module only loads it and passes numpy arrays.
 Every function takes a problem object with the attributes of a survey
 problem (src, rec, bin, n_t, dt, t_first, x, y, t0sq, s2, r2, weight,
 n_bins, and optionally a one-way traveltime table ttab [n_h][nz] with
-spacing tdh, which replaces the t0sq / s2 form, and optionally aa = (dx, dy,
-max half-width) for the anti-alias triangle filter) and, where samples are needed, a float64 data array [n_traces, n_t]
-(default: the problem's own data widened to float64).
+spacing tdh, which replaces the t0sq / s2 form, or with tgrid = (gx0, gy0,
+gdx, gdy) a laterally varying table ttab [n_gy][n_gx][n_h][nz] on the node
+grid (gx0 + i gdx, gy0 + j gdy), and optionally aa = (dx, dy, max
+half-width) for the anti-alias triangle filter) and, where samples are
+needed, a float64 data array [n_traces, n_t] (default: the problem's own data
+widened to float64).
 
 Parity status: all functions are pinned by the CPU tests (closed forms,
 invariants, adjoint identity, focusing); none is unpinned.  The pair counts
@@ -67,6 +70,8 @@ class _Problem(ctypes.Structure):
         ("weight", ctypes.c_int32),
         ("n_h", ctypes.c_int32), ("dh", ctypes.c_double), ("ttab", ctypes.c_void_p),
         ("aa_dx", ctypes.c_double), ("aa_dy", ctypes.c_double), ("aa_max", ctypes.c_int32),
+        ("n_gx", ctypes.c_int32), ("n_gy", ctypes.c_int32), ("gx0", ctypes.c_double), ("gy0", ctypes.c_double),
+        ("gdx", ctypes.c_double), ("gdy", ctypes.c_double),
     ]
 
 
@@ -113,9 +118,16 @@ class _Bound:
             self.keep["data"] = _arr(data, np.float64)
             assert self.keep["data"].shape == (self.keep["src"].shape[0], int(p.n_t))
         ttab = getattr(p, "ttab", None)
+        tgrid = getattr(p, "tgrid", None)
+        n_gx = n_gy = 0
         if ttab is not None:
-            self.keep["ttab"] = _arr(ttab, np.float32)
-            assert self.keep["ttab"].ndim == 2 and self.keep["ttab"].shape[1] == self.keep["t0sq"].shape[0]
+            self.keep["ttab"] = t = _arr(ttab, np.float32)
+            if tgrid is not None:
+                assert t.ndim == 4, "a laterally varying table is [n_gy][n_gx][n_h][nz]"
+                n_gy, n_gx = t.shape[0], t.shape[1]
+            else:
+                assert t.ndim == 2
+            assert t.shape[-1] == self.keep["t0sq"].shape[0]
         k = self.keep
         self.s = _Problem(
             n_traces=k["src"].shape[0], n_t=int(p.n_t), t_first=float(p.t_first), dt=float(p.dt),
@@ -124,8 +136,11 @@ class _Bound:
             nx=k["x"].shape[0], ny=k["y"].shape[0], nz=k["t0sq"].shape[0], n_bins=int(p.n_bins),
             x=k["x"].ctypes.data, y=k["y"].ctypes.data, t0sq=k["t0sq"].ctypes.data, s2=k["s2"].ctypes.data,
             r2=k["r2"].ctypes.data, weight=int(p.weight),
-            n_h=k["ttab"].shape[0] if "ttab" in k else 0, dh=float(getattr(p, "tdh", 0.0) or 0.0),
+            n_h=k["ttab"].shape[-2] if "ttab" in k else 0, dh=float(getattr(p, "tdh", 0.0) or 0.0),
             ttab=k["ttab"].ctypes.data if "ttab" in k else None)
+        if n_gx:
+            self.s.n_gx, self.s.n_gy = n_gx, n_gy
+            self.s.gx0, self.s.gy0, self.s.gdx, self.s.gdy = (float(v) for v in tgrid)
         aa = getattr(p, "aa", None)  # (dx, dy, max half-width) or None
         if aa is not None:
             self.s.aa_dx, self.s.aa_dy, self.s.aa_max = float(aa[0]), float(aa[1]), int(aa[2])

@@ -50,6 +50,16 @@
  *    ttab[ih][iz], the time at h = ih * dh, with h = sqrt(h^2) in FP64 and
  *    h / dh clamped to [0, n_h - 1] (beyond the table the last value holds).
  *    The aperture test is unchanged; W = 1 (weight kind 0 only).
+ *  - Laterally varying tables (ttab != NULL and n_gx >= 1; the medium below
+ *    each node of a coarse lateral grid X_i = gx0 + i gdx, Y_j = gy0 + j gdy
+ *    has its own table ttab[j][i][ih][iz]): the one-way time from a surface
+ *    point to image point (x, y, z[iz]) is the trilinear interpolation over
+ *    (x, y, h), taken as nested linear interpolations a + f (b - a): in h on
+ *    each of the four nodes around the image column (as above), then in x,
+ *    then in y.  The node coordinate (x - gx0) / gdx is clamped to
+ *    [0, n_gx - 1] (beyond the grid the edge nodes hold); a single node along
+ *    an axis takes no interpolation there.  With every node holding the same
+ *    table this is the laterally invariant table exactly (b - a = 0).
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
  */
@@ -84,6 +94,9 @@ typedef struct {
     const float* ttab;     /* [n_h][nz] one-way seconds, or NULL for the t0sq / s2 form */
     double aa_dx, aa_dy;   /* anti-aliasing: image spacings the dip is measured over */
     int32_t aa_max;        /* anti-aliasing: largest triangle half-width (samples); 0 = off */
+    int32_t n_gx, n_gy;    /* lateral table nodes (0: one table for every column) */
+    double gx0, gy0;       /* position of node (0, 0) */
+    double gdx, gdy;       /* node spacing (> 0 along an axis with more than one node) */
 } ko_problem;
 
 /* Linear interpolation in h of the one-way time table at depth iz. */
@@ -97,6 +110,48 @@ static double ko_table_time(const ko_problem* P, double h, int iz)
     const double f = hf - (double)ih;
     const double t0 = P->ttab[ih * (int64_t)P->nz + iz], t1 = P->ttab[(ih + 1) * (int64_t)P->nz + iz];
     return t0 + f * (t1 - t0);
+}
+
+/* Position of coordinate c on a node axis of n nodes (origin c0, spacing g):
+ * lower node *i and fraction *f with c clamped to the axis (see header). */
+static void ko_node_axis(double c, double c0, double g, int32_t n, int64_t* i, double* f)
+{
+    if (n <= 1) {
+        *i = 0;
+        *f = 0.0;
+        return;
+    }
+    double a = (c - c0) / g;
+    if (!(a > 0.0)) a = 0.0;
+    if (a > (double)(n - 1)) a = (double)(n - 1);
+    int64_t k = (int64_t)floor(a);
+    if (k > n - 2) k = n - 2;
+    *i = k;
+    *f = a - (double)k;
+}
+
+/* One-way time at horizontal distance h from the image column (px, py),
+ * depth iz, on the laterally varying tables (see header). */
+static double ko_lateral_time(const ko_problem* P, double px, double py, double h, int iz)
+{
+    int64_t i, j;
+    double fx, fy;
+    ko_node_axis(px, P->gx0, P->gdx, P->n_gx, &i, &fx);
+    ko_node_axis(py, P->gy0, P->gdy, P->n_gy, &j, &fy);
+    const int64_t i1 = P->n_gx > 1 ? i + 1 : i, j1 = P->n_gy > 1 ? j + 1 : j;
+    /* node (a, b) as a table of its own: ko_table_time on a shifted copy */
+    ko_problem Q = *P;
+    const int64_t node = (int64_t)P->n_h * P->nz;
+    Q.ttab = P->ttab + (j * P->n_gx + i) * node;
+    const double t00 = ko_table_time(&Q, h, iz);
+    Q.ttab = P->ttab + (j * P->n_gx + i1) * node;
+    const double t10 = ko_table_time(&Q, h, iz);
+    Q.ttab = P->ttab + (j1 * P->n_gx + i) * node;
+    const double t01 = ko_table_time(&Q, h, iz);
+    Q.ttab = P->ttab + (j1 * P->n_gx + i1) * node;
+    const double t11 = ko_table_time(&Q, h, iz);
+    const double t0 = t00 + fx * (t10 - t00), t1 = t01 + fx * (t11 - t01);
+    return t0 + fy * (t1 - t0);
 }
 
 /* Aperture decision in float32 (see header). */
@@ -120,6 +175,12 @@ static int ko_pair_p(const ko_problem* P, int64_t j, int ix, int iy, int iz, dou
     if (!ko_in_aperture(px, py, sx, sy, rx, ry, P->r2[iz])) return 0;
     double hs2 = ((double)px - sx) * ((double)px - sx) + ((double)py - sy) * ((double)py - sy);
     double hr2 = ((double)px - rx) * ((double)px - rx) + ((double)py - ry) * ((double)py - ry);
+    if (P->ttab && P->n_gx > 0) {
+        const double T = ko_lateral_time(P, px, py, sqrt(hs2), iz) + ko_lateral_time(P, px, py, sqrt(hr2), iz);
+        *u = (T - P->t_first) / P->dt;
+        *w = 1.0;
+        return 1;
+    }
     if (P->ttab) {
         const double T = ko_table_time(P, sqrt(hs2), iz) + ko_table_time(P, sqrt(hr2), iz);
         *u = (T - P->t_first) / P->dt;
@@ -233,6 +294,9 @@ static int ko_check(const ko_problem* P)
     if (!P || P->n_traces < 0 || P->n_t < 0 || P->nx < 0 || P->ny < 0 || P->nz < 0 || P->n_bins < 0) return 1;
     if (!(P->dt > 0.0)) return 1;
     if (P->ttab && (P->n_h < 2 || !(P->dh > 0.0) || P->weight != 0)) return 1;
+    if (P->n_gx < 0 || P->n_gy < 0 || (P->n_gx > 0) != (P->n_gy > 0)) return 1;
+    if (P->n_gx > 0 && (!P->ttab || (P->n_gx > 1 && !(P->gdx > 0.0)) || (P->n_gy > 1 && !(P->gdy > 0.0))))
+        return 1;
     if (P->aa_max < 0 || (P->aa_max > 0 && (P->ttab || !(P->aa_dx >= 0.0) || !(P->aa_dy >= 0.0)))) return 1;
     return 0;
 }

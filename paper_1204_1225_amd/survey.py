@@ -76,6 +76,9 @@ class Problem:
     # optional one-way traveltime table [n_h][nz] (seconds at h = ih * tdh), replacing t0sq / s2
     ttab: Optional[np.ndarray] = None
     tdh: float = 0.0
+    # laterally varying tables: (gx0, gy0, gdx, gdy) of the node grid X_i = gx0 + i gdx,
+    # Y_j = gy0 + j gdy; ttab is then [n_gy][n_gx][n_h][nz], one table per node
+    tgrid: Optional[tuple] = None
     # optional anti-alias triangle filter: (dx, dy, largest half-width in samples)
     aa: Optional[tuple] = None
 
@@ -179,6 +182,33 @@ def with_curved_ray_table(problem: "Problem", dh: float = 10.0, n_h: Optional[in
     return dataclasses.replace(problem, ttab=tab, tdh=float(dh), weight=WEIGHT_UNIT)
 
 
+def lateral_v0(v0: float, gx: float, gy: float, xc: float, yc: float):
+    """Surface velocity of a laterally varying medium v(x, y, z) = v0(x, y) + k z
+    with v0(x, y) = v0 + gx (x - xc) + gy (y - yc) (a plane; FP64)."""
+    return lambda x, y: v0 + gx * (np.asarray(x, np.float64) - xc) + gy * (np.asarray(y, np.float64) - yc)
+
+
+def with_lateral_tables(problem: "Problem", v0_at, k: float, gx0: float, gy0: float, gdx: float, gdy: float,
+                        n_gx: int, n_gy: int, dh: float = 10.0, n_h: Optional[int] = None) -> "Problem":
+    """The problem with laterally varying table traveltimes: below node
+    (X_i, Y_j) = (gx0 + i gdx, gy0 + j gdy) the medium is taken as the depth-only
+    v(z) = v0_at(X_i, Y_j) + k z, and the node's table holds its curved-ray
+    times, ttab[j][i][ih][iz] = curved_ray_time(ih dh, z[iz]; v0_at(X_i, Y_j), k)
+    rounded once to float32 (the local one-dimensional medium under each node).
+    n_h covers every in-aperture leg by default; weight becomes W = 1."""
+    if n_h is None:
+        hmax = float(np.sqrt(np.max(problem.r2.astype(np.float64))))
+        n_h = int(np.ceil(hmax / dh)) + 2
+    X = gx0 + gdx * np.arange(n_gx, dtype=np.float64)
+    Y = gy0 + gdy * np.arange(n_gy, dtype=np.float64)
+    tab = np.empty((n_gy, n_gx, n_h, problem.nz), dtype=np.float32)
+    for j in range(n_gy):
+        for i in range(n_gx):
+            tab[j, i] = curved_ray_table(problem.z, float(v0_at(X[i], Y[j])), k, dh, n_h)
+    return dataclasses.replace(problem, ttab=tab, tdh=float(dh), tgrid=(float(gx0), float(gy0), float(gdx),
+                                                                        float(gdy)), weight=WEIGHT_UNIT)
+
+
 def aperture_table(t0sq: np.ndarray, s2: np.ndarray, aperture_deg: float) -> np.ndarray:
     """r2[iz] = tan^2(theta_max) * t0^2 / s2, rounded once to float32.
 
@@ -238,7 +268,8 @@ def _leg_time_and_cos(velocity, sx, sy, rz, px, py):
 
 
 def model_scatterers(problem: Problem, scat: np.ndarray, f_peak: float = 25.0,
-                     device=None, chunk: int = 4096, half_width_s: float = 0.08, rays: str = "straight"):
+                     device=None, chunk: int = 4096, half_width_s: float = 0.08, rays: str = "straight",
+                     v0_at=None):
     """Trace samples from point scatterers: D_j(t) = sum_k a_kj r(t - tau_kj).
 
     tau_kj = source-leg + receiver-leg time, a_kj the obliquity/spreading
@@ -246,6 +277,9 @@ def model_scatterers(problem: Problem, scat: np.ndarray, f_peak: float = 25.0,
     over all traces.  rays = "straight": straight rays (Euclidean for constant
     v, the RMS model for v(z)); rays = "curved": the exact circular-arc ray
     times of v(z) = v0 + k z with a_kj = 1 / (T_s T_r) normalised the same way.
+    With v0_at (a function of (x, y)), curved rays see below each scatterer the
+    depth-only medium v0_at(x_k, y_k) + k z (a laterally varying medium taken
+    one-dimensional under the image point, as the lateral tables take it).
     Returns float32 [n, n_t] as a torch tensor on `device` (default CPU).
     """
     import torch
@@ -264,6 +298,9 @@ def model_scatterers(problem: Problem, scat: np.ndarray, f_peak: float = 25.0,
 
     vel = problem.velocity
     v0, kg = (float(vel[1]), 0.0) if vel[0] == "const" else (float(vel[1]), float(vel[2]))
+    if v0_at is not None:
+        sc_np = np.asarray(scat, dtype=np.float64)
+        v0 = torch.as_tensor(np.asarray(v0_at(sc_np[:, 0], sc_np[:, 1]), np.float64), device=dev)[None, :]
 
     def curved(sx, sy):
         h2 = (px - sx) ** 2 + (py - sy) ** 2
