@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define KM_ABI_VERSION 2
+#define KM_ABI_VERSION 3
 
 typedef enum km_status {
     KM_OK = 0,
@@ -183,6 +183,45 @@ km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, 
  * of kirchhoff_migrate_table for the same inputs. */
 km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, const km_ttable* table,
                                     const km_traces* out, int32_t accumulate, int32_t tile, void* stream);
+
+/* ---- laterally varying table traveltimes ------------------------------------
+ * In a medium that also varies laterally, the times depend on where the
+ * image point is.  The model is given as one table per node of a coarse
+ * lateral grid X_i = gx0 + i gdx, Y_j = gy0 + j gdy (node (i, j) holds the
+ * times of the medium below it, as a km_ttable holds them), and a one-way
+ * time is interpolated trilinearly over (image x, image y, h): linearly in h
+ * on each of the four nodes around the image column, then in x, then in y,
+ * each step a + f (b - a) in float64; the image depth is exact.  The node
+ * coordinate (x - gx0) / gdx is clamped to [0, n_gx - 1] (the edge nodes hold
+ * beyond the grid); an axis with one node takes no interpolation.  Every
+ * node holding the same table gives the km_ttable operators' times exactly.
+ * The column's fractions x and y are kept in float32 (a time error of at most
+ * 2^-25 of the difference between neighbouring nodes' times). */
+typedef struct km_ltable {
+    int32_t n_h;      /* rows per node table (>= 2) */
+    double dh;        /* row spacing in h (finite, > 0) */
+    int32_t n_gx, n_gy; /* nodes along x and y (>= 1 each) */
+    double gx0, gy0;  /* position of node (0, 0), same length unit as x, y (finite) */
+    double gdx, gdy;  /* node spacing (finite, > 0 on an axis with more than one node; else ignored) */
+    const float* t;   /* device float [n_gy][n_gx][n_h][nz]: node (i, j)'s one-way time in seconds at
+                         h = ih * dh and depth index iz */
+    const float* r2;  /* device float [nz]: aperture, as km_traveltime.r2 */
+    int32_t time_precision; /* km_time_precision, as in km_ttable */
+} km_ltable;
+
+/* As kirchhoff_migrate_table with laterally varying tables (W = 1).
+ * KM_E_INVALID also for a NULL table, n_gx or n_gy < 1, gx0 / gy0 not
+ * finite, gdx (gdy) not finite or <= 0 with n_gx (n_gy) > 1, and the
+ * km_ttable conditions on n_h, dh, t and r2; KM_E_UNSUPPORTED for
+ * n_gx * n_gy * n_h * nz >= 2^31.  Work per pair: 16 table reads (4 nodes x
+ * 2 rows x 2 legs) where a km_ttable pair takes 4. */
+km_status kirchhoff_migrate_ltable(const km_traces* traces, const km_grid* grid, const km_ltable* table,
+                                   float* image, int32_t accumulate, int32_t tile, void* stream);
+
+/* As kirchhoff_demigrate with laterally varying tables and W = 1: the exact
+ * transpose of kirchhoff_migrate_ltable for the same inputs. */
+km_status kirchhoff_demigrate_ltable(const float* image, const km_grid* grid, const km_ltable* table,
+                                     const km_traces* out, int32_t accumulate, int32_t tile, void* stream);
 
 /* Anti-alias operator filter (the paper is silent on aliasing; this is the
  * triangle filter of production Kirchhoff migration).  Per pair the trace is
@@ -338,7 +377,8 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
                   int32_t reps, void* stream, int32_t* best_tile /* host */, float* best_ms /* host */);
 
 /* The class cache of km_tune.  kind: 0 = square-root times, 1 = table times,
- * 2 = anti-alias filter.  km_tune_lookup returns -1 when nothing is recorded;
+ * 2 = anti-alias filter, 3 = laterally varying tables (km_tune does not time
+ * these: record their tile here).  km_tune_lookup returns -1 when nothing is recorded;
  * km_tune_record stores (and persists) a tile with its time. */
 int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
                        int32_t n_samples);

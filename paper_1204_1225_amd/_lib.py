@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # KM_LIBRARY names another build of this library (the sanitizer build of its
 # host code, for instance); by default the in-tree one
 LIB_PATH = os.environ.get("KM_LIBRARY") or os.path.join(HERE, "libkirchhoff.so")
-ABI_VERSION = 2
+ABI_VERSION = 3
 
 KM_OK, KM_E_INVALID, KM_E_UNSUPPORTED, KM_E_HIP, KM_E_NOMEM = range(5)
 KM_F32, KM_BF16, KM_F16 = 0, 1, 2
@@ -40,6 +40,11 @@ class KmTraveltime(ctypes.Structure):
 
 class KmTtable(ctypes.Structure):
     _fields_ = [("n_h", _i32), ("dh", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32)]
+
+
+class KmLtable(ctypes.Structure):
+    _fields_ = [("n_h", _i32), ("dh", _f64), ("n_gx", _i32), ("n_gy", _i32), ("gx0", _f64), ("gy0", _f64),
+                ("gdx", _f64), ("gdy", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32)]
 
 
 class KmAntialias(ctypes.Structure):
@@ -78,6 +83,8 @@ SIGNATURES = {
     "kirchhoff_demigrate": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmTraces), _i32, _i32, _vp]),
     "kirchhoff_migrate_table": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTtable), _vp, _i32, _i32, _vp]),
     "kirchhoff_demigrate_table": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTtable), _P(KmTraces), _i32, _i32, _vp]),
+    "kirchhoff_migrate_ltable": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmLtable), _vp, _i32, _i32, _vp]),
+    "kirchhoff_demigrate_ltable": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmLtable), _P(KmTraces), _i32, _i32, _vp]),
     "kirchhoff_migrate_aa": (ctypes.c_int, [_P(KmTraces), _P(KmGrid), _P(KmTraveltime), _P(KmWeight),
                                             _P(KmAntialias), _vp, _i32, _i32, _vp]),
     "kirchhoff_demigrate_aa": (ctypes.c_int, [_vp, _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmAntialias),

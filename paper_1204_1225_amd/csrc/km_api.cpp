@@ -333,7 +333,7 @@ void tune_save_locked() {
 }
 
 // Traveltime kinds of the cache key.
-enum { KIND_DSR = 0, KIND_TABLE = 1, KIND_AA = 2 };
+enum { KIND_DSR = 0, KIND_TABLE = 1, KIND_AA = 2, KIND_LTABLE = 3 };
 
 // Untuned choice: the shapes measured fastest on the 3D survey (migrate:
 // 8 waves x 4 column groups x 8 slots; demigrate: 8 waves x 4 slots x 1
@@ -344,7 +344,7 @@ enum { KIND_DSR = 0, KIND_TABLE = 1, KIND_AA = 2 };
 int default_tile(int op, int kind) {
     if (op == 0) return kind == KIND_AA ? 1 : 2;
     if (kind == KIND_AA) return 3;
-    return kind == KIND_TABLE ? 1 : 3;
+    return kind == KIND_TABLE || kind == KIND_LTABLE ? 1 : 3;
 }
 
 // The caller's tile, else the tuned tile of this problem's class, else the default.
@@ -371,9 +371,15 @@ km_status pick_tile(int op, int tile, int dtype, int kind, int prec, int nz, int
     return KM_OK;
 }
 
+// The node grid of laterally varying tables (a km_ltable without its arrays).
+struct Lateral {
+    int32_t n_gx, n_gy;
+    double gx0, gy0, gdx, gdy;
+};
+
 km_status run_op(int op, const km_traces* t, const km_grid* g, const km_traveltime* tt, const km_weight* w,
                  float* image, int accumulate, int tile, hipStream_t s, const km_ttable* tab = nullptr,
-                 const km_antialias* aa = nullptr) {
+                 const km_antialias* aa = nullptr, const Lateral* lat = nullptr) {
     km::Params P = base_params(t, g, tt, w, image, accumulate);
     if (aa) {
         P.aa_dx = static_cast<float>(aa->dx);
@@ -393,6 +399,17 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         P.s2 = nullptr;
         P.r2 = tab->r2;
         P.weight = KM_W_UNIT;
+    }
+    if (tab && lat) {
+        const int32_t node = tab->n_h * g->nz;  // < 2^31: checked with the whole table
+        P.n_gx = lat->n_gx;
+        P.n_gy = lat->n_gy;
+        P.ldx = lat->n_gx > 1 ? node : 0;
+        P.ldy = lat->n_gy > 1 ? lat->n_gx * node : 0;
+        P.gx0 = lat->gx0;
+        P.gy0 = lat->gy0;
+        P.gdx = lat->gdx;
+        P.gdy = lat->gdy;
     }
     km_status st = shape_params(op, tile, P);
     if (st != KM_OK) return st;
@@ -415,7 +432,7 @@ km_status zero_floats(float* p, int64_t n, hipStream_t s) {
 
 km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_traveltime* tt, const km_weight* weight,
                        float* image, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab,
-                       const km_antialias* aa = nullptr) {
+                       const km_antialias* aa = nullptr, const Lateral* lat = nullptr) {
     km_status st = check_traces(traces, true, "kirchhoff_migrate");
     if (st != KM_OK) return st;
     st = check_grid(grid, tt, weight, "kirchhoff_migrate");
@@ -423,18 +440,18 @@ km_status migrate_impl(const km_traces* traces, const km_grid* grid, const km_tr
     if (grid_empty(grid)) return KM_OK;
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_migrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_tile(0, tile, traces->dtype, tab ? KIND_TABLE : aa ? KIND_AA : KIND_DSR, tt->time_precision, grid->nz,
-                   traces->n_samples, &shape);
+    st = pick_tile(0, tile, traces->dtype, lat ? KIND_LTABLE : tab ? KIND_TABLE : aa ? KIND_AA : KIND_DSR,
+                   tt->time_precision, grid->nz, traces->n_samples, &shape);
     if (st != KM_OK) return st;
     hipStream_t s = static_cast<hipStream_t>(stream);
     if (traces->n_traces == 0 && !accumulate)
         return zero_floats(image, static_cast<int64_t>(grid->n_bins) * grid->ny * grid->nx * grid->nz, s);
-    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s, tab, aa);
+    return run_op(0, traces, grid, tt, weight, image, accumulate, shape, s, tab, aa, lat);
 }
 
 km_status demigrate_impl(const float* image, const km_grid* grid, const km_traveltime* tt, const km_weight* weight,
                          const km_traces* out, int32_t accumulate, int32_t tile, void* stream, const km_ttable* tab,
-                         const km_antialias* aa = nullptr) {
+                         const km_antialias* aa = nullptr, const Lateral* lat = nullptr) {
     km_status st = check_traces(out, true, "kirchhoff_demigrate");
     if (st != KM_OK) return st;
     if (out->dtype != KM_F32)
@@ -451,10 +468,10 @@ km_status demigrate_impl(const float* image, const km_grid* grid, const km_trave
     }
     if (!image || !aligned(image, 4)) return fail(KM_E_INVALID, "kirchhoff_demigrate: image is NULL or misaligned");
     int shape = 0;
-    st = pick_tile(1, tile, out->dtype, tab ? KIND_TABLE : aa ? KIND_AA : KIND_DSR, tt->time_precision, grid->nz,
-                   out->n_samples, &shape);
+    st = pick_tile(1, tile, out->dtype, lat ? KIND_LTABLE : tab ? KIND_TABLE : aa ? KIND_AA : KIND_DSR,
+                   tt->time_precision, grid->nz, out->n_samples, &shape);
     if (st != KM_OK) return st;
-    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab, aa);
+    return run_op(1, out, grid, tt, weight, const_cast<float*>(image), accumulate, shape, s, tab, aa, lat);
 }
 
 // Anti-alias filter options.
@@ -485,6 +502,25 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
         if (!tab->t || !tab->r2) return fail(KM_E_INVALID, "%s: t and r2 must be non-NULL", who);
         if (!aligned(tab->t, 4) || !aligned(tab->r2, 4)) return fail(KM_E_INVALID, "%s: t, r2 misaligned", who);
     }
+    return KM_OK;
+}
+
+// Laterally varying tables: the node grid, then the table as check_table
+// sees it (the node tables together must stay below 2^31 floats).
+km_status check_ltable(const km_ltable* lt, const km_grid* grid, const char* who, km_ttable* tab, Lateral* lat) {
+    if (!lt) return fail(KM_E_INVALID, "%s: table is NULL", who);
+    if (lt->n_gx < 1 || lt->n_gy < 1) return fail(KM_E_INVALID, "%s: n_gx and n_gy must be >= 1", who);
+    if (!std::isfinite(lt->gx0) || !std::isfinite(lt->gy0))
+        return fail(KM_E_INVALID, "%s: gx0 and gy0 must be finite", who);
+    if ((lt->n_gx > 1 && !(lt->gdx > 0.0 && std::isfinite(lt->gdx))) ||
+        (lt->n_gy > 1 && !(lt->gdy > 0.0 && std::isfinite(lt->gdy))))
+        return fail(KM_E_INVALID, "%s: gdx (gdy) must be finite and > 0 when n_gx (n_gy) > 1", who);
+    *tab = km_ttable{lt->n_h, lt->dh, lt->t, lt->r2, lt->time_precision};
+    const km_status st = check_table(tab, grid, who);
+    if (st != KM_OK) return st;
+    if (grid && static_cast<int64_t>(lt->n_gx) * lt->n_gy * lt->n_h * grid->nz >= (int64_t(1) << 31))
+        return fail(KM_E_UNSUPPORTED, "%s: n_gx * n_gy * n_h * nz must be < 2^31", who);
+    *lat = Lateral{lt->n_gx, lt->n_gy, lt->gx0, lt->gy0, lt->n_gx > 1 ? lt->gdx : 1.0, lt->n_gy > 1 ? lt->gdy : 1.0};
     return KM_OK;
 }
 
@@ -529,6 +565,28 @@ km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, con
     const km_traveltime tt{tab->r2, tab->r2, tab->r2, tab->time_precision};
     const km_weight w{KM_W_UNIT};
     return demigrate_impl(image, grid, &tt, &w, out, accumulate, tile, stream, tab);
+}
+
+km_status kirchhoff_migrate_ltable(const km_traces* traces, const km_grid* grid, const km_ltable* ltab, float* image,
+                                   int32_t accumulate, int32_t tile, void* stream) {
+    km_ttable tab;
+    Lateral lat;
+    km_status st = check_ltable(ltab, grid, "kirchhoff_migrate_ltable", &tab, &lat);
+    if (st != KM_OK) return st;
+    const km_traveltime tt{tab.r2, tab.r2, tab.r2, tab.time_precision};
+    const km_weight w{KM_W_UNIT};
+    return migrate_impl(traces, grid, &tt, &w, image, accumulate, tile, stream, &tab, nullptr, &lat);
+}
+
+km_status kirchhoff_demigrate_ltable(const float* image, const km_grid* grid, const km_ltable* ltab,
+                                     const km_traces* out, int32_t accumulate, int32_t tile, void* stream) {
+    km_ttable tab;
+    Lateral lat;
+    km_status st = check_ltable(ltab, grid, "kirchhoff_demigrate_ltable", &tab, &lat);
+    if (st != KM_OK) return st;
+    const km_traveltime tt{tab.r2, tab.r2, tab.r2, tab.time_precision};
+    const km_weight w{KM_W_UNIT};
+    return demigrate_impl(image, grid, &tt, &w, out, accumulate, tile, stream, &tab, nullptr, &lat);
 }
 
 km_status kirchhoff_migrate_aa(const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
@@ -685,7 +743,7 @@ int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t kind, int32_t time_pre
 km_status km_tune_record(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
                          int32_t n_samples, int32_t tile, float ms) {
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tune_record: op must be 0 or 1");
-    if (kind < KIND_DSR || kind > KIND_AA) return fail(KM_E_INVALID, "km_tune_record: unknown kind %d", kind);
+    if (kind < KIND_DSR || kind > KIND_LTABLE) return fail(KM_E_INVALID, "km_tune_record: unknown kind %d", kind);
     int shape = 0, level = 0;
     if (!decode_tile(op, tile, &shape, &level)) return fail(KM_E_INVALID, "km_tune_record: tile out of range");
     const TuneKey key = tune_key(op, dtype, kind, time_precision, nz, n_samples);

@@ -97,18 +97,19 @@ __device__ __forceinline__ void dem_masked_ext(float A0, float B0, float A1, flo
 }
 
 // dem_pair_table with extended legs (table_leg_ext).
-template <bool TF>
-__device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, int iz0, int iz1, double* row,
-                                                   float wlo, float whi, float x0, float x1, bool act0, bool act1) {
+template <bool TF, bool LAT>
+__device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, LCol C, int iz0, int iz1,
+                                                   double* row, float wlo, float whi, float x0, float x1, bool act0,
+                                                   bool act1) {
     if (act0) {
-        const PairX p0 = eval_pair_table_ext<TF>(P, Ls, Lr, iz0, wlo, whi);
+        const PairX p0 = eval_pair_table_ext<TF, LAT>(P, Ls, Lr, iz0, wlo, whi, C);
         const double q0 = static_cast<double>(x0);
         const double b0 = p0.fd * q0;
         atomicAdd(row + p0.i, q0 - b0);
         atomicAdd(row + p0.i + 1, b0);
     }
     if (act1) {
-        const PairX p1 = eval_pair_table_ext<TF>(P, Ls, Lr, iz1, wlo, whi);
+        const PairX p1 = eval_pair_table_ext<TF, LAT>(P, Ls, Lr, iz1, wlo, whi, C);
         const double q1 = static_cast<double>(x1);
         const double b1 = p1.fd * q1;
         atomicAdd(row + p1.i, q1 - b1);
@@ -117,19 +118,20 @@ __device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TL
 }
 
 // dem_masked with table traveltimes (W = 1); iz0, iz1 are the lane's depths
-// of the two slots, clamped into the table.
-template <bool TF, bool MASKED>
-__device__ __forceinline__ void dem_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz0, int iz1, double* row,
-                                               float tfo, float wlo, float whi, float x0, float x1, bool act0,
-                                               bool act1) {
+// of the two slots, clamped into the table.  LAT: laterally varying tables, C
+// the column on the node grid.
+template <bool TF, bool MASKED, bool LAT>
+__device__ __forceinline__ void dem_pair_table(const Params& P, TLeg Ls, TLeg Lr, LCol C, int iz0, int iz1,
+                                               double* row, float tfo, float wlo, float whi, float x0, float x1,
+                                               bool act0, bool act1) {
     if (!MASKED || act0) {
-        const Pair p0 = eval_pair_table<TF>(P, Ls, Lr, iz0, tfo, wlo, whi);
+        const Pair p0 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz0, tfo, wlo, whi, C);
         const float b0 = p0.f * x0;
         atomicAdd(row + p0.i, static_cast<double>(x0 - b0));
         atomicAdd(row + p0.i + 1, static_cast<double>(b0));
     }
     if (!MASKED || act1) {
-        const Pair p1 = eval_pair_table<TF>(P, Ls, Lr, iz1, tfo, wlo, whi);
+        const Pair p1 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz1, tfo, wlo, whi, C);
         const float b1 = p1.f * x1;
         atomicAdd(row + p1.i, static_cast<double>(x1 - b1));
         atomicAdd(row + p1.i + 1, static_cast<double>(b1));
@@ -257,8 +259,10 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
     const int nbx = ix1 - ix0 + 1;
 
     // every pairing of column c with the segment's traces
+    constexpr bool LAT = TT == TT_LTABLE;
     auto process = [&](Column<KS>& c) {
         const float px = c.px, py = c.py;
+        const LCol lc = LAT ? lateral_col(P, px, py) : LCol{0, 0.0f, 0.0f};
 #pragma unroll
         for (int k = 0; k < KS; ++k) c.x[k] *= S[k];
         const float* x = c.x;
@@ -287,27 +291,27 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
                 }
                 continue;
             }
-            if (TT == TT_TABLE && PX) {
+            if (is_table(TT) && PX) {
                 const TLegX Ls = table_leg_ext(P, Lx.hs2), Lr = table_leg_ext(P, Lx.hr2);
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
                     if (!((any >> k) & 3u)) continue;
                     const int iz0 = min(max(slot_depth<kIL>(z0, k, d), 0), P.nz - 1);
                     const int iz1 = min(max(slot_depth<kIL>(z0, k + 1, d), 0), P.nz - 1);
-                    dem_pair_table_ext<TF>(P, Ls, Lr, iz0, iz1, row, wlo, whi, x[k], x[k + 1], L.hmax <= T.R[k],
-                                           L.hmax <= T.R[k + 1]);
+                    dem_pair_table_ext<TF, LAT>(P, Ls, Lr, lc, iz0, iz1, row, wlo, whi, x[k], x[k + 1],
+                                                L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
                 }
                 continue;
             }
-            if (TT == TT_TABLE) {
+            if (is_table(TT)) {
                 const TLeg Ls = table_leg(P, L.hs2), Lr = table_leg(P, L.hr2);
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
                     if (!((any >> k) & 3u)) continue;
                     const int iz0 = min(max(slot_depth<kIL>(z0, k, d), 0), P.nz - 1);
                     const int iz1 = min(max(slot_depth<kIL>(z0, k + 1, d), 0), P.nz - 1);
-                    dem_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1],
-                                             L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
+                    dem_pair_table<TF, true, LAT>(P, Ls, Lr, lc, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1],
+                                                  L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
                 }
                 continue;
             }
@@ -511,6 +515,15 @@ static hipError_t launch_demigrate_shape(const Params& P, hipStream_t s) {
     const int64_t nblk = (P.n_traces + P.tb - 1) / P.tb;
     dim3 grid(static_cast<unsigned>(nblk)), block(NW * 64);
     const size_t lds = lds_bytes_f64rows(P);
+    if (P.ttab && P.n_gx > 0) {  // laterally varying tables: W = 1
+        if (P.prec) {
+            if (P.has_tf)
+                return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_LTABLE, true>, grid, block, lds, s, P);
+            return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_LTABLE, true>, grid, block, lds, s, P);
+        }
+        if (P.has_tf) return launch_with_lds(demigrate_kernel<NW, KS, NQ, true, W_UNIT, TT_LTABLE>, grid, block, lds, s, P);
+        return launch_with_lds(demigrate_kernel<NW, KS, NQ, false, W_UNIT, TT_LTABLE>, grid, block, lds, s, P);
+    }
     if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
         if (P.prec) {
             if (P.has_tf)

@@ -75,12 +75,21 @@ struct Params {
     // time precision: 0 = float32 evaluation, 1 = extended (the PX kernels)
     int32_t prec;
     double inv_dh_d;     // 1 / dh in float64 (extended table legs)
+    // laterally varying tables (the TT_LTABLE kernels): ttab then holds one
+    // [n_h][nz] table per node of the grid X_i = gx0 + i gdx, Y_j = gy0 + j gdy,
+    // node (i, j) at float offset (j n_gx + i) n_h nz
+    int32_t n_gx, n_gy;
+    int32_t ldx, ldy;    // floats from a node's table to its +x / +y neighbour's (0 on an axis of one node)
+    double gx0, gy0, gdx, gdy;
 };
 
 // Traveltime kinds of the kernels: the per-depth double-square-root form
 // (t0sq, s2) or a one-way time table T(h, z) interpolated linearly in h.
 // TT_AA: the double-square-root form with the anti-alias triangle filter.
-enum TravelKind : int32_t { TT_DSR = 0, TT_TABLE = 1, TT_AA = 2 };
+// TT_LTABLE: one table per node of a coarse lateral grid, interpolated over
+// (image x, image y, h).
+enum TravelKind : int32_t { TT_DSR = 0, TT_TABLE = 1, TT_AA = 2, TT_LTABLE = 3 };
+constexpr bool is_table(int tt) { return tt == TT_TABLE || tt == TT_LTABLE; }
 constexpr int kAAMaxHalf = 32;  // largest anti-alias half-width the kernels accept
 
 // First index in sorted bin[0..n) whose value is >= key.
@@ -300,12 +309,88 @@ __device__ __forceinline__ double table_time_ext(const Params& P, TLegX L, int i
     return fma(L.f, b - a, a);
 }
 
+// Interpolated one-way time in float64: b - a of two adjacent float32 table
+// values is exact, the interpolation and the sum are float64, so the time
+// keeps the table's own precision (float32 rounding of the time in seconds
+// and again in samples would cost about 1e-5 of a band-limited result).
+__device__ __forceinline__ double table_time(const Params& P, TLeg L, int iz) {
+    const float a = P.ttab[L.off + iz], b = P.ttab[L.off + P.nz + iz];
+    return fma(static_cast<double>(L.f), static_cast<double>(b - a), static_cast<double>(a));
+}
+
+// Laterally varying tables: the image column's place on the node grid, off
+// the float offset of the table of its lower node (i, j), fx and fy the
+// fractions towards nodes i + 1 and j + 1 (float32: the time then moves by at
+// most 2^-25 of the times' difference between neighbouring nodes).
+struct LCol {
+    int32_t off;
+    float fx, fy;
+};
+
+// Lower node and fraction of coordinate c on an axis of n nodes, c clamped
+// to the axis (beyond it the edge node holds); one node: no interpolation.
+__device__ __forceinline__ void node_axis(double c, double c0, double g, int n, int& i, double& f) {
+    if (n <= 1) {
+        i = 0;
+        f = 0.0;
+        return;
+    }
+    const double a = fmin(fmax((c - c0) / g, 0.0), static_cast<double>(n - 1));
+    i = min(static_cast<int>(a), n - 2);
+    f = a - static_cast<double>(i);
+}
+
+__device__ __forceinline__ LCol lateral_col(const Params& P, float px, float py) {
+    int i, j;
+    double fx, fy;
+    node_axis(px, P.gx0, P.gdx, P.n_gx, i, fx);
+    node_axis(py, P.gy0, P.gdy, P.n_gy, j, fy);
+    LCol C;
+    C.off = (j * P.n_gx + i) * P.n_h * P.nz;
+    C.fx = static_cast<float>(fx);
+    C.fy = static_cast<float>(fy);
+    return C;
+}
+
+// One-way time on the laterally varying tables: the interpolation in h of
+// table_time on the four nodes around the column, then in x, then in y, each
+// a + f (b - a) in float64 (equal node tables give table_time exactly).
+__device__ __forceinline__ double ltable_time(const Params& P, TLeg L, LCol C, int iz) {
+    const float* t = P.ttab + (C.off + L.off + iz);
+    const int nz = P.nz, dx = P.ldx, dy = P.ldy;
+    const double fh = L.f;
+    const float a00 = t[0], b00 = t[nz], a10 = t[dx], b10 = t[dx + nz];
+    const float a01 = t[dy], b01 = t[dy + nz], a11 = t[dx + dy], b11 = t[dx + dy + nz];
+    const double t00 = fma(fh, static_cast<double>(b00 - a00), static_cast<double>(a00));
+    const double t10 = fma(fh, static_cast<double>(b10 - a10), static_cast<double>(a10));
+    const double t01 = fma(fh, static_cast<double>(b01 - a01), static_cast<double>(a01));
+    const double t11 = fma(fh, static_cast<double>(b11 - a11), static_cast<double>(a11));
+    const double fx = C.fx, fy = C.fy;
+    const double t0 = fma(fx, t10 - t00, t00), t1 = fma(fx, t11 - t01, t01);
+    return fma(fy, t1 - t0, t0);
+}
+
+// ltable_time with an extended leg (the h fraction and the differences in float64).
+__device__ __forceinline__ double ltable_time_ext(const Params& P, TLegX L, LCol C, int iz) {
+    const float* t = P.ttab + (C.off + L.off + iz);
+    const int nz = P.nz, dx = P.ldx, dy = P.ldy;
+    const double fh = L.f;
+    const double a00 = t[0], b00 = t[nz], a10 = t[dx], b10 = t[dx + nz];
+    const double a01 = t[dy], b01 = t[dy + nz], a11 = t[dx + dy], b11 = t[dx + dy + nz];
+    const double t00 = fma(fh, b00 - a00, a00), t10 = fma(fh, b10 - a10, a10);
+    const double t01 = fma(fh, b01 - a01, a01), t11 = fma(fh, b11 - a11, a11);
+    const double fx = C.fx, fy = C.fy;
+    const double t0 = fma(fx, t10 - t00, t00), t1 = fma(fx, t11 - t01, t01);
+    return fma(fy, t1 - t0, t0);
+}
+
 // eval_pair_table with extended legs (same clamp as eval_pair_table; the
 // fraction is returned in float32 and float64).
-template <bool TF>
+template <bool TF, bool LAT = false>
 __device__ __forceinline__ PairX eval_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, int iz, float wlo,
-                                                     float whi) {
-    double w = (table_time_ext(P, Ls, iz) + table_time_ext(P, Lr, iz)) * P.inv_dt;
+                                                     float whi, LCol C = LCol{0, 0.0f, 0.0f}) {
+    double w = (LAT ? ltable_time_ext(P, Ls, C, iz) + ltable_time_ext(P, Lr, C, iz)
+                    : table_time_ext(P, Ls, iz) + table_time_ext(P, Lr, iz)) * P.inv_dt;
     if (TF) w = w + P.tf_off_d;
     w = fmin(fmax(w, static_cast<double>(wlo)), static_cast<double>(whi));
     PairX p;
@@ -316,22 +401,15 @@ __device__ __forceinline__ PairX eval_pair_table_ext(const Params& P, TLegX Ls, 
     return p;
 }
 
-// Interpolated one-way time in float64: b - a of two adjacent float32 table
-// values is exact, the interpolation and the sum are float64, so the time
-// keeps the table's own precision (float32 rounding of the time in seconds
-// and again in samples would cost about 1e-5 of a band-limited result).
-__device__ __forceinline__ double table_time(const Params& P, TLeg L, int iz) {
-    const float a = P.ttab[L.off + iz], b = P.ttab[L.off + P.nz + iz];
-    return fma(static_cast<double>(L.f), static_cast<double>(b - a), static_cast<double>(a));
-}
-
 // The pair evaluation of eval_pair with table times (iz < nz; W = 1); the
-// clamp bounds are those of clamp_bounds.
-template <bool TF, bool CLAMP = true>
+// clamp bounds are those of clamp_bounds.  LAT: laterally varying tables at
+// column C.
+template <bool TF, bool CLAMP = true, bool LAT = false>
 __device__ __forceinline__ Pair eval_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz, float tf_off, float wlo,
-                                                float whi) {
+                                                float whi, LCol C = LCol{0, 0.0f, 0.0f}) {
     (void)tf_off;
-    double w = (table_time(P, Ls, iz) + table_time(P, Lr, iz)) * P.inv_dt;
+    double w = (LAT ? ltable_time(P, Ls, C, iz) + ltable_time(P, Lr, C, iz)
+                    : table_time(P, Ls, iz) + table_time(P, Lr, iz)) * P.inv_dt;
     if (TF) w = w + P.tf_off_d;
     if (CLAMP) w = fmin(fmax(w, static_cast<double>(wlo)), static_cast<double>(whi));
     Pair p;
@@ -408,7 +486,7 @@ __device__ __forceinline__ void load_chunk_tables(const Params& P, int z0, int d
         float A = 1.0f, B = 0.0f, R = -1.0f;
         bool valid = false;
         if (iz >= 0 && iz < P.nz) {
-            if (TT == TT_TABLE) {
+            if (is_table(TT)) {
                 // table times carry no t0sq / s2; A, B are unused and W = 1
                 valid = true;
                 A = 0.0f;

@@ -125,13 +125,14 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
 }
 
 // mig_pair with table traveltimes (W = 1): iz0, iz1 are the lane's depths of
-// the two slots, clamped into the table.
-template <bool TF, bool MASKED>
-__device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz0, int iz1, float hm,
+// the two slots, clamped into the table.  LAT: laterally varying tables, C the
+// lane's column on the node grid.
+template <bool TF, bool MASKED, bool LAT>
+__device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr, LCol C, int iz0, int iz1, float hm,
                                                const float* row, float tfo, float wlo, float whi, float R0, float R1,
                                                float& acc0, float& acc1) {
-    const Pair p0 = eval_pair_table<TF>(P, Ls, Lr, iz0, tfo, wlo, whi);
-    const Pair p1 = eval_pair_table<TF>(P, Ls, Lr, iz1, tfo, wlo, whi);
+    const Pair p0 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz0, tfo, wlo, whi, C);
+    const Pair p1 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz1, tfo, wlo, whi, C);
     const float a0 = row[p0.i], b0 = row[p0.i + 1];
     const float a1 = row[p1.i], b1 = row[p1.i + 1];
     float v0 = fmaf(p0.f, b0 - a0, a0);
@@ -163,12 +164,12 @@ __device__ __forceinline__ void mig_slot_ext(float A, float B, double Hs, double
 }
 
 // mig_pair_table with extended legs (table_leg_ext).
-template <bool TF>
-__device__ __forceinline__ void mig_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, int iz0, int iz1, float hm,
-                                                   const float* row, float wlo, float whi, float R0, float R1,
-                                                   float& acc0, float& acc1) {
-    const PairX p0 = eval_pair_table_ext<TF>(P, Ls, Lr, iz0, wlo, whi);
-    const PairX p1 = eval_pair_table_ext<TF>(P, Ls, Lr, iz1, wlo, whi);
+template <bool TF, bool LAT>
+__device__ __forceinline__ void mig_pair_table_ext(const Params& P, TLegX Ls, TLegX Lr, LCol C, int iz0, int iz1,
+                                                   float hm, const float* row, float wlo, float whi, float R0,
+                                                   float R1, float& acc0, float& acc1) {
+    const PairX p0 = eval_pair_table_ext<TF, LAT>(P, Ls, Lr, iz0, wlo, whi, C);
+    const PairX p1 = eval_pair_table_ext<TF, LAT>(P, Ls, Lr, iz1, wlo, whi, C);
     const float a0 = row[p0.i], b0 = row[p0.i + 1];
     const float a1 = row[p1.i], b1 = row[p1.i + 1];
     float v0 = fmaf(p0.f, b0 - a0, a0);
@@ -214,7 +215,8 @@ __device__ __forceinline__ void mig_slot_aa(float A, float B, float hs2, float h
 
 // RREG: the masked slots take the lanes' aperture values from registers
 // (else from the LDS copy, which costs fewer registers).
-// TT: traveltime kind (TT_TABLE: one-way time table, W = 1).
+// TT: traveltime kind (TT_TABLE: one-way time table, W = 1; TT_LTABLE: one
+// table per node of a lateral grid, W = 1).
 // PX: extended-precision times (eval_pair_ext, table_leg_ext); the squared
 // leg lengths then also reach the depth lanes in float64.
 //
@@ -274,6 +276,12 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             py[q] = P.y[col / P.nx];
         }
     }
+
+    // the lane's columns on the node grid of laterally varying tables
+    constexpr bool LAT = TT == TT_LTABLE;
+    LCol lc[CWQ];
+#pragma unroll
+    for (int q = 0; q < CWQ; ++q) lc[q] = LAT ? lateral_col(P, px[q], py[q]) : LCol{0, 0.0f, 0.0f};
 
     float acc[CWQ][KS];
 #pragma unroll
@@ -543,7 +551,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     // max(hs2, hr2): one v_max (fmaxf would first quiet both inputs)
                     float hm;
                     asm("v_max_f32 %0, %1, %2" : "=v"(hm) : "v"(hs2), "v"(hr2));
-                    if (TT == TT_TABLE && PX) {
+                    if (is_table(TT) && PX) {
                         const TLegX Ls = table_leg_ext(P, Hs), Lr = table_leg_ext(P, Hr);
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
@@ -552,11 +560,11 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 const int iz1 = min(max(z0 + (k + 1) * kGroup + d, 0), P.nz - 1);
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair_table_ext<TF>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, wlo, whi, R0, R1, acc[q][k],
-                                                       acc[q][k + 1]);
+                                mig_pair_table_ext<TF, LAT>(P, Ls, Lr, lc[q], iz0, iz1, hm, sTr + rb, wlo, whi, R0, R1,
+                                                            acc[q][k], acc[q][k + 1]);
                             }
                         }
-                    } else if (TT == TT_TABLE) {
+                    } else if (is_table(TT)) {
                         const TLeg Ls = table_leg(P, hs2), Lr = table_leg(P, hr2);
 #pragma unroll
                         for (int k = 0; k < KS; k += 2) {
@@ -565,8 +573,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 const int iz1 = min(max(z0 + (k + 1) * kGroup + d, 0), P.nz - 1);
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair_table<TF, true>(P, Ls, Lr, iz0, iz1, hm, sTr + rb, tfo, wlo, whi, R0, R1, acc[q][k],
-                                                         acc[q][k + 1]);
+                                mig_pair_table<TF, true, LAT>(P, Ls, Lr, lc[q], iz0, iz1, hm, sTr + rb, tfo, wlo, whi, R0,
+                                                              R1, acc[q][k], acc[q][k + 1]);
                             }
                         }
                     } else if (AA) {
@@ -712,6 +720,15 @@ template <int NW, int CWQ, int KS>
 static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
     dim3 grid(P.n_coltiles, P.n_zchunks, P.n_bins), block(NW * 64);
     const size_t lds = lds_bytes(P, KS);
+    if (P.ttab && P.n_gx > 0) {  // laterally varying tables: W = 1
+        if (P.prec) {
+            if (P.has_tf)
+                return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_LTABLE, true>, grid, block, lds, s, P);
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_LTABLE, true>, grid, block, lds, s, P);
+        }
+        if (P.has_tf) return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_LTABLE>, grid, block, lds, s, P);
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_LTABLE>, grid, block, lds, s, P);
+    }
     if (P.ttab) {  // table traveltimes: W = 1 (the host rejects other weights)
         if (P.prec) {
             if (P.has_tf)

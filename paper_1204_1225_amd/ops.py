@@ -15,7 +15,8 @@ import numpy as np
 import torch
 
 from . import _lib
-from ._lib import KmAntialias, KmGrid, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmTtable, KmWeight, check
+from ._lib import (KmAntialias, KmGrid, KmLtable, KmProblem, KmTileInfo, KmTraces, KmTraveltime, KmTtable, KmWeight,
+                   check)
 
 _DTYPES = {"f32": _lib.KM_F32, "bf16": _lib.KM_BF16, "f16": _lib.KM_F16}
 _PRECISIONS = {"fp32": _lib.KM_TIME_FP32, "extended": _lib.KM_TIME_EXTENDED}
@@ -52,6 +53,8 @@ class DeviceProblem:
     dtype: str = "f32"
     ttab: Optional[torch.Tensor] = None   # float32 [n_h, nz] one-way times: table traveltimes (W = 1)
     tdh: float = 0.0
+    # laterally varying tables: (gx0, gy0, gdx, gdy) of the node grid; ttab is then [n_gy, n_gx, n_h, nz]
+    tgrid: Optional[tuple] = None
     aa: Optional[tuple] = None            # (dx, dy, max half-width): anti-alias triangle filter
     prec: str = "fp32"                    # time arithmetic: "fp32" or "extended" (km_time_precision)
 
@@ -114,9 +117,18 @@ class DeviceProblem:
         return KmAntialias(dx=float(self.aa[0]), dy=float(self.aa[1]), max_half=int(self.aa[2]))
 
     def c_table(self) -> KmTtable:
-        assert self.ttab is not None and self.ttab.shape[1] == self.nz and self.ttab.is_contiguous()
+        assert self.ttab is not None and self.tgrid is None
+        assert self.ttab.dim() == 2 and self.ttab.shape[1] == self.nz and self.ttab.is_contiguous()
         return KmTtable(n_h=int(self.ttab.shape[0]), dh=float(self.tdh), t=_ptr(self.ttab), r2=_ptr(self.r2),
                         time_precision=self.c_prec)
+
+    def c_ltable(self) -> KmLtable:
+        assert self.ttab is not None and self.tgrid is not None
+        assert self.ttab.dim() == 4 and self.ttab.shape[3] == self.nz and self.ttab.is_contiguous()
+        n_gy, n_gx, n_h, _ = (int(v) for v in self.ttab.shape)
+        gx0, gy0, gdx, gdy = (float(v) for v in self.tgrid)
+        return KmLtable(n_h=n_h, dh=float(self.tdh), n_gx=n_gx, n_gy=n_gy, gx0=gx0, gy0=gy0, gdx=gdx, gdy=gdy,
+                        t=_ptr(self.ttab), r2=_ptr(self.r2), time_precision=self.c_prec)
 
 
 def to_device(problem, device="cuda", data=None, dtype: str = "f32", prec: str = "fp32") -> DeviceProblem:
@@ -140,7 +152,9 @@ def to_device(problem, device="cuda", data=None, dtype: str = "f32", prec: str =
                        x=f32(problem.x), y=f32(problem.y), t0sq=f32(problem.t0sq), s2=f32(problem.s2),
                        r2=f32(problem.r2), prec=prec)
     if getattr(problem, "ttab", None) is not None:
-        dp = dataclasses.replace(dp, ttab=f32(problem.ttab), tdh=float(problem.tdh))
+        tgrid = getattr(problem, "tgrid", None)
+        dp = dataclasses.replace(dp, ttab=f32(problem.ttab), tdh=float(problem.tdh),
+                                 tgrid=None if tgrid is None else tuple(float(v) for v in tgrid))
     if getattr(problem, "aa", None) is not None:
         dp = dataclasses.replace(dp, aa=tuple(problem.aa))
     d = problem.data if data is None else data
@@ -169,6 +183,11 @@ def migrate(dp: DeviceProblem, data: Optional[torch.Tensor] = None, image: Optio
     assert image.shape == dp.image_shape and image.dtype == torch.float32 and image.is_contiguous()
     tr = dp.c_traces(data, dtype if data is not None else None, scale)
     lib = _lib.load()
+    if dp.tgrid is not None:
+        check(lib.kirchhoff_migrate_ltable(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_ltable()),
+                                           _ptr(image), int(accumulate), int(tile),
+                                           ctypes.c_void_p(_stream(dp.device))))
+        return image
     if dp.ttab is not None:
         check(lib.kirchhoff_migrate_table(ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_table()),
                                           _ptr(image), int(accumulate), int(tile),
@@ -195,6 +214,11 @@ def demigrate(dp: DeviceProblem, image: torch.Tensor, out: Optional[torch.Tensor
             out.zero_()
     tr = dp.c_traces(out, "f32")
     lib = _lib.load()
+    if dp.tgrid is not None:
+        check(lib.kirchhoff_demigrate_ltable(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_ltable()),
+                                             ctypes.byref(tr), int(accumulate), int(tile),
+                                             ctypes.c_void_p(_stream(dp.device))))
+        return out
     if dp.ttab is not None:
         check(lib.kirchhoff_demigrate_table(_ptr(image), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_table()),
                                             ctypes.byref(tr), int(accumulate), int(tile),
@@ -358,10 +382,12 @@ def tiles(op: int):
     return out
 
 
-KIND_DSR, KIND_TABLE, KIND_AA = 0, 1, 2
+KIND_DSR, KIND_TABLE, KIND_AA, KIND_LTABLE = 0, 1, 2, 3
 
 
 def problem_kind(dp: DeviceProblem) -> int:
+    if dp.tgrid is not None:
+        return KIND_LTABLE
     return KIND_TABLE if dp.ttab is not None else KIND_AA if dp.aa is not None else KIND_DSR
 
 
@@ -371,6 +397,9 @@ def tune(op: int, dp: DeviceProblem, image: torch.Tensor, traces_out: Optional[t
     kind) and record the fastest for its class; returns (tile, ms).  For op 0
     `image` is overwritten with the migration; for op 1 `image` is the input
     and `traces_out` (float32 [n_traces, n_t]) is overwritten."""
+    if dp.tgrid is not None:
+        raise _lib.KirchhoffError(_lib.KM_E_UNSUPPORTED, "tune: laterally varying tables are recorded with "
+                                                         "km_tune_record, not timed by km_tune")
     best, ms = ctypes.c_int32(-1), ctypes.c_float(0.0)
     tr = dp.c_traces() if op == 0 else dp.c_traces(traces_out, "f32")
     tab = ctypes.byref(dp.c_table()) if dp.ttab is not None else None

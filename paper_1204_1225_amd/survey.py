@@ -209,6 +209,18 @@ def with_lateral_tables(problem: "Problem", v0_at, k: float, gx0: float, gy0: fl
                                                                         float(gdy)), weight=WEIGHT_UNIT)
 
 
+SURVEY3D_LATERAL_V0 = (1500.0, 0.05, -0.04, 2500.0, 2500.0)  # v0, d v0 / dx, d v0 / dy, centre x, y
+
+
+def with_survey3d_lateral_tables(p: "Problem", dh: float = 10.0) -> "Problem":
+    """The 3D survey's laterally varying model: v(x, y, z) = v0(x, y) + 0.5 z
+    with v0 = 1500 + 0.05 (x - 2500) - 0.04 (y - 2500) m/s (about 1420 to 1580
+    over the image), tables of curved rays under each node of a 9 x 9 grid at
+    400 m (900 .. 4100 m in x and y, covering the image), rows every dh m."""
+    v0_at = lateral_v0(*SURVEY3D_LATERAL_V0)
+    return with_lateral_tables(p, v0_at, 0.5, 900.0, 900.0, 400.0, 400.0, 9, 9, dh=dh)
+
+
 def aperture_table(t0sq: np.ndarray, s2: np.ndarray, aperture_deg: float) -> np.ndarray:
     """r2[iz] = tan^2(theta_max) * t0^2 / s2, rounded once to float32.
 

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(lib):
 def test_abi_version_and_limits(lib):
     from paper_1204_1225_amd import _lib
 
-    assert lib.km_abi_version() == _lib.ABI_VERSION == 2
+    assert lib.km_abi_version() == _lib.ABI_VERSION == 3
     assert lib.km_max_samples() >= 20000
     assert lib.km_tile_count(0) >= 2 and lib.km_tile_count(1) >= 2
     assert lib.km_tile_count(7) == 0
@@ -268,6 +268,39 @@ def test_table_entry_points_reject_bad_tables(lib):
             _lib.KM_E_INVALID
     big = _lib.KmTtable(n_h=1 << 30, dh=1.0, t=p, r2=p)
     assert lib.kirchhoff_migrate_table(ctypes.byref(t), ctypes.byref(g), ctypes.byref(big), p, 0, -1, None) == \
+        _lib.KM_E_UNSUPPORTED
+
+
+def test_ltable_entry_points_reject_bad_tables(lib):
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib)
+    p = ctypes.c_void_p(0x1000)
+
+    def lt(**over):
+        f = dict(n_h=4, dh=10.0, n_gx=3, n_gy=2, gx0=0.0, gy0=0.0, gdx=100.0, gdy=100.0, t=p, r2=p)
+        f.update(over)
+        return _lib.KmLtable(**f)
+
+    for tab, msg in [(None, b"NULL"), (lt(n_gx=0), b"n_gx and n_gy"), (lt(n_gy=-1), b"n_gx and n_gy"),
+                     (lt(gx0=float("nan")), b"gx0 and gy0"), (lt(gy0=float("inf")), b"gx0 and gy0"),
+                     (lt(gdx=0.0), b"gdx"), (lt(gdy=-5.0), b"gdx"), (lt(gdx=float("inf")), b"gdx"),
+                     (lt(n_h=1), b"n_h"), (lt(dh=0.0), b"dh"), (lt(t=None), b"non-NULL"),
+                     (lt(r2=ctypes.c_void_p(0x1002)), b"misaligned")]:
+        ref = ctypes.byref(tab) if tab is not None else None
+        assert lib.kirchhoff_migrate_ltable(ctypes.byref(t), ctypes.byref(g), ref, p, 0, -1, None) == \
+            _lib.KM_E_INVALID
+        assert msg in lib.km_last_error()
+        assert lib.kirchhoff_demigrate_ltable(p, ctypes.byref(g), ref, ctypes.byref(t), 0, -1, None) == \
+            _lib.KM_E_INVALID
+        assert msg in lib.km_last_error()
+    # the spacing of an axis with one node is not read
+    one = lt(n_gx=1, n_gy=1, gdx=0.0, gdy=float("nan"), n_h=1)
+    assert lib.kirchhoff_migrate_ltable(ctypes.byref(t), ctypes.byref(g), ctypes.byref(one), p, 0, -1, None) == \
+        _lib.KM_E_INVALID
+    assert b"n_h" in lib.km_last_error()
+    big = lt(n_gx=1 << 12, n_gy=1 << 12, n_h=64)
+    assert lib.kirchhoff_migrate_ltable(ctypes.byref(t), ctypes.byref(g), ctypes.byref(big), p, 0, -1, None) == \
         _lib.KM_E_UNSUPPORTED
 
 
