@@ -87,7 +87,7 @@ def main():
                          "hardware byte counters)")
     ap.add_argument("--workload", default="survey3d",
                     choices=["survey3d", "survey3d_bf16", "survey3d_f16", "survey3d_ext", "line2d_vz", "batch", "cig",
-                             "filter", "table", "aa"],
+                             "filter", "table", "ltable", "aa"],
                     help="survey3d (default) is the headline; the others print their own JSON line")
     args = ap.parse_args()
     if args.gpus != 1:

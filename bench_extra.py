@@ -20,6 +20,9 @@ aa: the 3D survey migrated and demigrated with the anti-alias triangle filter:
 table: the 3D survey migrated and demigrated with curved-ray traveltime
     tables (v = 1500 + 0.5 z, h every 10 m) instead of the RMS double square
     root: throughput of both operators next to the table-gather rate.
+ltable: the same with laterally varying tables (v0 from 1420 to 1580 m/s
+    across the image, curved rays under each node of a 9 x 9 grid at 400 m):
+    throughput of both operators next to the table-gather rate.
 filter: the rho pre-filter (anti-causal derivative, 65 taps) forward and
     transposed over the 3D survey's 200 000 x 1500 traces: HBM bandwidth
     against 8 TB/s and the FP64 oracle timed on sampled traces.
@@ -249,6 +252,41 @@ def _table(steps, warmup, dev):
                                       "frac": round(valu / PEAK_VALU_LANE_OPS, 4)}}}
 
 
+def _ltable(steps, warmup, dev):
+    p = survey.make_survey3d(seed=2, device=dev)
+    pl = survey.with_survey3d_lateral_tables(p, dh=10.0)
+    dp = ops.to_device(pl, dev)
+    n_ap, _ = ops.count(dp, aperture_only=True)
+    img = torch.empty(dp.image_shape, device=dev)
+    out = torch.empty((dp.n_traces, dp.n_t), device=dev)
+    ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
+    ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
+    # Per pair 16 float32 table reads (64 bytes: two rows of each of the four
+    # nodes around the column, per leg), through the L2 (the 81 node tables
+    # are 45 MB in all; a workgroup's depth chunk touches four nodes' rows).
+    # VALU: per node and leg one float32 difference, two widenings and one
+    # float64 FMA (16 per leg), the x and y steps (3 float64 differences and 3
+    # FMAs per leg), then sum + scale + 2 clamps (4), index, fraction and its
+    # narrowing (3), row address, interpolation (2), accumulate (1) = 54.
+    c_k = 54
+    table_bytes = 64
+    dom = max(ms_m, ms_d)
+    gather = n_ap * table_bytes / (dom * 1e-3)
+    valu = n_ap * c_k / (dom * 1e-3)
+    return {"workload": "ltable", "metric": "G contributions/s (migrate, demigrate; laterally varying tables)",
+            "pairs_in_aperture": n_ap, "table_shape": list(pl.ttab.shape), "node_grid": list(pl.tgrid),
+            "ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
+            "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
+            "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
+            "roofline": {"bound": "l2_gather", "achieved": round(gather / 1e12, 3),
+                         "peak": round(PEAK_L2_BYTES / 1e12, 3), "unit": "TB/s",
+                         "frac": round(gather / PEAK_L2_BYTES, 4), "bytes_per_pair": table_bytes,
+                         "kernel": "migrate" if ms_m >= ms_d else "demigrate",
+                         "co_bound": {"resource": "VALU", "ops_per_pair": c_k, "achieved": round(valu / 1e12, 3),
+                                      "peak": round(PEAK_VALU_LANE_OPS / 1e12, 3), "unit": "T lane-ops/s",
+                                      "frac": round(valu / PEAK_VALU_LANE_OPS, 4)}}}
+
+
 def _aa(steps, warmup, dev):
     """The 3D survey with the anti-alias triangle filter (dip over the 12.5 m
     image spacing in x and y, half-widths up to 8 samples)."""
@@ -338,6 +376,8 @@ def run(workload, steps, warmup, dev):
         return _aa(steps, warmup, dev)
     if workload == "table":
         return _table(steps, warmup, dev)
+    if workload == "ltable":
+        return _ltable(steps, warmup, dev)
     if workload == "filter":
         return _filter(steps, warmup, dev)
     if workload == "cig":

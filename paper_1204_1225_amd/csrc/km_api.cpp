@@ -340,11 +340,13 @@ enum { KIND_DSR = 0, KIND_TABLE = 1, KIND_AA = 2, KIND_LTABLE = 3 };
 // trace quad, and 16 waves x 8 slots x 3 quads with table traveltimes, whose
 // table gathers favour more traces per workgroup).  With the anti-alias
 // filter: migrate 16 waves x 4 column groups x 8 slots (the largest trace
-// blocks), demigrate 8 waves x 4 slots x 1 quad.
+// blocks), demigrate 8 waves x 4 slots x 1 quad.  With laterally varying
+// tables (16 reads per pair): migrate 4 waves x 3 column groups x 16 slots,
+// demigrate 8 waves x 4 slots x 1 quad.
 int default_tile(int op, int kind) {
-    if (op == 0) return kind == KIND_AA ? 1 : 2;
-    if (kind == KIND_AA) return 3;
-    return kind == KIND_TABLE || kind == KIND_LTABLE ? 1 : 3;
+    if (op == 0) return kind == KIND_AA ? 1 : kind == KIND_LTABLE ? 3 : 2;
+    if (kind == KIND_AA || kind == KIND_LTABLE) return 3;
+    return kind == KIND_TABLE ? 1 : 3;
 }
 
 // The caller's tile, else the tuned tile of this problem's class, else the default.
@@ -399,6 +401,8 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         P.s2 = nullptr;
         P.r2 = tab->r2;
         P.weight = KM_W_UNIT;
+        // < 2^32: checked with the table
+        P.ttab_bytes = static_cast<uint32_t>(int64_t{4} * tab->n_h * g->nz * (lat ? int64_t{lat->n_gx} * lat->n_gy : 1));
     }
     if (tab && lat) {
         const int32_t node = tab->n_h * g->nz;  // < 2^31: checked with the whole table
@@ -496,8 +500,8 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
     if (!tab) return fail(KM_E_INVALID, "%s: table is NULL", who);
     if (tab->n_h < 2) return fail(KM_E_INVALID, "%s: n_h < 2", who);
     if (!(tab->dh > 0.0) || !std::isfinite(tab->dh)) return fail(KM_E_INVALID, "%s: dh must be finite and > 0", who);
-    if (grid && static_cast<int64_t>(tab->n_h) * grid->nz >= (int64_t(1) << 31))
-        return fail(KM_E_UNSUPPORTED, "%s: n_h * nz must be < 2^31", who);
+    if (grid && static_cast<int64_t>(tab->n_h) * grid->nz >= (int64_t(1) << 30))
+        return fail(KM_E_UNSUPPORTED, "%s: n_h * nz must be < 2^30", who);
     if (grid && !grid_empty(grid)) {
         if (!tab->t || !tab->r2) return fail(KM_E_INVALID, "%s: t and r2 must be non-NULL", who);
         if (!aligned(tab->t, 4) || !aligned(tab->r2, 4)) return fail(KM_E_INVALID, "%s: t, r2 misaligned", who);
@@ -506,7 +510,8 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
 }
 
 // Laterally varying tables: the node grid, then the table as check_table
-// sees it (the node tables together must stay below 2^31 floats).
+// sees it (the node tables together must stay below 2^30 floats: the kernels
+// read them through one buffer of at most 4 GiB).
 km_status check_ltable(const km_ltable* lt, const km_grid* grid, const char* who, km_ttable* tab, Lateral* lat) {
     if (!lt) return fail(KM_E_INVALID, "%s: table is NULL", who);
     if (lt->n_gx < 1 || lt->n_gy < 1) return fail(KM_E_INVALID, "%s: n_gx and n_gy must be >= 1", who);
@@ -518,8 +523,8 @@ km_status check_ltable(const km_ltable* lt, const km_grid* grid, const char* who
     *tab = km_ttable{lt->n_h, lt->dh, lt->t, lt->r2, lt->time_precision};
     const km_status st = check_table(tab, grid, who);
     if (st != KM_OK) return st;
-    if (grid && static_cast<int64_t>(lt->n_gx) * lt->n_gy * lt->n_h * grid->nz >= (int64_t(1) << 31))
-        return fail(KM_E_UNSUPPORTED, "%s: n_gx * n_gy * n_h * nz must be < 2^31", who);
+    if (grid && static_cast<int64_t>(lt->n_gx) * lt->n_gy * lt->n_h * grid->nz >= (int64_t(1) << 30))
+        return fail(KM_E_UNSUPPORTED, "%s: n_gx * n_gy * n_h * nz must be < 2^30", who);
     *lat = Lateral{lt->n_gx, lt->n_gy, lt->gx0, lt->gy0, lt->n_gx > 1 ? lt->gdx : 1.0, lt->n_gy > 1 ? lt->gdy : 1.0};
     return KM_OK;
 }

@@ -160,14 +160,6 @@ __device__ __forceinline__ void dem_slot_aa(const PairAA& p, float x, double* ro
     atomicAdd(row + i + L + 1, b * be);
 }
 
-// Raw buffer resources (gfx9 family: no format conversion, no swizzle).
-// Out-of-range offsets read 0.
-constexpr int kRawBufferWord3 = 0x00020000;
-
-__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void* p, uint32_t bytes) {
-    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRawBufferWord3);
-}
-
 // Image values (this lane's depth slots) and coordinates of one swept column.
 template <int KS>
 struct Column {

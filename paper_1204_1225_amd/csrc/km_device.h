@@ -81,7 +81,16 @@ struct Params {
     int32_t n_gx, n_gy;
     int32_t ldx, ldy;    // floats from a node's table to its +x / +y neighbour's (0 on an axis of one node)
     double gx0, gy0, gdx, gdy;
+    uint32_t ttab_bytes; // size of ttab (every node), < 2^32
 };
+
+// Raw buffer resources (gfx9 family: no format conversion, no swizzle).
+// Out-of-range offsets read 0.
+constexpr int kRawBufferWord3 = 0x00020000;
+
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t raw_buffer(const void* p, uint32_t bytes) {
+    return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(p), 0, static_cast<int>(bytes), kRawBufferWord3);
+}
 
 // Traveltime kinds of the kernels: the per-depth double-square-root form
 // (t0sq, s2) or a one-way time table T(h, z) interpolated linearly in h.
@@ -304,8 +313,18 @@ __device__ __forceinline__ TLegX table_leg_ext(const Params& P, double H) {
     return L;
 }
 
+// Table reads go through a raw buffer over the tables: a read's row, node and
+// depth displacements are scalar byte offsets, so a leg costs one vector
+// address (its row plus the lane's depth) however many values it reads.
+// Every read the kernels make lies inside the tables (the buffer's range check
+// would return 0 past them).
+__device__ __forceinline__ float table_read(const Params& P, int vbyte, int sbyte) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(raw_buffer(P.ttab, P.ttab_bytes), vbyte, sbyte, 0));
+}
+
 __device__ __forceinline__ double table_time_ext(const Params& P, TLegX L, int iz) {
-    const double a = P.ttab[L.off + iz], b = P.ttab[L.off + P.nz + iz];
+    const int vo = (L.off + iz) * 4;
+    const double a = table_read(P, vo, 0), b = table_read(P, vo, 4 * P.nz);
     return fma(L.f, b - a, a);
 }
 
@@ -314,7 +333,8 @@ __device__ __forceinline__ double table_time_ext(const Params& P, TLegX L, int i
 // keeps the table's own precision (float32 rounding of the time in seconds
 // and again in samples would cost about 1e-5 of a band-limited result).
 __device__ __forceinline__ double table_time(const Params& P, TLeg L, int iz) {
-    const float a = P.ttab[L.off + iz], b = P.ttab[L.off + P.nz + iz];
+    const int vo = (L.off + iz) * 4;
+    const float a = table_read(P, vo, 0), b = table_read(P, vo, 4 * P.nz);
     return fma(static_cast<double>(L.f), static_cast<double>(b - a), static_cast<double>(a));
 }
 
@@ -356,11 +376,13 @@ __device__ __forceinline__ LCol lateral_col(const Params& P, float px, float py)
 // table_time on the four nodes around the column, then in x, then in y, each
 // a + f (b - a) in float64 (equal node tables give table_time exactly).
 __device__ __forceinline__ double ltable_time(const Params& P, TLeg L, LCol C, int iz) {
-    const float* t = P.ttab + (C.off + L.off + iz);
-    const int nz = P.nz, dx = P.ldx, dy = P.ldy;
+    const int vo = (C.off + L.off + iz) * 4;
+    const int nz = 4 * P.nz, dx = 4 * P.ldx, dy = 4 * P.ldy;  // byte offsets (scalar)
     const double fh = L.f;
-    const float a00 = t[0], b00 = t[nz], a10 = t[dx], b10 = t[dx + nz];
-    const float a01 = t[dy], b01 = t[dy + nz], a11 = t[dx + dy], b11 = t[dx + dy + nz];
+    const float a00 = table_read(P, vo, 0), b00 = table_read(P, vo, nz);
+    const float a10 = table_read(P, vo, dx), b10 = table_read(P, vo, dx + nz);
+    const float a01 = table_read(P, vo, dy), b01 = table_read(P, vo, dy + nz);
+    const float a11 = table_read(P, vo, dx + dy), b11 = table_read(P, vo, dx + dy + nz);
     const double t00 = fma(fh, static_cast<double>(b00 - a00), static_cast<double>(a00));
     const double t10 = fma(fh, static_cast<double>(b10 - a10), static_cast<double>(a10));
     const double t01 = fma(fh, static_cast<double>(b01 - a01), static_cast<double>(a01));
@@ -372,11 +394,13 @@ __device__ __forceinline__ double ltable_time(const Params& P, TLeg L, LCol C, i
 
 // ltable_time with an extended leg (the h fraction and the differences in float64).
 __device__ __forceinline__ double ltable_time_ext(const Params& P, TLegX L, LCol C, int iz) {
-    const float* t = P.ttab + (C.off + L.off + iz);
-    const int nz = P.nz, dx = P.ldx, dy = P.ldy;
+    const int vo = (C.off + L.off + iz) * 4;
+    const int nz = 4 * P.nz, dx = 4 * P.ldx, dy = 4 * P.ldy;  // byte offsets (scalar)
     const double fh = L.f;
-    const double a00 = t[0], b00 = t[nz], a10 = t[dx], b10 = t[dx + nz];
-    const double a01 = t[dy], b01 = t[dy + nz], a11 = t[dx + dy], b11 = t[dx + dy + nz];
+    const double a00 = table_read(P, vo, 0), b00 = table_read(P, vo, nz);
+    const double a10 = table_read(P, vo, dx), b10 = table_read(P, vo, dx + nz);
+    const double a01 = table_read(P, vo, dy), b01 = table_read(P, vo, dy + nz);
+    const double a11 = table_read(P, vo, dx + dy), b11 = table_read(P, vo, dx + dy + nz);
     const double t00 = fma(fh, b00 - a00, a00), t10 = fma(fh, b10 - a10, a10);
     const double t01 = fma(fh, b01 - a01, a01), t11 = fma(fh, b11 - a11, a11);
     const double fx = C.fx, fy = C.fy;
