@@ -48,9 +48,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "2b0d50ba83511fb47b80ee26aa83e1eef9c3fa424b69e05c2cde6442535472e7",
-    "migrate": 9.0419e10,
-    "demigrate": 3.1404e12,
+    "sources_sha256": "87a069852197a47bf0b1275b227c8be4ead9f657929bd76372e3f7ac1196fbfb",
+    "migrate": 9.1587e10,
+    "demigrate": 3.0076e12,
 }
 
 
