@@ -10,7 +10,8 @@ problem (src, rec, bin, n_t, dt, t_first, x, y, t0sq, s2, r2, weight,
 n_bins, and optionally a one-way traveltime table ttab [n_h][nz] with
 spacing tdh, which replaces the t0sq / s2 form, or with tgrid = (gx0, gy0,
 gdx, gdy) a laterally varying table ttab [n_gy][n_gx][n_h][nz] on the node
-grid (gx0 + i gdx, gy0 + j gdy), and optionally aa = (dx, dy, max
+grid (gx0 + i gdx, gy0 + j gdy), with optionally tamp, one-way amplitudes of
+the same layout (W = A_s A_r instead of 1), and optionally aa = (dx, dy, max
 half-width) for the anti-alias triangle filter) and, where samples are
 needed, a float64 data array [n_traces, n_t] (default: the problem's own data
 widened to float64).
@@ -71,7 +72,7 @@ class _Problem(ctypes.Structure):
         ("n_h", ctypes.c_int32), ("dh", ctypes.c_double), ("ttab", ctypes.c_void_p),
         ("aa_dx", ctypes.c_double), ("aa_dy", ctypes.c_double), ("aa_max", ctypes.c_int32),
         ("n_gx", ctypes.c_int32), ("n_gy", ctypes.c_int32), ("gx0", ctypes.c_double), ("gy0", ctypes.c_double),
-        ("gdx", ctypes.c_double), ("gdy", ctypes.c_double),
+        ("gdx", ctypes.c_double), ("gdy", ctypes.c_double), ("tamp", ctypes.c_void_p),
     ]
 
 
@@ -138,6 +139,11 @@ class _Bound:
             r2=k["r2"].ctypes.data, weight=int(p.weight),
             n_h=k["ttab"].shape[-2] if "ttab" in k else 0, dh=float(getattr(p, "tdh", 0.0) or 0.0),
             ttab=k["ttab"].ctypes.data if "ttab" in k else None)
+        tamp = getattr(p, "tamp", None)
+        if tamp is not None:
+            self.keep["tamp"] = _arr(tamp, np.float32)
+            assert ttab is not None and self.keep["tamp"].shape == self.keep["ttab"].shape
+            self.s.tamp = self.keep["tamp"].ctypes.data
         if n_gx:
             self.s.n_gx, self.s.n_gy = n_gx, n_gy
             self.s.gx0, self.s.gy0, self.s.gdx, self.s.gdy = (float(v) for v in tgrid)

@@ -60,6 +60,10 @@
  *    [0, n_gx - 1] (beyond the grid the edge nodes hold); a single node along
  *    an axis takes no interpolation there.  With every node holding the same
  *    table this is the laterally invariant table exactly (b - a = 0).
+ *  - Amplitudes for table traveltimes (tamp != NULL, same layout as ttab): a
+ *    one-way amplitude A per leg, interpolated exactly as the time is, and
+ *    W = A_s A_r in place of W = 1.  (For constant velocity A = t0 / T^2 gives
+ *    the cos cos / (T_s T_r) weight of the square-root form.)
  *
  * Build: gcc -O2 -fopenmp -ffp-contract=off -shared -fPIC (no fast-math).
  */
@@ -97,6 +101,7 @@ typedef struct {
     int32_t n_gx, n_gy;    /* lateral table nodes (0: one table for every column) */
     double gx0, gy0;       /* position of node (0, 0) */
     double gdx, gdy;       /* node spacing (> 0 along an axis with more than one node) */
+    const float* tamp;     /* table traveltimes: one-way amplitudes, same layout as ttab, or NULL (W = 1) */
 } ko_problem;
 
 /* Linear interpolation in h of the one-way time table at depth iz. */
@@ -175,16 +180,20 @@ static int ko_pair_p(const ko_problem* P, int64_t j, int ix, int iy, int iz, dou
     if (!ko_in_aperture(px, py, sx, sy, rx, ry, P->r2[iz])) return 0;
     double hs2 = ((double)px - sx) * ((double)px - sx) + ((double)py - sy) * ((double)py - sy);
     double hr2 = ((double)px - rx) * ((double)px - rx) + ((double)py - ry) * ((double)py - ry);
-    if (P->ttab && P->n_gx > 0) {
-        const double T = ko_lateral_time(P, px, py, sqrt(hs2), iz) + ko_lateral_time(P, px, py, sqrt(hr2), iz);
-        *u = (T - P->t_first) / P->dt;
-        *w = 1.0;
-        return 1;
-    }
     if (P->ttab) {
-        const double T = ko_table_time(P, sqrt(hs2), iz) + ko_table_time(P, sqrt(hr2), iz);
+        const double hs = sqrt(hs2), hr = sqrt(hr2);
+        const int lat = P->n_gx > 0;
+        const double T = lat ? ko_lateral_time(P, px, py, hs, iz) + ko_lateral_time(P, px, py, hr, iz)
+                             : ko_table_time(P, hs, iz) + ko_table_time(P, hr, iz);
         *u = (T - P->t_first) / P->dt;
         *w = 1.0;
+        if (P->tamp) {
+            /* the amplitude tables, interpolated as the time tables are */
+            ko_problem A = *P;
+            A.ttab = P->tamp;
+            *w = lat ? ko_lateral_time(&A, px, py, hs, iz) * ko_lateral_time(&A, px, py, hr, iz)
+                     : ko_table_time(&A, hs, iz) * ko_table_time(&A, hr, iz);
+        }
         return 1;
     }
     double a_s = P->t0sq[iz] + P->s2[iz] * hs2;
@@ -295,6 +304,7 @@ static int ko_check(const ko_problem* P)
     if (!(P->dt > 0.0)) return 1;
     if (P->ttab && (P->n_h < 2 || !(P->dh > 0.0) || P->weight != 0)) return 1;
     if (P->n_gx < 0 || P->n_gy < 0 || (P->n_gx > 0) != (P->n_gy > 0)) return 1;
+    if (P->tamp && !P->ttab) return 1;
     if (P->n_gx > 0 && (!P->ttab || (P->n_gx > 1 && !(P->gdx > 0.0)) || (P->n_gy > 1 && !(P->gdy > 0.0))))
         return 1;
     if (P->aa_max < 0 || (P->aa_max > 0 && (P->ttab || !(P->aa_dx >= 0.0) || !(P->aa_dy >= 0.0)))) return 1;

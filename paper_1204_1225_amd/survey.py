@@ -79,6 +79,8 @@ class Problem:
     # laterally varying tables: (gx0, gy0, gdx, gdy) of the node grid X_i = gx0 + i gdx,
     # Y_j = gy0 + j gdy; ttab is then [n_gy][n_gx][n_h][nz], one table per node
     tgrid: Optional[tuple] = None
+    # optional one-way amplitudes of the table traveltimes (same layout as ttab): W = A_s A_r instead of 1
+    tamp: Optional[np.ndarray] = None
     # optional anti-alias triangle filter: (dx, dy, largest half-width in samples)
     aa: Optional[tuple] = None
 
@@ -169,17 +171,32 @@ def curved_ray_table(z, v0: float, k: float, dh: float, n_h: int) -> np.ndarray:
     return curved_ray_time(h[:, None], np.asarray(z, np.float64)[None, :], v0, k).astype(np.float32)
 
 
-def with_curved_ray_table(problem: "Problem", dh: float = 10.0, n_h: Optional[int] = None) -> "Problem":
+def curved_ray_amplitude_table(z, v0: float, k: float, dh: float, n_h: int) -> np.ndarray:
+    """amp[ih][iz] = t0 / T^2 with T = curved_ray_time(ih dh, z[iz]) and t0 =
+    T(0, z[iz]) (cos / T of the leg, cos = t0 / T), rounded once to float32.
+    For constant velocity the product over the two legs is the square-root
+    form's cos cos / (T_s T_r) weight exactly."""
+    h = dh * np.arange(n_h, dtype=np.float64)
+    zz = np.asarray(z, np.float64)[None, :]
+    T = curved_ray_time(h[:, None], zz, v0, k)
+    t0 = curved_ray_time(0.0, zz, v0, k)
+    return (t0 / (T * T)).astype(np.float32)
+
+
+def with_curved_ray_table(problem: "Problem", dh: float = 10.0, n_h: Optional[int] = None,
+                          amplitude: bool = False) -> "Problem":
     """The problem with its traveltimes replaced by the curved-ray table of its
     linear (or constant) velocity model, covering every in-aperture leg;
-    weight becomes W = 1."""
+    weight becomes W = 1, or with amplitude=True the product of the legs'
+    curved_ray_amplitude_table values."""
     vel = problem.velocity
     v0, k = (float(vel[1]), 0.0) if vel[0] == "const" else (float(vel[1]), float(vel[2]))
     if n_h is None:
         hmax = float(np.sqrt(np.max(problem.r2.astype(np.float64))))
         n_h = int(np.ceil(hmax / dh)) + 2
     tab = curved_ray_table(problem.z, v0, k, dh, n_h)
-    return dataclasses.replace(problem, ttab=tab, tdh=float(dh), weight=WEIGHT_UNIT)
+    amp = curved_ray_amplitude_table(problem.z, v0, k, dh, n_h) if amplitude else None
+    return dataclasses.replace(problem, ttab=tab, tdh=float(dh), tamp=amp, weight=WEIGHT_UNIT)
 
 
 def lateral_v0(v0: float, gx: float, gy: float, xc: float, yc: float):
@@ -189,24 +206,31 @@ def lateral_v0(v0: float, gx: float, gy: float, xc: float, yc: float):
 
 
 def with_lateral_tables(problem: "Problem", v0_at, k: float, gx0: float, gy0: float, gdx: float, gdy: float,
-                        n_gx: int, n_gy: int, dh: float = 10.0, n_h: Optional[int] = None) -> "Problem":
+                        n_gx: int, n_gy: int, dh: float = 10.0, n_h: Optional[int] = None,
+                        amplitude: bool = False) -> "Problem":
     """The problem with laterally varying table traveltimes: below node
     (X_i, Y_j) = (gx0 + i gdx, gy0 + j gdy) the medium is taken as the depth-only
     v(z) = v0_at(X_i, Y_j) + k z, and the node's table holds its curved-ray
     times, ttab[j][i][ih][iz] = curved_ray_time(ih dh, z[iz]; v0_at(X_i, Y_j), k)
     rounded once to float32 (the local one-dimensional medium under each node).
-    n_h covers every in-aperture leg by default; weight becomes W = 1."""
+    n_h covers every in-aperture leg by default; weight becomes W = 1, or with
+    amplitude=True the product of the legs' amplitudes, each node holding its
+    medium's curved_ray_amplitude_table."""
     if n_h is None:
         hmax = float(np.sqrt(np.max(problem.r2.astype(np.float64))))
         n_h = int(np.ceil(hmax / dh)) + 2
     X = gx0 + gdx * np.arange(n_gx, dtype=np.float64)
     Y = gy0 + gdy * np.arange(n_gy, dtype=np.float64)
     tab = np.empty((n_gy, n_gx, n_h, problem.nz), dtype=np.float32)
+    amp = np.empty_like(tab) if amplitude else None
     for j in range(n_gy):
         for i in range(n_gx):
-            tab[j, i] = curved_ray_table(problem.z, float(v0_at(X[i], Y[j])), k, dh, n_h)
-    return dataclasses.replace(problem, ttab=tab, tdh=float(dh), tgrid=(float(gx0), float(gy0), float(gdx),
-                                                                        float(gdy)), weight=WEIGHT_UNIT)
+            v0 = float(v0_at(X[i], Y[j]))
+            tab[j, i] = curved_ray_table(problem.z, v0, k, dh, n_h)
+            if amplitude:
+                amp[j, i] = curved_ray_amplitude_table(problem.z, v0, k, dh, n_h)
+    return dataclasses.replace(problem, ttab=tab, tdh=float(dh), tamp=amp,
+                               tgrid=(float(gx0), float(gy0), float(gdx), float(gdy)), weight=WEIGHT_UNIT)
 
 
 SURVEY3D_LATERAL_V0 = (1500.0, 0.05, -0.04, 2500.0, 2500.0)  # v0, d v0 / dx, d v0 / dy, centre x, y
