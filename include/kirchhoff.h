@@ -171,17 +171,22 @@ typedef struct km_ttable {
     int32_t time_precision; /* km_time_precision: KM_TIME_EXTENDED takes h = sqrt(h^2), h / dh and the
                                fraction in float64 from the float64 h^2 (the interpolated times and their
                                sum are float64 in both) */
+    const float* amp; /* device float [n_h][nz] or NULL: one-way amplitude A at h = ih * dh, depth iz,
+                         interpolated as the time is (float32); the pair's weight is W = A_s A_r
+                         (NULL: W = 1).  For constant velocity A = t0 / T^2 gives the square-root
+                         operators' KM_W_COSCOS_OVER_TT weight. */
 } km_ttable;
 
-/* As kirchhoff_migrate with table traveltimes and W = 1.  KM_E_INVALID also
- * for a NULL table, n_h < 2, dh not finite or <= 0, NULL or misaligned t / r2;
+/* As kirchhoff_migrate with table traveltimes and W = 1 (or the amplitude
+ * tables' A_s A_r).  KM_E_INVALID also for a NULL table, n_h < 2, dh not
+ * finite or <= 0, NULL or misaligned t / r2, misaligned amp;
  * KM_E_UNSUPPORTED for n_h * nz >= 2^30 (the kernels read the table
  * through one buffer of at most 4 GiB). */
 km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, const km_ttable* table, float* image,
                                   int32_t accumulate, int32_t tile, void* stream);
 
-/* As kirchhoff_demigrate with table traveltimes and W = 1: the exact transpose
- * of kirchhoff_migrate_table for the same inputs. */
+/* As kirchhoff_demigrate with table traveltimes and the same weight: the
+ * exact transpose of kirchhoff_migrate_table for the same inputs. */
 km_status kirchhoff_demigrate_table(const float* image, const km_grid* grid, const km_ttable* table,
                                     const km_traces* out, int32_t accumulate, int32_t tile, void* stream);
 
@@ -208,9 +213,12 @@ typedef struct km_ltable {
                          h = ih * dh and depth index iz */
     const float* r2;  /* device float [nz]: aperture, as km_traveltime.r2 */
     int32_t time_precision; /* km_time_precision, as in km_ttable */
+    const float* amp; /* device float [n_gy][n_gx][n_h][nz] or NULL: one-way amplitudes, interpolated as
+                         the times are (float32); W = A_s A_r (NULL: W = 1) */
 } km_ltable;
 
-/* As kirchhoff_migrate_table with laterally varying tables (W = 1).
+/* As kirchhoff_migrate_table with laterally varying tables (W = 1, or the
+ * amplitude tables' A_s A_r).
  * KM_E_INVALID also for a NULL table, n_gx or n_gy < 1, gx0 / gy0 not
  * finite, gdx (gdy) not finite or <= 0 with n_gx (n_gy) > 1, and the
  * km_ttable conditions on n_h, dh, t and r2; KM_E_UNSUPPORTED for
@@ -219,8 +227,8 @@ typedef struct km_ltable {
 km_status kirchhoff_migrate_ltable(const km_traces* traces, const km_grid* grid, const km_ltable* table,
                                    float* image, int32_t accumulate, int32_t tile, void* stream);
 
-/* As kirchhoff_demigrate with laterally varying tables and W = 1: the exact
- * transpose of kirchhoff_migrate_ltable for the same inputs. */
+/* As kirchhoff_demigrate with laterally varying tables and the same weight:
+ * the exact transpose of kirchhoff_migrate_ltable for the same inputs. */
 km_status kirchhoff_demigrate_ltable(const float* image, const km_grid* grid, const km_ltable* table,
                                      const km_traces* out, int32_t accumulate, int32_t tile, void* stream);
 

@@ -39,12 +39,12 @@ class KmTraveltime(ctypes.Structure):
 
 
 class KmTtable(ctypes.Structure):
-    _fields_ = [("n_h", _i32), ("dh", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32)]
+    _fields_ = [("n_h", _i32), ("dh", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32), ("amp", _vp)]
 
 
 class KmLtable(ctypes.Structure):
     _fields_ = [("n_h", _i32), ("dh", _f64), ("n_gx", _i32), ("n_gy", _i32), ("gx0", _f64), ("gy0", _f64),
-                ("gdx", _f64), ("gdy", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32)]
+                ("gdx", _f64), ("gdy", _f64), ("t", _vp), ("r2", _vp), ("time_precision", _i32), ("amp", _vp)]
 
 
 class KmAntialias(ctypes.Structure):

@@ -400,6 +400,7 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         P.t0sq = nullptr;
         P.s2 = nullptr;
         P.r2 = tab->r2;
+        P.tamp = tab->amp;
         P.weight = KM_W_UNIT;
         // < 2^32: checked with the table
         P.ttab_bytes = static_cast<uint32_t>(int64_t{4} * tab->n_h * g->nz * (lat ? int64_t{lat->n_gx} * lat->n_gy : 1));
@@ -504,7 +505,8 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
         return fail(KM_E_UNSUPPORTED, "%s: n_h * nz must be < 2^30", who);
     if (grid && !grid_empty(grid)) {
         if (!tab->t || !tab->r2) return fail(KM_E_INVALID, "%s: t and r2 must be non-NULL", who);
-        if (!aligned(tab->t, 4) || !aligned(tab->r2, 4)) return fail(KM_E_INVALID, "%s: t, r2 misaligned", who);
+        if (!aligned(tab->t, 4) || !aligned(tab->r2, 4) || !aligned(tab->amp, 4))
+            return fail(KM_E_INVALID, "%s: t, r2 or amp misaligned", who);
     }
     return KM_OK;
 }
@@ -520,7 +522,7 @@ km_status check_ltable(const km_ltable* lt, const km_grid* grid, const char* who
     if ((lt->n_gx > 1 && !(lt->gdx > 0.0 && std::isfinite(lt->gdx))) ||
         (lt->n_gy > 1 && !(lt->gdy > 0.0 && std::isfinite(lt->gdy))))
         return fail(KM_E_INVALID, "%s: gdx (gdy) must be finite and > 0 when n_gx (n_gy) > 1", who);
-    *tab = km_ttable{lt->n_h, lt->dh, lt->t, lt->r2, lt->time_precision};
+    *tab = km_ttable{lt->n_h, lt->dh, lt->t, lt->r2, lt->time_precision, lt->amp};
     const km_status st = check_table(tab, grid, who);
     if (st != KM_OK) return st;
     if (grid && static_cast<int64_t>(lt->n_gx) * lt->n_gy * lt->n_h * grid->nz >= (int64_t(1) << 30))

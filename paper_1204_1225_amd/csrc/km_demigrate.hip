@@ -103,22 +103,22 @@ __device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TL
                                                    bool act1) {
     if (act0) {
         const PairX p0 = eval_pair_table_ext<TF, LAT>(P, Ls, Lr, iz0, wlo, whi, C);
-        const double q0 = static_cast<double>(x0);
+        const double q0 = static_cast<double>(x0 * p0.r);
         const double b0 = p0.fd * q0;
         atomicAdd(row + p0.i, q0 - b0);
         atomicAdd(row + p0.i + 1, b0);
     }
     if (act1) {
         const PairX p1 = eval_pair_table_ext<TF, LAT>(P, Ls, Lr, iz1, wlo, whi, C);
-        const double q1 = static_cast<double>(x1);
+        const double q1 = static_cast<double>(x1 * p1.r);
         const double b1 = p1.fd * q1;
         atomicAdd(row + p1.i, q1 - b1);
         atomicAdd(row + p1.i + 1, b1);
     }
 }
 
-// dem_masked with table traveltimes (W = 1); iz0, iz1 are the lane's depths
-// of the two slots, clamped into the table.  LAT: laterally varying tables, C
+// dem_masked with table traveltimes (W = A_s A_r with amplitude tables, else
+// 1); iz0, iz1 are the lane's depths of the two slots, clamped into the table.  LAT: laterally varying tables, C
 // the column on the node grid.
 template <bool TF, bool MASKED, bool LAT>
 __device__ __forceinline__ void dem_pair_table(const Params& P, TLeg Ls, TLeg Lr, LCol C, int iz0, int iz1,
@@ -126,14 +126,16 @@ __device__ __forceinline__ void dem_pair_table(const Params& P, TLeg Ls, TLeg Lr
                                                bool act0, bool act1) {
     if (!MASKED || act0) {
         const Pair p0 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz0, tfo, wlo, whi, C);
-        const float b0 = p0.f * x0;
-        atomicAdd(row + p0.i, static_cast<double>(x0 - b0));
+        const float q0 = x0 * p0.r;  // r = 1 without amplitude tables
+        const float b0 = p0.f * q0;
+        atomicAdd(row + p0.i, static_cast<double>(q0 - b0));
         atomicAdd(row + p0.i + 1, static_cast<double>(b0));
     }
     if (!MASKED || act1) {
         const Pair p1 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz1, tfo, wlo, whi, C);
-        const float b1 = p1.f * x1;
-        atomicAdd(row + p1.i, static_cast<double>(x1 - b1));
+        const float q1 = x1 * p1.r;
+        const float b1 = p1.f * q1;
+        atomicAdd(row + p1.i, static_cast<double>(q1 - b1));
         atomicAdd(row + p1.i + 1, static_cast<double>(b1));
     }
 }

@@ -82,6 +82,9 @@ struct Params {
     int32_t ldx, ldy;    // floats from a node's table to its +x / +y neighbour's (0 on an axis of one node)
     double gx0, gy0, gdx, gdy;
     uint32_t ttab_bytes; // size of ttab (every node), < 2^32
+    // one-way amplitudes of the table kinds (same layout and size as ttab), or
+    // NULL: W = A_s A_r instead of 1
+    const float* tamp;
 };
 
 // Raw buffer resources (gfx9 family: no format conversion, no swizzle).
@@ -408,6 +411,32 @@ __device__ __forceinline__ double ltable_time_ext(const Params& P, TLegX L, LCol
     return fma(fy, t1 - t0, t0);
 }
 
+// Amplitude of a leg (the table kinds with P.tamp): the amplitude tables
+// interpolated as the times are, in float32 (a weight needs no more).
+__device__ __forceinline__ float amp_read(const Params& P, int vbyte, int sbyte) {
+    return __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(raw_buffer(P.tamp, P.ttab_bytes), vbyte, sbyte, 0));
+}
+
+template <bool LAT>
+__device__ __forceinline__ float table_amp(const Params& P, int off, float fh, LCol C, int iz) {
+    const int nz = 4 * P.nz;
+    if (!LAT) {
+        const int vo = (off + iz) * 4;
+        const float a = amp_read(P, vo, 0), b = amp_read(P, vo, nz);
+        return fmaf(fh, b - a, a);
+    }
+    const int vo = (C.off + off + iz) * 4;
+    const int dx = 4 * P.ldx, dy = 4 * P.ldy;
+    const float a00 = amp_read(P, vo, 0), b00 = amp_read(P, vo, nz);
+    const float a10 = amp_read(P, vo, dx), b10 = amp_read(P, vo, dx + nz);
+    const float a01 = amp_read(P, vo, dy), b01 = amp_read(P, vo, dy + nz);
+    const float a11 = amp_read(P, vo, dx + dy), b11 = amp_read(P, vo, dx + dy + nz);
+    const float t00 = fmaf(fh, b00 - a00, a00), t10 = fmaf(fh, b10 - a10, a10);
+    const float t01 = fmaf(fh, b01 - a01, a01), t11 = fmaf(fh, b11 - a11, a11);
+    const float t0 = fmaf(C.fx, t10 - t00, t00), t1 = fmaf(C.fx, t11 - t01, t01);
+    return fmaf(C.fy, t1 - t0, t0);
+}
+
 // eval_pair_table with extended legs (same clamp as eval_pair_table; the
 // fraction is returned in float32 and float64).
 template <bool TF, bool LAT = false>
@@ -422,12 +451,15 @@ __device__ __forceinline__ PairX eval_pair_table_ext(const Params& P, TLegX Ls, 
     p.fd = w - static_cast<double>(p.i);
     p.f = static_cast<float>(p.fd);
     p.r = 1.0f;
+    if (P.tamp)
+        p.r = table_amp<LAT>(P, Ls.off, static_cast<float>(Ls.f), C, iz) *
+              table_amp<LAT>(P, Lr.off, static_cast<float>(Lr.f), C, iz);
     return p;
 }
 
-// The pair evaluation of eval_pair with table times (iz < nz; W = 1); the
-// clamp bounds are those of clamp_bounds.  LAT: laterally varying tables at
-// column C.
+// The pair evaluation of eval_pair with table times (iz < nz); the clamp
+// bounds are those of clamp_bounds.  LAT: laterally varying tables at column
+// C.  r = A_s A_r with amplitude tables, else 1.
 template <bool TF, bool CLAMP = true, bool LAT = false>
 __device__ __forceinline__ Pair eval_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz, float tf_off, float wlo,
                                                 float whi, LCol C = LCol{0, 0.0f, 0.0f}) {
@@ -440,6 +472,7 @@ __device__ __forceinline__ Pair eval_pair_table(const Params& P, TLeg Ls, TLeg L
     p.i = static_cast<int32_t>(w);
     p.f = static_cast<float>(w - static_cast<double>(p.i));
     p.r = 1.0f;
+    if (P.tamp) p.r = table_amp<LAT>(P, Ls.off, Ls.f, C, iz) * table_amp<LAT>(P, Lr.off, Lr.f, C, iz);
     return p;
 }
 

@@ -124,8 +124,8 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
     acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
 }
 
-// mig_pair with table traveltimes (W = 1): iz0, iz1 are the lane's depths of
-// the two slots, clamped into the table.  LAT: laterally varying tables, C the
+// mig_pair with table traveltimes (W = A_s A_r with amplitude tables, else 1):
+// iz0, iz1 are the lane's depths of the two slots, clamped into the table.  LAT: laterally varying tables, C the
 // lane's column on the node grid.
 template <bool TF, bool MASKED, bool LAT>
 __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr, LCol C, int iz0, int iz1, float hm,
@@ -141,8 +141,9 @@ __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr
         v0 = (hm <= R0) ? v0 : 0.0f;
         v1 = (hm <= R1) ? v1 : 0.0f;
     }
-    acc0 += v0;
-    acc1 += v1;
+    // r = 1 without amplitude tables: the same bits as acc + v
+    acc0 = fmaf(v0, p0.r, acc0);
+    acc1 = fmaf(v1, p1.r, acc1);
 }
 
 // One slot with the extended-precision time (eval_pair_ext): leg lengths in
@@ -176,8 +177,8 @@ __device__ __forceinline__ void mig_pair_table_ext(const Params& P, TLegX Ls, TL
     float v1 = fmaf(p1.f, b1 - a1, a1);
     v0 = (hm <= R0) ? v0 : 0.0f;
     v1 = (hm <= R1) ? v1 : 0.0f;
-    acc0 += v0;
-    acc1 += v1;
+    acc0 = fmaf(v0, p0.r, acc0);
+    acc1 = fmaf(v1, p1.r, acc1);
 }
 
 // Two slots with the anti-alias triangle filter.  row[n] = I2 at window

@@ -55,6 +55,7 @@ class DeviceProblem:
     tdh: float = 0.0
     # laterally varying tables: (gx0, gy0, gdx, gdy) of the node grid; ttab is then [n_gy, n_gx, n_h, nz]
     tgrid: Optional[tuple] = None
+    tamp: Optional[torch.Tensor] = None   # float32, ttab's shape: one-way amplitudes (W = A_s A_r)
     aa: Optional[tuple] = None            # (dx, dy, max half-width): anti-alias triangle filter
     prec: str = "fp32"                    # time arithmetic: "fp32" or "extended" (km_time_precision)
 
@@ -120,7 +121,13 @@ class DeviceProblem:
         assert self.ttab is not None and self.tgrid is None
         assert self.ttab.dim() == 2 and self.ttab.shape[1] == self.nz and self.ttab.is_contiguous()
         return KmTtable(n_h=int(self.ttab.shape[0]), dh=float(self.tdh), t=_ptr(self.ttab), r2=_ptr(self.r2),
-                        time_precision=self.c_prec)
+                        time_precision=self.c_prec, amp=self._c_amp())
+
+    def _c_amp(self):
+        if self.tamp is None:
+            return None
+        assert self.tamp.shape == self.ttab.shape and self.tamp.is_contiguous()
+        return _ptr(self.tamp)
 
     def c_ltable(self) -> KmLtable:
         assert self.ttab is not None and self.tgrid is not None
@@ -128,7 +135,7 @@ class DeviceProblem:
         n_gy, n_gx, n_h, _ = (int(v) for v in self.ttab.shape)
         gx0, gy0, gdx, gdy = (float(v) for v in self.tgrid)
         return KmLtable(n_h=n_h, dh=float(self.tdh), n_gx=n_gx, n_gy=n_gy, gx0=gx0, gy0=gy0, gdx=gdx, gdy=gdy,
-                        t=_ptr(self.ttab), r2=_ptr(self.r2), time_precision=self.c_prec)
+                        t=_ptr(self.ttab), r2=_ptr(self.r2), time_precision=self.c_prec, amp=self._c_amp())
 
 
 def to_device(problem, device="cuda", data=None, dtype: str = "f32", prec: str = "fp32") -> DeviceProblem:
@@ -153,8 +160,10 @@ def to_device(problem, device="cuda", data=None, dtype: str = "f32", prec: str =
                        r2=f32(problem.r2), prec=prec)
     if getattr(problem, "ttab", None) is not None:
         tgrid = getattr(problem, "tgrid", None)
+        tamp = getattr(problem, "tamp", None)
         dp = dataclasses.replace(dp, ttab=f32(problem.ttab), tdh=float(problem.tdh),
-                                 tgrid=None if tgrid is None else tuple(float(v) for v in tgrid))
+                                 tgrid=None if tgrid is None else tuple(float(v) for v in tgrid),
+                                 tamp=None if tamp is None else f32(tamp))
     if getattr(problem, "aa", None) is not None:
         dp = dataclasses.replace(dp, aa=tuple(problem.aa))
     d = problem.data if data is None else data

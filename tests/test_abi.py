@@ -260,7 +260,8 @@ def test_table_entry_points_reject_bad_tables(lib):
                      (_lib.KmTtable(n_h=4, dh=0.0, t=p, r2=p), b"dh"),
                      (_lib.KmTtable(n_h=4, dh=float("inf"), t=p, r2=p), b"dh"),
                      (_lib.KmTtable(n_h=4, dh=10.0, t=None, r2=p), b"non-NULL"),
-                     (_lib.KmTtable(n_h=4, dh=10.0, t=ctypes.c_void_p(0x1002), r2=p), b"misaligned")]:
+                     (_lib.KmTtable(n_h=4, dh=10.0, t=ctypes.c_void_p(0x1002), r2=p), b"misaligned"),
+                     (_lib.KmTtable(n_h=4, dh=10.0, t=p, r2=p, amp=ctypes.c_void_p(0x1001)), b"misaligned")]:
         ref = ctypes.byref(tab) if tab is not None else None
         assert lib.kirchhoff_migrate_table(ctypes.byref(t), ctypes.byref(g), ref, p, 0, -1, None) == _lib.KM_E_INVALID
         assert msg in lib.km_last_error()
@@ -286,7 +287,7 @@ def test_ltable_entry_points_reject_bad_tables(lib):
                      (lt(gx0=float("nan")), b"gx0 and gy0"), (lt(gy0=float("inf")), b"gx0 and gy0"),
                      (lt(gdx=0.0), b"gdx"), (lt(gdy=-5.0), b"gdx"), (lt(gdx=float("inf")), b"gdx"),
                      (lt(n_h=1), b"n_h"), (lt(dh=0.0), b"dh"), (lt(t=None), b"non-NULL"),
-                     (lt(r2=ctypes.c_void_p(0x1002)), b"misaligned")]:
+                     (lt(r2=ctypes.c_void_p(0x1002)), b"misaligned"), (lt(amp=ctypes.c_void_p(0x1003)), b"misaligned")]:
         ref = ctypes.byref(tab) if tab is not None else None
         assert lib.kirchhoff_migrate_ltable(ctypes.byref(t), ctypes.byref(g), ref, p, 0, -1, None) == \
             _lib.KM_E_INVALID

@@ -146,3 +146,25 @@ def test_ltable_survey3d_sampled(ops, oracle_lib):
         e = rel_l2(got_d, ref_d)
         print(f"lateral survey {prec}: adjoint sample rel L2 {e:.3e}")
         assert e <= tol_d, prec
+
+
+@pytest.mark.parametrize("case", [CASES[1], CASES[3]], ids=lambda c: f"seed{c[0]}")
+def test_ltable_amplitudes_all_tiles(ops, oracle_lib, case):
+    # W = A_s A_r from each node's curved-ray amplitude table, interpolated
+    # over (x, y, h) as the times are
+    seed, n, nt, nx, ny, nz, nb, tf, (gx0, gy0, gdx, gdy, n_gx, n_gy) = case
+    p = survey.make_random(seed, n_traces=n, n_t=nt, nx=nx, ny=ny, nz=nz, n_bins=nb, dz=10.0, t_first=tf)
+    v0_at = survey.lateral_v0(1500.0, 0.4, -0.3, 1000.0, 2000.0 if ny > 1 else 0.0)
+    p = survey.with_lateral_tables(p, v0_at, 0.5, gx0, gy0, gdx, gdy, n_gx, n_gy, dh=7.5, amplitude=True)
+    ref = oracle_lib.migrate(p)
+    m = survey.bandlimited_image(p, seed + 3)
+    ref_d = oracle_lib.demigrate(p, m)
+    mt = torch.from_numpy(m).cuda()
+    for prec in ("fp32", "extended"):
+        dp = ops.to_device(p, prec=prec)
+        for tile in range(ops.tile_count(0)):
+            e = rel_l2(ops.migrate(dp, tile=tile).cpu().numpy(), ref)
+            assert e <= 1e-5, (prec, tile, e)
+        for tile in range(ops.tile_count(1)):
+            e = rel_l2(ops.demigrate(dp, mt, tile=tile).cpu().numpy(), ref_d)
+            assert e <= 1e-5, (prec, tile, e)

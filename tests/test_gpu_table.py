@@ -137,3 +137,35 @@ def test_table_not_increasing_in_h_falls_back(ops, oracle_lib):
     for tile in range(ops.tile_count(0)):
         img = ops.migrate(dp, tile=tile).cpu().numpy()
         assert rel_l2(img, ref) <= 1e-5, tile
+
+
+@pytest.mark.parametrize("case", CASES[1:3], ids=lambda c: f"seed{c[0]}")
+def test_table_amplitudes_all_tiles(ops, oracle_lib, case):
+    # W = A_s A_r from curved-ray amplitude tables (t0 / T^2 per leg)
+    seed, n, nt, nx, ny, nz, nb, tf = case
+    p = survey.make_random(seed, n_traces=n, n_t=nt, nx=nx, ny=ny, nz=nz, n_bins=nb, dz=10.0, t_first=tf)
+    p = survey.with_curved_ray_table(p, dh=7.5, amplitude=True)
+    ref = oracle_lib.migrate(p)
+    m = survey.bandlimited_image(p, seed + 3)
+    ref_d = oracle_lib.demigrate(p, m)
+    mt = torch.from_numpy(m).cuda()
+    for prec in ("fp32", "extended"):
+        dp = ops.to_device(p, prec=prec)
+        for tile in range(ops.tile_count(0)):
+            e = rel_l2(ops.migrate(dp, tile=tile).cpu().numpy(), ref)
+            assert e <= 1e-5, (prec, tile, e)
+        for tile in range(ops.tile_count(1)):
+            e = rel_l2(ops.demigrate(dp, mt, tile=tile).cpu().numpy(), ref_d)
+            assert e <= 1e-5, (prec, tile, e)
+
+
+def test_table_unit_amplitudes_are_bitwise_unit_weight(ops):
+    p = table_problem(CASES[0])
+    q = dataclasses.replace(p, tamp=np.ones_like(p.ttab))
+    d0, d1 = ops.to_device(p), ops.to_device(q)
+    m = torch.from_numpy(survey.random_image(p, 5)).cuda()
+    for tile in range(ops.tile_count(0)):
+        assert torch.equal(ops.migrate(d0, tile=tile), ops.migrate(d1, tile=tile)), tile
+    for tile in range(ops.tile_count(1)):
+        a, b = ops.demigrate(d0, m, tile=tile), ops.demigrate(d1, m, tile=tile)
+        assert rel_l2(a.cpu().numpy(), b.cpu().numpy()) <= 1e-7, tile
