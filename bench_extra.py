@@ -19,7 +19,8 @@ aa: the 3D survey migrated and demigrated with the anti-alias triangle filter:
     throughput of both operators and a sampled parity against the oracle.
 table: the 3D survey migrated and demigrated with curved-ray traveltime
     tables (v = 1500 + 0.5 z, h every 10 m) instead of the RMS double square
-    root: throughput of both operators next to the table-gather rate.
+    root: throughput of both operators next to the table-gather rate, and with
+    amplitude tables (W = A_s A_r).
 ltable: the same with laterally varying tables (v0 from 1420 to 1580 m/s
     across the image, curved rays under each node of a 9 x 9 grid at 400 m):
     throughput of both operators next to the table-gather rate.
@@ -227,6 +228,10 @@ def _table(steps, warmup, dev):
     out = torch.empty((dp.n_traces, dp.n_t), device=dev)
     ms_m = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
     ms_d = _time(lambda: ops.demigrate(dp, img, out=out), steps, warmup)
+    # the same with amplitude tables (W = A_s A_r: 4 more table reads per pair)
+    da = ops.to_device(survey.with_curved_ray_table(p, dh=10.0, amplitude=True), dev)
+    ms_ma = _time(lambda: ops.migrate(da, image=img), steps, warmup)
+    ms_da = _time(lambda: ops.demigrate(da, img, out=out), steps, warmup)
     # Two resources per pair once the legs are hoisted.  The table gathers:
     # 4 float32 values (16 bytes: two rows of each leg at the lane's depth), read
     # through the L2 (the tables are 565 KB, resident in every XCD's 4 MB L2).
@@ -243,6 +248,8 @@ def _table(steps, warmup, dev):
             "ms_migrate": round(ms_m, 3), "ms_demigrate": round(ms_d, 3),
             "gcps_migrate": round(n_ap / ms_m / 1e6, 3), "gcps_demigrate": round(n_ap / ms_d / 1e6, 3),
             "step_gcps": round(2 * n_ap / (ms_m + ms_d) / 1e6, 3),
+            "amplitudes": {"ms_migrate": round(ms_ma, 3), "ms_demigrate": round(ms_da, 3),
+                           "step_gcps": round(2 * n_ap / (ms_ma + ms_da) / 1e6, 3), "bytes_per_pair": 32},
             "roofline": {"bound": "l2_gather", "achieved": round(gather / 1e12, 3),
                          "peak": round(PEAK_L2_BYTES / 1e12, 3), "unit": "TB/s",
                          "frac": round(gather / PEAK_L2_BYTES, 4), "bytes_per_pair": table_bytes,
