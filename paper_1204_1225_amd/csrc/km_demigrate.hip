@@ -117,6 +117,55 @@ __device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TL
     }
 }
 
+// The two slots of a full depth chunk's slot pair with table times: depths
+// iz and iz + 1 of the same legs, read together (table_time_pair); each slot's
+// time, weight and taps have the bits of dem_pair_table / dem_pair_table_ext
+// (XF: extended legs).
+template <bool TF, bool LAT, bool XF, typename Leg>
+__device__ __forceinline__ void dem_pair_table2(const Params& P, Leg Ls, Leg Lr, LCol C, int iz, double* row,
+                                                float wlo, float whi, float x0, float x1, bool act0, bool act1) {
+    const Dbl2 ts = table_time_pair<LAT, XF>(P, Ls.off, static_cast<double>(Ls.f), C, iz);
+    const Dbl2 tr = table_time_pair<LAT, XF>(P, Lr.off, static_cast<double>(Lr.f), C, iz);
+    float r0 = 1.0f, r1 = 1.0f;
+    if (P.tamp) {
+        const Flt2 as = table_amp_pair<LAT>(P, Ls.off, static_cast<float>(Ls.f), C, iz);
+        const Flt2 ar = table_amp_pair<LAT>(P, Lr.off, static_cast<float>(Lr.f), C, iz);
+        r0 = as.a * ar.a;
+        r1 = as.b * ar.b;
+    }
+    double w0 = (ts.a + tr.a) * P.inv_dt, w1 = (ts.b + tr.b) * P.inv_dt;
+    if (TF) {
+        w0 = w0 + P.tf_off_d;
+        w1 = w1 + P.tf_off_d;
+    }
+    w0 = fmin(fmax(w0, static_cast<double>(wlo)), static_cast<double>(whi));
+    w1 = fmin(fmax(w1, static_cast<double>(wlo)), static_cast<double>(whi));
+    const int i0 = static_cast<int32_t>(w0), i1 = static_cast<int32_t>(w1);
+    if (XF) {
+        if (act0) {
+            const double q = static_cast<double>(x0 * r0), b = (w0 - static_cast<double>(i0)) * q;
+            atomicAdd(row + i0, q - b);
+            atomicAdd(row + i0 + 1, b);
+        }
+        if (act1) {
+            const double q = static_cast<double>(x1 * r1), b = (w1 - static_cast<double>(i1)) * q;
+            atomicAdd(row + i1, q - b);
+            atomicAdd(row + i1 + 1, b);
+        }
+    } else {
+        if (act0) {
+            const float q = x0 * r0, b = static_cast<float>(w0 - static_cast<double>(i0)) * q;
+            atomicAdd(row + i0, static_cast<double>(q - b));
+            atomicAdd(row + i0 + 1, static_cast<double>(b));
+        }
+        if (act1) {
+            const float q = x1 * r1, b = static_cast<float>(w1 - static_cast<double>(i1)) * q;
+            atomicAdd(row + i1, static_cast<double>(q - b));
+            atomicAdd(row + i1 + 1, static_cast<double>(b));
+        }
+    }
+}
+
 // dem_masked with table traveltimes (W = A_s A_r with amplitude tables, else
 // 1); iz0, iz1 are the lane's depths of the two slots, clamped into the table.  LAT: laterally varying tables, C
 // the column on the node grid.
@@ -290,6 +339,11 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
                     if (!((any >> k) & 3u)) continue;
+                    if (!TAIL) {  // every depth of the chunk exists: slot k + 1 is depth + 1
+                        dem_pair_table2<TF, LAT, true>(P, Ls, Lr, lc, slot_depth<kIL>(z0, k, d), row, wlo, whi, x[k],
+                                                       x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
+                        continue;
+                    }
                     const int iz0 = min(max(slot_depth<kIL>(z0, k, d), 0), P.nz - 1);
                     const int iz1 = min(max(slot_depth<kIL>(z0, k + 1, d), 0), P.nz - 1);
                     dem_pair_table_ext<TF, LAT>(P, Ls, Lr, lc, iz0, iz1, row, wlo, whi, x[k], x[k + 1],
@@ -302,6 +356,11 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 #pragma unroll
                 for (int k = 0; k < KS; k += 2) {
                     if (!((any >> k) & 3u)) continue;
+                    if (!TAIL) {
+                        dem_pair_table2<TF, LAT, false>(P, Ls, Lr, lc, slot_depth<kIL>(z0, k, d), row, wlo, whi,
+                                                        x[k], x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
+                        continue;
+                    }
                     const int iz0 = min(max(slot_depth<kIL>(z0, k, d), 0), P.nz - 1);
                     const int iz1 = min(max(slot_depth<kIL>(z0, k + 1, d), 0), P.nz - 1);
                     dem_pair_table<TF, true, LAT>(P, Ls, Lr, lc, iz0, iz1, row, tfo, wlo, whi, x[k], x[k + 1],

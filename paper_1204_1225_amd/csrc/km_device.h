@@ -437,6 +437,85 @@ __device__ __forceinline__ float table_amp(const Params& P, int off, float fh, L
     return fmaf(C.fy, t1 - t0, t0);
 }
 
+// Two adjacent depths iz, iz + 1 of one leg (the adjoint's interleaved slot
+// pairs in full depth chunks, iz + 1 < nz): one 8-byte read per row and node
+// gives both, where table_time / ltable_time read one value per read.  The
+// arithmetic is theirs (XF: that of the extended forms), so each depth's time
+// has the same bits as the single-depth functions give.
+struct Dbl2 {
+    double a, b;
+};
+struct Flt2 {
+    float a, b;
+};
+
+template <bool LAT, bool XF>
+__device__ __forceinline__ Dbl2 table_time_pair(const Params& P, int off, double fh, LCol C, int iz) {
+    const __amdgpu_buffer_rsrc_t R = raw_buffer(P.ttab, P.ttab_bytes);
+    const int vo = ((LAT ? C.off : 0) + off + iz) * 4;
+    const int nz = 4 * P.nz;
+    auto node = [&](int so) {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so, 0);       // row ih: iz, iz + 1
+        const auto b = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so + nz, 0);  // row ih + 1
+        const float a0 = __uint_as_float(a[0]), a1 = __uint_as_float(a[1]);
+        const float b0 = __uint_as_float(b[0]), b1 = __uint_as_float(b[1]);
+        Dbl2 t;
+        if (XF) {
+            const double da0 = a0, da1 = a1, db0 = b0, db1 = b1;
+            t.a = fma(fh, db0 - da0, da0);
+            t.b = fma(fh, db1 - da1, da1);
+        } else {
+            t.a = fma(fh, static_cast<double>(b0 - a0), static_cast<double>(a0));
+            t.b = fma(fh, static_cast<double>(b1 - a1), static_cast<double>(a1));
+        }
+        return t;
+    };
+    const Dbl2 t00 = node(0);
+    if (!LAT) return t00;
+    const int dx = 4 * P.ldx, dy = 4 * P.ldy;
+    const Dbl2 t10 = node(dx), t01 = node(dy), t11 = node(dx + dy);
+    const double fx = C.fx, fy = C.fy;
+    Dbl2 t;
+    {
+        const double t0 = fma(fx, t10.a - t00.a, t00.a), t1 = fma(fx, t11.a - t01.a, t01.a);
+        t.a = fma(fy, t1 - t0, t0);
+    }
+    {
+        const double t0 = fma(fx, t10.b - t00.b, t00.b), t1 = fma(fx, t11.b - t01.b, t01.b);
+        t.b = fma(fy, t1 - t0, t0);
+    }
+    return t;
+}
+
+// table_amp at two adjacent depths (same bits per depth).
+template <bool LAT>
+__device__ __forceinline__ Flt2 table_amp_pair(const Params& P, int off, float fh, LCol C, int iz) {
+    const __amdgpu_buffer_rsrc_t R = raw_buffer(P.tamp, P.ttab_bytes);
+    const int vo = ((LAT ? C.off : 0) + off + iz) * 4;
+    const int nz = 4 * P.nz;
+    auto node = [&](int so) {
+        const auto a = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so, 0);
+        const auto b = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so + nz, 0);
+        const float a0 = __uint_as_float(a[0]), a1 = __uint_as_float(a[1]);
+        const float b0 = __uint_as_float(b[0]), b1 = __uint_as_float(b[1]);
+        return Flt2{fmaf(fh, b0 - a0, a0), fmaf(fh, b1 - a1, a1)};
+    };
+    const Flt2 t00 = node(0);
+    if (!LAT) return t00;
+    const int dx = 4 * P.ldx, dy = 4 * P.ldy;
+    const Flt2 t10 = node(dx), t01 = node(dy), t11 = node(dx + dy);
+    Flt2 t;
+    {
+        const float t0 = fmaf(C.fx, t10.a - t00.a, t00.a), t1 = fmaf(C.fx, t11.a - t01.a, t01.a);
+        t.a = fmaf(C.fy, t1 - t0, t0);
+    }
+    {
+        const float t0 = fmaf(C.fx, t10.b - t00.b, t00.b), t1 = fmaf(C.fx, t11.b - t01.b, t01.b);
+        t.b = fmaf(C.fy, t1 - t0, t0);
+    }
+    return t;
+}
+
 // eval_pair_table with extended legs (same clamp as eval_pair_table; the
 // fraction is returned in float32 and float64).
 template <bool TF, bool LAT = false>
