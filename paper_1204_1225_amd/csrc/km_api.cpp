@@ -342,10 +342,11 @@ enum { KIND_DSR = 0, KIND_TABLE = 1, KIND_AA = 2, KIND_LTABLE = 3 };
 // filter: migrate 16 waves x 4 column groups x 8 slots (the largest trace
 // blocks), demigrate 8 waves x 4 slots x 1 quad.  With laterally varying
 // tables (16 reads per pair): migrate 4 waves x 3 column groups x 16 slots,
-// demigrate 8 waves x 4 slots x 1 quad.
+// demigrate 8 waves x 8 slots x 3 quads.
 int default_tile(int op, int kind) {
     if (op == 0) return kind == KIND_AA ? 1 : kind == KIND_LTABLE ? 3 : 2;
-    if (kind == KIND_AA || kind == KIND_LTABLE) return 3;
+    if (kind == KIND_AA) return 3;
+    if (kind == KIND_LTABLE) return 4;
     return kind == KIND_TABLE ? 1 : 3;
 }
 
