@@ -385,9 +385,14 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
                   const km_weight* weight, const km_ttable* table, const km_antialias* aa, float* image,
                   int32_t reps, void* stream, int32_t* best_tile /* host */, float* best_ms /* host */);
 
+/* km_tune for laterally varying tables (kind 3 of the class cache); the
+ * arguments as in kirchhoff_migrate_ltable / kirchhoff_demigrate_ltable. */
+km_status km_tune_ltable(int32_t op, const km_traces* traces, const km_grid* grid, const km_ltable* table,
+                         float* image, int32_t reps, void* stream, int32_t* best_tile /* host */,
+                         float* best_ms /* host */);
+
 /* The class cache of km_tune.  kind: 0 = square-root times, 1 = table times,
- * 2 = anti-alias filter, 3 = laterally varying tables (km_tune does not time
- * these: record their tile here).  km_tune_lookup returns -1 when nothing is recorded;
+ * 2 = anti-alias filter, 3 = laterally varying tables.  km_tune_lookup returns -1 when nothing is recorded;
  * km_tune_record stores (and persists) a tile with its time. */
 int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
                        int32_t n_samples);

@@ -102,6 +102,8 @@ SIGNATURES = {
     "km_tile_describe": (ctypes.c_int, [_i32, _i32, _P(KmTileInfo)]),
     "km_tune": (ctypes.c_int, [_i32, _P(KmTraces), _P(KmGrid), _P(KmTraveltime), _P(KmWeight), _P(KmTtable),
                                _P(KmAntialias), _vp, _i32, _vp, _P(_i32), _P(ctypes.c_float)]),
+    "km_tune_ltable": (ctypes.c_int, [_i32, _P(KmTraces), _P(KmGrid), _P(KmLtable), _vp, _i32, _vp,
+                                       ctypes.POINTER(_i32), ctypes.POINTER(ctypes.c_float)]),
     "km_tune_lookup": (_i32, [_i32, _i32, _i32, _i32, _i32, _i32]),
     "km_tune_record": (ctypes.c_int, [_i32, _i32, _i32, _i32, _i32, _i32, _i32, ctypes.c_float]),
     "km_batch_create": (ctypes.c_int, [_P(KmProblem), _i32, _i32, _i32, _vp, _P(_vp)]),

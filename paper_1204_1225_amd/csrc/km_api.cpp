@@ -762,9 +762,10 @@ km_status km_tune_record(int32_t op, int32_t dtype, int32_t kind, int32_t time_p
     return KM_OK;
 }
 
-km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
-                  const km_weight* weight, const km_ttable* table, const km_antialias* aa, float* image,
-                  int32_t reps, void* stream, int32_t* best_tile, float* best_ms) {
+// km_tune and km_tune_ltable: lat (with table) selects the laterally varying tables.
+static km_status tune_impl(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                           const km_weight* weight, const km_ttable* table, const km_antialias* aa, const Lateral* lat,
+                           float* image, int32_t reps, void* stream, int32_t* best_tile, float* best_ms) {
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tune: op must be 0 or 1");
     if (reps < 1) return fail(KM_E_INVALID, "km_tune: reps < 1");
     if (table && aa) return fail(KM_E_INVALID, "km_tune: table traveltimes and the anti-alias filter exclude each other");
@@ -772,9 +773,11 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
     if (st != KM_OK) return st;
     km_traveltime ttab_tt{};
     km_weight unit{KM_W_UNIT};
-    if (table) {
+    if (table && !lat) {
         st = check_table(table, grid, "km_tune");
         if (st != KM_OK) return st;
+    }
+    if (table) {
         ttab_tt = km_traveltime{table->r2, table->r2, table->r2, table->time_precision};
         tt = &ttab_tt;
         weight = &unit;
@@ -789,7 +792,7 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
     if (op == 1 && traces->dtype != KM_F32) return fail(KM_E_UNSUPPORTED, "km_tune: demigrate output must be KM_F32");
     if (grid_empty(grid) || traces->n_traces == 0) return fail(KM_E_INVALID, "km_tune: empty problem");
     if (!image) return fail(KM_E_INVALID, "km_tune: image is NULL");
-    const int kind = table ? KIND_TABLE : aa ? KIND_AA : KIND_DSR;
+    const int kind = lat ? KIND_LTABLE : table ? KIND_TABLE : aa ? KIND_AA : KIND_DSR;
     hipStream_t s = static_cast<hipStream_t>(stream);
     hipEvent_t e0, e1;
     hipError_t he = hipEventCreate(&e0);
@@ -816,11 +819,11 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
             if (table) P.ttab = table->t;
             if (shape_params(op, tile, P) != KM_OK) continue;
             if (op == 1 && lv > 0 && P.tb < 4 * lv) continue;  // the level's quads do not fit: same as a lower one
-            st = run_op(op, traces, grid, tt, weight, image, 0, tile, s, table, aa);
+            st = run_op(op, traces, grid, tt, weight, image, 0, tile, s, table, aa, lat);
             if (st != KM_OK) break;
             hipEventRecord(e0, s);
             for (int r = 0; r < reps && st == KM_OK; ++r)
-                st = run_op(op, traces, grid, tt, weight, image, 0, tile, s, table, aa);
+                st = run_op(op, traces, grid, tt, weight, image, 0, tile, s, table, aa, lat);
             hipEventRecord(e1, s);
             he = hipEventSynchronize(e1);
             if (he != hipSuccess) {
@@ -845,6 +848,23 @@ km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, cons
     if (best_tile) *best_tile = best;
     if (best_ms) *best_ms = best_t;
     return KM_OK;
+}
+
+km_status km_tune(int32_t op, const km_traces* traces, const km_grid* grid, const km_traveltime* tt,
+                  const km_weight* weight, const km_ttable* table, const km_antialias* aa, float* image,
+                  int32_t reps, void* stream, int32_t* best_tile, float* best_ms) {
+    return tune_impl(op, traces, grid, tt, weight, table, aa, nullptr, image, reps, stream, best_tile, best_ms);
+}
+
+km_status km_tune_ltable(int32_t op, const km_traces* traces, const km_grid* grid, const km_ltable* ltab,
+                         float* image, int32_t reps, void* stream, int32_t* best_tile, float* best_ms) {
+    km_ttable tab;
+    Lateral lat;
+    const km_status st = check_ltable(ltab, grid, "km_tune_ltable", &tab, &lat);
+    if (st != KM_OK) return st;
+    const km_traveltime tt{tab.r2, tab.r2, tab.r2, tab.time_precision};
+    const km_weight w{KM_W_UNIT};
+    return tune_impl(op, traces, grid, &tt, &w, &tab, nullptr, &lat, image, reps, stream, best_tile, best_ms);
 }
 
 // ---- batched persistent migration -----------------------------------------

@@ -406,11 +406,13 @@ def tune(op: int, dp: DeviceProblem, image: torch.Tensor, traces_out: Optional[t
     kind) and record the fastest for its class; returns (tile, ms).  For op 0
     `image` is overwritten with the migration; for op 1 `image` is the input
     and `traces_out` (float32 [n_traces, n_t]) is overwritten."""
-    if dp.tgrid is not None:
-        raise _lib.KirchhoffError(_lib.KM_E_UNSUPPORTED, "tune: laterally varying tables are recorded with "
-                                                         "km_tune_record, not timed by km_tune")
     best, ms = ctypes.c_int32(-1), ctypes.c_float(0.0)
     tr = dp.c_traces() if op == 0 else dp.c_traces(traces_out, "f32")
+    if dp.tgrid is not None:
+        check(_lib.load().km_tune_ltable(op, ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_ltable()),
+                                         _ptr(image), int(reps), ctypes.c_void_p(_stream(dp.device)),
+                                         ctypes.byref(best), ctypes.byref(ms)))
+        return int(best.value), float(ms.value)
     tab = ctypes.byref(dp.c_table()) if dp.ttab is not None else None
     aa = ctypes.byref(dp.c_aa()) if dp.aa is not None else None
     check(_lib.load().km_tune(op, ctypes.byref(tr), ctypes.byref(dp.c_grid()), ctypes.byref(dp.c_tt()),

@@ -295,6 +295,11 @@ def test_ltable_entry_points_reject_bad_tables(lib):
         assert lib.kirchhoff_demigrate_ltable(p, ctypes.byref(g), ref, ctypes.byref(t), 0, -1, None) == \
             _lib.KM_E_INVALID
         assert msg in lib.km_last_error()
+    # the tuner validates the table the same way (before any launch)
+    assert lib.km_tune_ltable(0, ctypes.byref(t), ctypes.byref(g), None, p, 1, None, None, None) == _lib.KM_E_INVALID
+    assert lib.km_tune_ltable(0, ctypes.byref(t), ctypes.byref(g), ctypes.byref(lt(gdx=0.0)), p, 1, None, None,
+                              None) == _lib.KM_E_INVALID
+    assert b"gdx" in lib.km_last_error()
     # the spacing of an axis with one node is not read
     one = lt(n_gx=1, n_gy=1, gdx=0.0, gdy=float("nan"), n_h=1)
     assert lib.kirchhoff_migrate_ltable(ctypes.byref(t), ctypes.byref(g), ctypes.byref(one), p, 0, -1, None) == \

@@ -53,7 +53,7 @@ def test_every_tile_level_matches_oracle(ops, oracle_lib, prec, tol):
     assert len(ops.tiles(0)) > ops.tile_count(0) and len(ops.tiles(1)) > ops.tile_count(1)
 
 
-@pytest.mark.parametrize("kind", ["plain", "table"])
+@pytest.mark.parametrize("kind", ["plain", "table", "ltable"])
 def test_tune_pick_persist_reload(ops, oracle_lib, tmp_path, kind):
     path = str(tmp_path / "tune.json")
     os.environ["KM_TUNE_CACHE"] = path
@@ -61,6 +61,9 @@ def test_tune_pick_persist_reload(ops, oracle_lib, tmp_path, kind):
         p = survey.make_random(63, n_traces=150, n_t=380, nx=17, ny=3, nz=70, n_bins=2, dz=10.0)
         if kind == "table":
             p = survey.with_curved_ray_table(p, dh=7.5)
+        if kind == "ltable":
+            p = survey.with_lateral_tables(p, survey.lateral_v0(1500.0, 0.3, -0.2, 1000.0, 2000.0), 0.5, 960.0,
+                                           1970.0, 60.0, 40.0, 3, 3, dh=7.5, amplitude=True)
         # the extended time keeps the oracle check at 1e-5 on this geometry
         # (the float32 time's adjoint sits near 1.1e-5 here)
         dp = ops.to_device(p, prec="extended")
@@ -77,7 +80,7 @@ def test_tune_pick_persist_reload(ops, oracle_lib, tmp_path, kind):
         assert rel_l2(ops.migrate(dp).cpu().numpy(), oracle_lib.migrate(p)) <= 1e-5
         assert rel_l2(ops.demigrate(dp, m).cpu().numpy(), oracle_lib.demigrate(p, m.cpu().numpy())) <= 1e-5
         # a fresh process reads the file and finds the same tiles for the class
-        kind_id = 1 if kind == "table" else 0
+        kind_id = {"plain": 0, "table": 1, "ltable": 3}[kind]
         code = (f"import sys; sys.path.insert(0, {ROOT!r})\n"
                 "from paper_1204_1225_amd import _lib\n"
                 "lib = _lib.load()\n"
