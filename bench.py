@@ -48,9 +48,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "87a069852197a47bf0b1275b227c8be4ead9f657929bd76372e3f7ac1196fbfb",
-    "migrate": 9.1587e10,
-    "demigrate": 3.0076e12,
+    "sources_sha256": "71775327d88fbfb46ba92c5f902df57bb3ee99f18d92ebcf10463c24b60f0c8e",
+    "migrate": 9.1788e10,
+    "demigrate": 3.0074e12,
 }
 
 
