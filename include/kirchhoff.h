@@ -58,7 +58,9 @@ typedef enum km_status {
     KM_OK = 0,
     KM_E_INVALID = 1,     /* bad argument (null pointer, size, enum, layout) */
     KM_E_UNSUPPORTED = 2, /* valid but not supported (e.g. 16-bit demigrate output, record too long) */
-    KM_E_HIP = 3,         /* a HIP runtime call failed; km_last_error has its message */
+    KM_E_HIP = 3,         /* a HIP runtime call failed; km_last_error has its message.  With
+                             KM_FAULT_INJECT=launch in the environment every kernel launch of the
+                             library fails this way without launching (for tests of error paths) */
     KM_E_NOMEM = 4        /* a library-owned allocation failed (batch handles only) */
 } km_status;
 

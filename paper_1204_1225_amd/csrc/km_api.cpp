@@ -9,6 +9,8 @@
 #include <cmath>
 #include <cstdarg>
 #include <cstdio>
+#include <cstdlib>
+#include <cstring>
 #include <map>
 #include <mutex>
 #include <string>
@@ -33,6 +35,20 @@ km_status fail(km_status st, const char* fmt, ...) {
 
 km_status hip_fail(hipError_t e, const char* what) {
     return fail(KM_E_HIP, "%s: %s (%d)", what, hipGetErrorString(e), static_cast<int>(e));
+}
+
+// Failure injection for tests of the error path: with KM_FAULT_INJECT=launch
+// in the environment every kernel launch of the library reports a HIP launch
+// failure instead of launching (nothing runs; outputs are untouched).
+bool inject_launch_failure() {
+    const char* v = std::getenv("KM_FAULT_INJECT");
+    return v && std::strcmp(v, "launch") == 0;
+}
+
+// The status of a launch that is about to happen: KM_E_HIP when failures are injected.
+km_status injected(const char* what) {
+    return inject_launch_failure() ? fail(KM_E_HIP, "%s: launch failure injected (KM_FAULT_INJECT=launch)", what)
+                                   : KM_OK;
 }
 
 constexpr int kMaxLds = 160 * 1024;  // LDS per workgroup on gfx950
@@ -424,6 +440,8 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         return fail(KM_E_UNSUPPORTED, "kirchhoff_demigrate: too many trace blocks");
     if (op == 0 && P.n_traces > INT32_MAX)  // block slots record trace indices within a bin as int32
         return fail(KM_E_UNSUPPORTED, "kirchhoff_migrate: more than 2^31 - 1 traces");
+    st = injected(op == 0 ? "migrate launch" : "demigrate launch");
+    if (st != KM_OK) return st;
     hipError_t e = op == 0 ? km::launch_migrate(shape, P, s) : km::launch_demigrate(shape, P, s);
     if (e != hipSuccess) return hip_fail(e, op == 0 ? "migrate launch" : "demigrate launch");
     return KM_OK;
@@ -432,6 +450,8 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
 // Image zero fill for empty problems (nothing to evaluate, overwrite semantics).
 km_status zero_floats(float* p, int64_t n, hipStream_t s) {
     if (n <= 0) return KM_OK;
+    const km_status st = injected("zero fill");
+    if (st != KM_OK) return st;
     const hipError_t e = km::launch_axpby(0.0f, p, 0.0f, p, n, s);
     return e == hipSuccess ? KM_OK : hip_fail(e, "zero fill");
 }
@@ -626,6 +646,10 @@ km_status km_count_contributions(const km_traces* traces, const km_grid* grid, c
     if (!counts || !aligned(counts, 8)) return fail(KM_E_INVALID, "km_count_contributions: counts NULL/misaligned");
     km::Params P = base_params(traces, grid, tt, &w, nullptr, 0);
     if (grid_empty(grid)) { P.nx = P.ny = P.nz = P.n_bins = 0; }
+    {
+        const km_status ist = injected("count launch");
+        if (ist != KM_OK) return ist;
+    }
     const hipError_t e = km::launch_count(P, reinterpret_cast<unsigned long long*>(counts),
                                           static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "count launch");
@@ -636,6 +660,10 @@ km_status km_dot_f64(const float* a, const float* b, int64_t n, double* out, voi
     if (!out || !aligned(out, 8)) return fail(KM_E_INVALID, "km_dot_f64: out NULL/misaligned");
     if (n > 0 && (!a || !b || !aligned(a, 4) || !aligned(b, 4)))
         return fail(KM_E_INVALID, "km_dot_f64: a, b NULL/misaligned");
+    {
+        const km_status ist = injected("dot launch");
+        if (ist != KM_OK) return ist;
+    }
     const hipError_t e = km::launch_dot_f64(a, b, n, out, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "dot launch");
 }
@@ -645,6 +673,10 @@ km_status km_axpby(double alpha, const float* x, double beta, float* y, int64_t 
     if (n > 0 && (!x || !y || !aligned(x, 4) || !aligned(y, 4)))
         return fail(KM_E_INVALID, "km_axpby: x, y NULL/misaligned");
     if (!std::isfinite(alpha) || !std::isfinite(beta)) return fail(KM_E_INVALID, "km_axpby: non-finite scalar");
+    {
+        const km_status ist = injected("axpby launch");
+        if (ist != KM_OK) return ist;
+    }
     const hipError_t e = km::launch_axpby(static_cast<float>(alpha), x, static_cast<float>(beta), y, n,
                                           static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "axpby launch");
@@ -670,6 +702,10 @@ km_status km_trace_filter(const float* in, int64_t in_stride, float* out, int64_
     }
     if (km::fir_lds_bytes(n_samples, n_taps) > static_cast<size_t>(kMaxLds))
         return fail(KM_E_UNSUPPORTED, "km_trace_filter: %d samples and %d taps do not fit in LDS", n_samples, n_taps);
+    {
+        const km_status ist = injected("filter launch");
+        if (ist != KM_OK) return ist;
+    }
     const hipError_t e = km::launch_fir(in, in_stride, out, out_stride, n_traces, n_samples, taps, n_taps, center,
                                         adjoint ? 1 : 0, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "filter launch");
@@ -681,6 +717,10 @@ km_status km_stack_offsets(const float* image, int32_t n_bins, int64_t n_points,
     if (n_points == 0) return KM_OK;
     if (!image || !stack || !aligned(image, 4) || !aligned(stack, 4))
         return fail(KM_E_INVALID, "km_stack_offsets: image, stack NULL/misaligned");
+    {
+        const km_status ist = injected("stack launch");
+        if (ist != KM_OK) return ist;
+    }
     const hipError_t e = km::launch_stack(image, n_bins, n_points, stack, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "stack launch");
 }
@@ -709,6 +749,10 @@ km_status km_cig_moveout(const float* image, const km_grid* grid, const float* o
         return fail(KM_E_UNSUPPORTED, "km_cig_moveout: %d bins x %d depths do not fit in LDS", grid->n_bins,
                     grid->nz);
     if (grid->nx == 0 || grid->ny == 0) return KM_OK;
+    {
+        const km_status ist = injected("moveout launch");
+        if (ist != KM_OK) return ist;
+    }
     const hipError_t e = km::launch_cig(image, grid->n_bins, grid->ny, grid->nx, grid->nz, max_lag, z_lo, z_hi,
                                         offsets, stack, shift, peak, curvature, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "moveout launch");
@@ -1144,6 +1188,8 @@ km_status km_batch_migrate_static(const km_problem* probs, int32_t n, int32_t ti
     int n_wg = 0;
     st = batch_grid(L, device, &n_wg, nullptr, who);
     if (st != KM_OK) return st;
+    st = injected("km_batch_migrate_static launch");
+    if (st != KM_OK) return st;
     e = km::launch_reset_counter(d_counter, s);
     if (e == hipSuccess)
         e = km::launch_migrate_batch(L.shape, d_probs, d_items, static_cast<int64_t>(L.items.size()), d_counter,
@@ -1153,6 +1199,8 @@ km_status km_batch_migrate_static(const km_problem* probs, int32_t n, int32_t ti
 
 km_status km_batch_run(km_batch* batch, void* stream) {
     if (!batch) return fail(KM_E_INVALID, "km_batch_run: batch is NULL");
+    const km_status st = injected("km_batch_run launch");
+    if (st != KM_OK) return st;
     const hipError_t e = hipGraphLaunch(batch->exec, static_cast<hipStream_t>(stream));
     return e == hipSuccess ? KM_OK : hip_fail(e, "hipGraphLaunch");
 }

@@ -377,3 +377,29 @@ def test_batch_static_rejects_what_does_not_fit(lib):
         big[k] = _lib.KmProblem(traces=t, grid=g, tt=tt, weight=w, image=ctypes.c_void_p(0x1000))
     assert lib.km_batch_migrate_static(big, 4097, 2, None) == _lib.KM_E_UNSUPPORTED
     assert lib.km_batch_migrate_static(None, 0, -1, None) == _lib.KM_E_INVALID
+
+
+def test_injected_launch_failure_is_reported(lib, monkeypatch):
+    # KM_FAULT_INJECT=launch: a valid call reaches its launch and reports
+    # KM_E_HIP with a message instead of launching (host only: the pointers
+    # are never dereferenced, no GPU is touched); without it validation errors
+    # still come first.
+    from paper_1204_1225_amd import _lib
+
+    t, g, tt, w = _args(_lib)
+    p = ctypes.c_void_p(0x1000)
+    monkeypatch.setenv("KM_FAULT_INJECT", "launch")
+    assert lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), p, 0, 2,
+                                 None) == _lib.KM_E_HIP
+    assert b"migrate launch" in lib.km_last_error() and b"injected" in lib.km_last_error()
+    assert lib.kirchhoff_demigrate(p, ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), ctypes.byref(t), 0, 3,
+                                   None) == _lib.KM_E_HIP
+    assert b"demigrate launch" in lib.km_last_error()
+    assert lib.km_dot_f64(p, p, 16, p, None) == _lib.KM_E_HIP
+    assert lib.km_axpby(1.0, p, 1.0, p, 16, None) == _lib.KM_E_HIP
+    t_bad, g2, tt2, w2 = _args(_lib, t__dt=0.0)
+    assert lib.kirchhoff_migrate(ctypes.byref(t_bad), ctypes.byref(g2), ctypes.byref(tt2), ctypes.byref(w2), p, 0,
+                                 2, None) == _lib.KM_E_INVALID
+    monkeypatch.setenv("KM_FAULT_INJECT", "other")
+    assert lib.kirchhoff_migrate(ctypes.byref(t_bad), ctypes.byref(g2), ctypes.byref(tt2), ctypes.byref(w2), p, 0,
+                                 2, None) == _lib.KM_E_INVALID
