@@ -113,7 +113,7 @@ def main():
     if args.workload != "survey3d":
         import bench_extra
 
-        print(json.dumps(bench_extra.run(args.workload, args.steps, args.warmup, dev)), flush=True)
+        emit(bench_extra.run(args.workload, args.steps, args.warmup, dev), dev)
         return
 
     t0 = time.time()
@@ -246,7 +246,24 @@ def main():
         "cpu_baseline": cpu,
         "parity_sample_rel_l2": parity,
     }
-    print(json.dumps(out), flush=True)
+    emit(out, dev)
+
+
+def emit(record, dev):
+    """Print the JSON line; with KM_LOG naming a file, also append it there
+    (JSONL) with the GPU's name, compute units and clock and the time."""
+    print(json.dumps(record), flush=True)
+    path = os.environ.get("KM_LOG")
+    if path:
+        import torch
+
+        prop = torch.cuda.get_device_properties(dev)
+        gpu = {"name": prop.name, "arch": getattr(prop, "gcnArchName", ""),
+               "compute_units": prop.multi_processor_count,
+               "clock_mhz": getattr(prop, "clock_rate", 0) // 1000 if hasattr(prop, "clock_rate") else None}
+        with open(path, "a") as fh:
+            fh.write(json.dumps({**record, "gpu": gpu, "time": time.strftime("%Y-%m-%dT%H:%M:%S"),
+                                 "argv": sys.argv[1:]}) + "\n")
 
 
 if __name__ == "__main__":
