@@ -182,8 +182,8 @@ typedef struct km_ttable {
 /* As kirchhoff_migrate with table traveltimes and W = 1 (or the amplitude
  * tables' A_s A_r).  KM_E_INVALID also for a NULL table, n_h < 2, dh not
  * finite or <= 0, NULL or misaligned t / r2, misaligned amp;
- * KM_E_UNSUPPORTED for n_h * nz >= 2^30 (the kernels read the table
- * through one buffer of at most 4 GiB). */
+ * KM_E_UNSUPPORTED for n_h * nz >= 2^29 (the kernels read the table
+ * through one buffer addressed with 32-bit signed byte offsets: 2 GiB). */
 km_status kirchhoff_migrate_table(const km_traces* traces, const km_grid* grid, const km_ttable* table, float* image,
                                   int32_t accumulate, int32_t tile, void* stream);
 
@@ -224,7 +224,7 @@ typedef struct km_ltable {
  * KM_E_INVALID also for a NULL table, n_gx or n_gy < 1, gx0 / gy0 not
  * finite, gdx (gdy) not finite or <= 0 with n_gx (n_gy) > 1, and the
  * km_ttable conditions on n_h, dh, t and r2; KM_E_UNSUPPORTED for
- * n_gx * n_gy * n_h * nz >= 2^30.  Work per pair: 16 table reads (4 nodes x
+ * n_gx * n_gy * n_h * nz >= 2^29.  Work per pair: 16 table reads (4 nodes x
  * 2 rows x 2 legs) where a km_ttable pair takes 4. */
 km_status kirchhoff_migrate_ltable(const km_traces* traces, const km_grid* grid, const km_ltable* table,
                                    float* image, int32_t accumulate, int32_t tile, void* stream);

@@ -419,11 +419,11 @@ km_status run_op(int op, const km_traces* t, const km_grid* g, const km_travelti
         P.r2 = tab->r2;
         P.tamp = tab->amp;
         P.weight = KM_W_UNIT;
-        // < 2^32: checked with the table
+        // < 2^31: checked with the table
         P.ttab_bytes = static_cast<uint32_t>(int64_t{4} * tab->n_h * g->nz * (lat ? int64_t{lat->n_gx} * lat->n_gy : 1));
     }
     if (tab && lat) {
-        const int32_t node = tab->n_h * g->nz;  // < 2^31: checked with the whole table
+        const int32_t node = tab->n_h * g->nz;  // < 2^29: checked with the whole table
         P.n_gx = lat->n_gx;
         P.n_gy = lat->n_gy;
         P.ldx = lat->n_gx > 1 ? node : 0;
@@ -522,8 +522,8 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
     if (!tab) return fail(KM_E_INVALID, "%s: table is NULL", who);
     if (tab->n_h < 2) return fail(KM_E_INVALID, "%s: n_h < 2", who);
     if (!(tab->dh > 0.0) || !std::isfinite(tab->dh)) return fail(KM_E_INVALID, "%s: dh must be finite and > 0", who);
-    if (grid && static_cast<int64_t>(tab->n_h) * grid->nz >= (int64_t(1) << 30))
-        return fail(KM_E_UNSUPPORTED, "%s: n_h * nz must be < 2^30", who);
+    if (grid && static_cast<int64_t>(tab->n_h) * grid->nz >= (int64_t(1) << 29))
+        return fail(KM_E_UNSUPPORTED, "%s: n_h * nz must be < 2^29", who);
     if (grid && !grid_empty(grid)) {
         if (!tab->t || !tab->r2) return fail(KM_E_INVALID, "%s: t and r2 must be non-NULL", who);
         if (!aligned(tab->t, 4) || !aligned(tab->r2, 4) || !aligned(tab->amp, 4))
@@ -533,8 +533,8 @@ km_status check_table(const km_ttable* tab, const km_grid* grid, const char* who
 }
 
 // Laterally varying tables: the node grid, then the table as check_table
-// sees it (the node tables together must stay below 2^30 floats: the kernels
-// read them through one buffer of at most 4 GiB).
+// sees it (the node tables together must stay below 2^29 floats: the kernels
+// read them through one buffer whose byte offsets are 32-bit signed values).
 km_status check_ltable(const km_ltable* lt, const km_grid* grid, const char* who, km_ttable* tab, Lateral* lat) {
     if (!lt) return fail(KM_E_INVALID, "%s: table is NULL", who);
     if (lt->n_gx < 1 || lt->n_gy < 1) return fail(KM_E_INVALID, "%s: n_gx and n_gy must be >= 1", who);
@@ -546,8 +546,8 @@ km_status check_ltable(const km_ltable* lt, const km_grid* grid, const char* who
     *tab = km_ttable{lt->n_h, lt->dh, lt->t, lt->r2, lt->time_precision, lt->amp};
     const km_status st = check_table(tab, grid, who);
     if (st != KM_OK) return st;
-    if (grid && static_cast<int64_t>(lt->n_gx) * lt->n_gy * lt->n_h * grid->nz >= (int64_t(1) << 30))
-        return fail(KM_E_UNSUPPORTED, "%s: n_gx * n_gy * n_h * nz must be < 2^30", who);
+    if (grid && static_cast<int64_t>(lt->n_gx) * lt->n_gy * lt->n_h * grid->nz >= (int64_t(1) << 29))
+        return fail(KM_E_UNSUPPORTED, "%s: n_gx * n_gy * n_h * nz must be < 2^29", who);
     *lat = Lateral{lt->n_gx, lt->n_gy, lt->gx0, lt->gy0, lt->n_gx > 1 ? lt->gdx : 1.0, lt->n_gy > 1 ? lt->gdy : 1.0};
     return KM_OK;
 }

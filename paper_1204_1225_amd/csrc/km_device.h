@@ -81,7 +81,7 @@ struct Params {
     int32_t n_gx, n_gy;
     int32_t ldx, ldy;    // floats from a node's table to its +x / +y neighbour's (0 on an axis of one node)
     double gx0, gy0, gdx, gdy;
-    uint32_t ttab_bytes; // size of ttab (every node), < 2^32
+    uint32_t ttab_bytes; // size of ttab (every node), < 2^31: byte offsets into it fit an int
     // one-way amplitudes of the table kinds (same layout and size as ttab), or
     // NULL: W = A_s A_r instead of 1
     const float* tamp;
