@@ -52,7 +52,7 @@
 extern "C" {
 #endif
 
-#define KM_ABI_VERSION 3
+#define KM_ABI_VERSION 4
 
 typedef enum km_status {
     KM_OK = 0,
@@ -355,8 +355,14 @@ km_status km_cig_moveout(const float* image, const km_grid* grid, const float* o
  * op: 0 = migrate, 1 = demigrate.  A tile is a compiled shape (waves, column
  * groups, depth slots, LDS budget; km_tile_count(op) of them) and a runtime
  * level of it, passed as tile = shape + 64 * level, level < km_tile_levels(op):
- * migrate levels scale the trace block's LDS budget (traces per block) by 1,
- * 0.5, 1.5 and 2 (at most 160 KiB); demigrate level 0 takes as many trace quads
+ * migrate levels 0..3 scale the trace block's LDS budget (traces per block) by
+ * 1, 0.5, 1.5 and 2 (at most 160 KiB); migrate levels 4 and 5 (lds16 = 1) take
+ * budgets 1 and 2 and stage KM_BF16 / KM_F16 traces in LDS as their 16-bit
+ * storage, widened and scaled as they are read (more traces per block, an
+ * extra conversion per sample read): a migrate call with such a tile returns
+ * KM_E_UNSUPPORTED for KM_F32 traces, KM_TIME_EXTENDED and the anti-alias
+ * filter, and the batched calls refuse it (a tuned one becomes level 0 or 3
+ * there); demigrate level 0 takes as many trace quads
  * per workgroup as the shape allows, level L >= 1 takes L quads (L at most the
  * shape's trace_quads). */
 typedef struct km_tile_info {
@@ -366,6 +372,7 @@ typedef struct km_tile_info {
     int32_t lds_budget;       /* bytes of LDS the trace block (migrate) or trace rows (demigrate) may use */
     int32_t trace_quads;      /* demigrate: most groups of 4 traces per workgroup at this level; 0 for migrate */
     int32_t shape, level;     /* the decoded tile */
+    int32_t lds16;            /* migrate: 1 if the level stages 16-bit traces as 16-bit storage */
 } km_tile_info;
 
 int32_t km_tile_count(int32_t op);

@@ -13,7 +13,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 # KM_LIBRARY names another build of this library (the sanitizer build of its
 # host code, for instance); by default the in-tree one
 LIB_PATH = os.environ.get("KM_LIBRARY") or os.path.join(HERE, "libkirchhoff.so")
-ABI_VERSION = 3
+ABI_VERSION = 4
 
 KM_OK, KM_E_INVALID, KM_E_UNSUPPORTED, KM_E_HIP, KM_E_NOMEM = range(5)
 KM_F32, KM_BF16, KM_F16 = 0, 1, 2
@@ -57,7 +57,7 @@ class KmWeight(ctypes.Structure):
 
 class KmTileInfo(ctypes.Structure):
     _fields_ = [("waves", _i32), ("column_groups", _i32), ("depth_slots", _i32), ("lds_budget", _i32),
-                ("trace_quads", _i32), ("shape", _i32), ("level", _i32)]
+                ("trace_quads", _i32), ("shape", _i32), ("level", _i32), ("lds16", _i32)]
 
 
 class KmProblem(ctypes.Structure):

@@ -157,16 +157,20 @@ int traces_per_block(int lt, int budget, int ks, int row_bytes_per_sample) {
 
 // Migrate blocks: at most kMigrateSlots traces, and the shape's LDS budget
 // less the fixed part for their time windows (2 floats per staged sample, 1
-// for table traveltimes);
+// for table traveltimes, half as many bytes with 16-bit staging);
 // at least one whole record (samples -1 .. nt + 1) must fit, with fewer
 // slots for the longest records.  Sets P.tb and P.cap (floats); false if a
 // record does not fit in LDS.
 constexpr int kMigrateSlots = 128;
 bool migrate_block_params(km::Params& P, int budget, int ks) {
     // square-root times stage (sample, difference) pairs, table times samples,
-    // anti-aliasing float64 running sums over nt + 4 max_half + 9 positions
+    // 16-bit staging packed pairs of 16-bit samples and 16-bit samples (half
+    // as many bytes), anti-aliasing float64 running sums over nt + 4 max_half
+    // + 9 positions
     const int64_t nt = P.nt;
-    const int64_t need = (P.aa_max > 0 ? 2 * (nt + 4 * P.aa_max + 9) : P.ttab ? nt + 3 : 2 * (nt + 2)) + 3 & ~int64_t{3};
+    const int64_t need = (P.aa_max > 0 ? 2 * (nt + 4 * P.aa_max + 9)
+                          : P.ttab   ? (P.s16 ? (nt + 4) / 2 : nt + 3)
+                                     : (P.s16 ? nt + 2 : 2 * (nt + 2))) + 3 & ~int64_t{3};
     for (int tb = kMigrateSlots; tb >= 1; tb /= 2) {
         const int64_t fixed = static_cast<int64_t>(km::migrate_lds_words(0, tb, ks));
         const int64_t cap = std::max<int64_t>((budget / 4 - fixed) & ~int64_t{3}, need);
@@ -183,18 +187,27 @@ int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demig
 
 // A tile is a compiled shape and a runtime variant of it, encoded as
 // shape + kTileLevelStride * level.  Migrate levels scale the LDS budget of the
-// trace block (traces per block): 1, 0.5, 1.5, 2 times the shape's.  Demigrate
-// level 0 takes as many trace quads per workgroup as the shape's budget and
-// template allow; level L >= 1 takes L quads (L <= the shape's quads).
+// trace block (traces per block): 1, 0.5, 1.5, 2 times the shape's, and levels
+// 4 and 5 stage 16-bit traces as their 16-bit storage (the S16 kernels) with 1
+// and 2 times the budget: twice the samples per byte of float staging.
+// Demigrate level 0 takes as
+// many trace quads per workgroup as the shape's budget and template allow;
+// level L >= 1 takes L quads (L <= the shape's quads).
 constexpr int kTileLevelStride = 64;
-constexpr int kTileLevels = 4;
-constexpr double kMigrateBudgetScale[kTileLevels] = {1.0, 0.5, 1.5, 2.0};
+constexpr int kMigrateLevels = 6;
+constexpr int kDemigrateLevels = 4;
+constexpr double kMigrateBudgetScale[kMigrateLevels] = {1.0, 0.5, 1.5, 2.0, 1.0, 2.0};
+constexpr int kMigrateLds16[kMigrateLevels] = {0, 0, 0, 0, 1, 1};
+// the float-staging level of a 16-bit staging level's budget
+constexpr int kMigrateFloatLevel[kMigrateLevels] = {0, 1, 2, 3, 0, 3};
+
+int level_count(int op) { return op == 0 ? kMigrateLevels : kDemigrateLevels; }
 
 bool decode_tile(int op, int tile, int* shape, int* level) {
     if (tile < 0) return false;
     *shape = tile % kTileLevelStride;
     *level = tile / kTileLevelStride;
-    if (*shape >= shape_count(op) || *level >= kTileLevels) return false;
+    if (*shape >= shape_count(op) || *level >= level_count(op)) return false;
     if (op == 1 && *level > 0 && *level > km::demigrate_shape(*shape).max_quads) return false;
     return true;
 }
@@ -204,6 +217,11 @@ km_status shape_params(int op, int tile, km::Params& P) {
     if (!decode_tile(op, tile, &shape, &level)) return fail(KM_E_INVALID, "tile %d is not a tile of op %d", tile, op);
     const km::TileShape& S = op == 0 ? km::migrate_shape(shape) : km::demigrate_shape(shape);
     if (op == 0) {
+        P.s16 = kMigrateLds16[level];
+        if (P.s16 && (P.dtype == km::F32 || P.aa_max > 0 || P.prec))
+            return fail(KM_E_UNSUPPORTED,
+                        "tile %d stages 16-bit traces: it needs KM_BF16 or KM_F16 traces, float32 time precision "
+                        "and no anti-alias filter", tile);
         const int budget = static_cast<int>(std::min<double>(kMaxLds, S.lds_budget * kMigrateBudgetScale[level]));
         if (!migrate_block_params(P, budget, S.depth_slots)) P.tb = 0;
     } else {
@@ -372,7 +390,7 @@ km_status pick_tile(int op, int tile, int dtype, int kind, int prec, int nz, int
         int shape = 0, level = 0;
         if (!decode_tile(op, tile, &shape, &level))
             return fail(KM_E_INVALID, "tile %d out of range (shape < %d, level < %d)", tile, shape_count(op),
-                        kTileLevels);
+                        level_count(op));
         *out = tile;
         return KM_OK;
     }
@@ -760,11 +778,7 @@ km_status km_cig_moveout(const float* image, const km_grid* grid, const float* o
 
 int32_t km_tile_count(int32_t op) { return (op == 0 || op == 1) ? shape_count(op) : 0; }
 
-int32_t km_tile_levels(int32_t op) {
-    if (op == 0) return kTileLevels;
-    if (op == 1) return kTileLevels;
-    return 0;
-}
+int32_t km_tile_levels(int32_t op) { return (op == 0 || op == 1) ? level_count(op) : 0; }
 
 km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out) {
     if (op != 0 && op != 1) return fail(KM_E_INVALID, "km_tile_describe: op must be 0 or 1");
@@ -780,6 +794,7 @@ km_status km_tile_describe(int32_t op, int32_t tile, km_tile_info* out) {
     out->trace_quads = op == 0 ? 0 : (level > 0 ? level : S.max_quads);
     out->shape = shape;
     out->level = level;
+    out->lds16 = op == 0 ? kMigrateLds16[level] : 0;
     return KM_OK;
 }
 
@@ -851,7 +866,7 @@ static km_status tune_impl(int32_t op, const km_traces* traces, const km_grid* g
     st = KM_OK;
     // every compiled shape at every variant level that applies to it
     for (int sh = 0; sh < shape_count(op) && st == KM_OK; ++sh) {
-        for (int lv = 0; lv < kTileLevels && st == KM_OK; ++lv) {
+        for (int lv = 0; lv < level_count(op) && st == KM_OK; ++lv) {
             int d_shape = 0, d_level = 0;
             const int tile = sh + kTileLevelStride * lv;
             if (!decode_tile(op, tile, &d_shape, &d_level)) continue;
@@ -953,6 +968,15 @@ km_status batch_plan(const km_problem* probs, int32_t n, int32_t tile, const cha
                              &B.tile);
     if (st != KM_OK) return st;
     B.shape = B.tile % kTileLevelStride;
+    {
+        // the batched kernels stage floats: a tuned 16-bit staging tile becomes
+        // its float-staging level, a requested one is refused
+        const int lv = B.tile / kTileLevelStride;
+        if (kMigrateLds16[lv]) {
+            if (tile >= 0) return fail(KM_E_UNSUPPORTED, "%s: 16-bit staging tiles are not batched", who);
+            B.tile = B.shape + kTileLevelStride * kMigrateFloatLevel[lv];
+        }
+    }
     const km::TileShape& S = km::migrate_shape(B.shape);
     B.has_tf = probs[0].traces.t_first != 0.0 ? 1 : 0;
     B.weight = probs[0].weight.kind;

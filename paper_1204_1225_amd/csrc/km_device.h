@@ -85,6 +85,9 @@ struct Params {
     // one-way amplitudes of the table kinds (same layout and size as ttab), or
     // NULL: W = A_s A_r instead of 1
     const float* tamp;
+    // migrate: 16-bit traces staged in LDS as their 16-bit storage (the S16
+    // kernels), widened and scaled per pair
+    int32_t s16;
 };
 
 // Raw buffer resources (gfx9 family: no format conversion, no swizzle).

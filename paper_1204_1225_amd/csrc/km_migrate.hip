@@ -47,6 +47,78 @@ __device__ __forceinline__ void stage_window_f(const Params& P, int64_t j, int l
     }
 }
 
+// 16-bit storage bits of sample k of trace row src (zero bits, +0, outside the record).
+__device__ __forceinline__ uint32_t sample_bits16(const Params& P, const uint16_t* src, int k) {
+    return (k >= 0 && k < P.nt) ? static_cast<uint32_t>(src[k]) : 0u;
+}
+
+// Stage the window of samples lo .. lo + len - 1 of trace j as len - 1 packed
+// pairs dst[e] = bits(D[lo + e]) | bits(D[lo + e + 1]) << 16 of the 16-bit
+// storage (half the LDS of float (sample, difference) pairs); the reads widen
+// them and apply the trace's scale.  One wavefront.
+__device__ __forceinline__ void stage_window_16p(const Params& P, int64_t j, int lo, int len, uint32_t* dst, int lane) {
+    const uint16_t* src = static_cast<const uint16_t*>(P.data) + j * P.stride;
+    for (int e0 = 0; e0 < len - 1; e0 += 2 * kLanes) {
+        uint32_t a[2], b[2];
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            a[u] = 0u;
+            b[u] = 0u;
+            if (e < len - 1) {
+                a[u] = sample_bits16(P, src, lo + e);
+                b[u] = sample_bits16(P, src, lo + e + 1);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            if (e < len - 1) dst[e] = a[u] | (b[u] << 16);
+        }
+    }
+}
+
+// Stage the window of samples lo .. lo + len - 1 of trace j as len 16-bit
+// storage values (half the LDS of float samples: the whole-record windows of
+// table traveltimes).  One wavefront.
+__device__ __forceinline__ void stage_window_16(const Params& P, int64_t j, int lo, int len, uint16_t* dst, int lane) {
+    const uint16_t* src = static_cast<const uint16_t*>(P.data) + j * P.stride;
+    for (int e0 = 0; e0 < len; e0 += 4 * kLanes) {
+        uint32_t v[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            v[u] = e < len ? sample_bits16(P, src, lo + e) : 0u;
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int e = e0 + u * kLanes + lane;
+            if (e < len) dst[e] = static_cast<uint16_t>(v[u]);
+        }
+    }
+}
+
+// The two samples of a packed pair (low half: the first), widened.
+template <int DT>
+__device__ __forceinline__ void widen_pair(uint32_t w, float& a, float& b) {
+    if (DT == BF16) {
+        a = __uint_as_float(w << 16);
+        b = __uint_as_float(w & 0xffff0000u);
+    } else {
+        a = widen16(w & 0xffffu, DT);
+        b = widen16(w >> 16, DT);
+    }
+}
+
+// Samples k and k + 1 of a window staged by stage_window_16, k counted in
+// 16-bit values from s: the two aligned words that hold them, funnel-shifted
+// (for even k the second word is not used; it is still inside the
+// workgroup's LDS, as the trace block's slot records follow the windows).
+__device__ __forceinline__ uint32_t read_pair16(const uint32_t* s, int k) {
+    const uint32_t w0 = s[k >> 1], w1 = s[(k >> 1) + 1];
+    return __builtin_amdgcn_alignbit(w1, w0, static_cast<uint32_t>(k & 1) << 4);
+}
+
 // Stage, for positions lo .. lo + len - 1 of trace j, the double running sum
 // I2[n] = sum_{m <= n} sum_{k <= m} D[k] (float64, from position lo; D zero
 // outside [0, nt)): the anti-alias triangles are second differences of it.
@@ -124,6 +196,25 @@ __device__ __forceinline__ void mig_pair(float A0, float B0, float A1, float B1,
     acc1 = (WK == W_COSCOS) ? fmaf(v1, p1.r, acc1) : acc1 + v1;
 }
 
+// mig_pair on a window staged as packed 16-bit pairs (stage_window_16p): the
+// pair is widened and interpolated, and the trace's scale joins the weight.
+template <bool TF, int WK, int DT>
+__device__ __forceinline__ void mig_pair16(float A0, float B0, float A1, float B1, float hs2, float hr2, float hm,
+                                           const uint32_t* row, float scl, float tfo, float wlo, float whi,
+                                           float R0, float R1, float& acc0, float& acc1) {
+    const Pair p0 = eval_pair<TF, WK, true>(A0, B0, hs2, hr2, tfo, wlo, whi);
+    const Pair p1 = eval_pair<TF, WK, true>(A1, B1, hs2, hr2, tfo, wlo, whi);
+    float a0, b0, a1, b1;
+    widen_pair<DT>(row[p0.i], a0, b0);
+    widen_pair<DT>(row[p1.i], a1, b1);
+    float v0 = fmaf(p0.f, b0 - a0, a0);
+    float v1 = fmaf(p1.f, b1 - a1, a1);
+    v0 = (hm <= R0) ? v0 : 0.0f;
+    v1 = (hm <= R1) ? v1 : 0.0f;
+    acc0 = fmaf(v0, (WK == W_COSCOS) ? p0.r * scl : scl, acc0);
+    acc1 = fmaf(v1, (WK == W_COSCOS) ? p1.r * scl : scl, acc1);
+}
+
 // mig_pair with table traveltimes (W = A_s A_r with amplitude tables, else 1):
 // iz0, iz1 are the lane's depths of the two slots, clamped into the table.  LAT: laterally varying tables, C the
 // lane's column on the node grid.
@@ -144,6 +235,25 @@ __device__ __forceinline__ void mig_pair_table(const Params& P, TLeg Ls, TLeg Lr
     // r = 1 without amplitude tables: the same bits as acc + v
     acc0 = fmaf(v0, p0.r, acc0);
     acc1 = fmaf(v1, p1.r, acc1);
+}
+
+// mig_pair_table on a window staged as 16-bit values (stage_window_16): s is
+// the trace block's windows as words, rb the row's offset in 16-bit values.
+template <bool TF, bool LAT, int DT>
+__device__ __forceinline__ void mig_pair_table16(const Params& P, TLeg Ls, TLeg Lr, LCol C, int iz0, int iz1, float hm,
+                                                 const uint32_t* s, int rb, float scl, float tfo, float wlo, float whi,
+                                                 float R0, float R1, float& acc0, float& acc1) {
+    const Pair p0 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz0, tfo, wlo, whi, C);
+    const Pair p1 = eval_pair_table<TF, true, LAT>(P, Ls, Lr, iz1, tfo, wlo, whi, C);
+    float a0, b0, a1, b1;
+    widen_pair<DT>(read_pair16(s, rb + p0.i), a0, b0);
+    widen_pair<DT>(read_pair16(s, rb + p1.i), a1, b1);
+    float v0 = fmaf(p0.f, b0 - a0, a0);
+    float v1 = fmaf(p1.f, b1 - a1, a1);
+    v0 = (hm <= R0) ? v0 : 0.0f;
+    v1 = (hm <= R1) ? v1 : 0.0f;
+    acc0 = fmaf(v0, p0.r * scl, acc0);
+    acc1 = fmaf(v1, p1.r * scl, acc1);
 }
 
 // One slot with the extended-precision time (eval_pair_ext): leg lengths in
@@ -225,9 +335,11 @@ __device__ __forceinline__ void mig_slot_aa(float A, float B, float hs2, float h
 // n - 1 pairs], per block slot the trace geometry (float4) and (float offset,
 // first sample, last sample, trace - bin start) (int4) [P.tb each], the aperture values [KS * 16], the tile box
 // [4 per wavefront] and the candidates of one pass [NW * 4 x (int2, float4)].
-template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR, bool PX = false>
+template <int NW, int CWQ, int KS, bool TF, int WK, bool RREG, int TT = TT_DSR, bool PX = false, int S16 = 0>
 __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, int zc, float* lds) {
     static_assert(!(PX && TT == TT_AA), "no extended-precision anti-alias kernels");
+    // S16: the 16-bit storage type (BF16 or F16) staged as it is, 0 for float staging
+    static_assert(!(S16 && (PX || TT == TT_AA)), "16-bit staging: float32 time, no anti-alias filter");
     static_assert(KS % 2 == 0, "slots are evaluated in pairs");
     constexpr int NG = NW * kGroupsPerWave;  // candidate traces per pass: one per 16-lane group
     static_assert(NG <= kLanes && NW <= kBoxFloats / 4, "at most 16 wavefronts");
@@ -243,8 +355,10 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
     // of a few hundred samples), plain samples for the whole-record windows of
     // table times (half the LDS per trace), float64 double running sums with
     // the anti-alias filter
-    constexpr bool PAIRS = TT == TT_DSR;
+    constexpr bool PAIRS = TT == TT_DSR && !S16;
     constexpr bool AA = TT == TT_AA;
+    constexpr bool P16 = TT == TT_DSR && S16;  // packed 16-bit pairs
+    constexpr bool T16 = is_table(TT) && S16;  // 16-bit samples
     // anti-aliasing: largest half-width, and the reach of a pair's reads around
     // its sample (L + 2 below, L + 2 above counting the pair's second sample)
     const int lmax = AA ? P.aa_max : 0;
@@ -444,11 +558,13 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             __syncthreads();
             // Every wavefront takes the same decision: candidates 0 .. k - 1 join the
             // block (the others do not fit and open the next one).
-            int clen = 0, cwl = 0;  // LDS floats of the candidate's window
+            int clen = 0, cwl = 0, cn = 0;  // LDS floats of the candidate's window, its first and number of samples
             if (lane < NG) {
                 const int2 c = sCand[lane];
                 cwl = c.x;
-                clen = c.y > 0 ? (AA ? 2 * c.y : PAIRS ? 2 * (c.y - 1) : c.y) : 0;
+                cn = c.y;
+                clen = c.y > 0 ? (AA ? 2 * c.y : T16 ? (c.y + 1) / 2 : P16 ? c.y - 1 : PAIRS ? 2 * (c.y - 1) : c.y)
+                               : 0;
             }
             int plen = clen, pcnt = clen > 0 ? 1 : 0;  // inclusive prefix sums
 #pragma unroll
@@ -465,9 +581,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             if (wave == 0 && lane < k && clen > 0) {
                 const int slot = nb + pcnt - 1;
                 sGeo[slot] = sCandGeo[lane];
-                sMeta[slot] = make_int4(used + plen - clen, cwl,
-                                        cwl + (AA ? clen / 2 - 1 : PAIRS ? clen / 2 : clen - 1),
-                                        static_cast<int>(jn + lane - lo));
+                sMeta[slot] = make_int4(used + plen - clen, cwl, cwl + cn - 1, static_cast<int>(jn + lane - lo));
             }
             if (k > 0) {
                 nb += __builtin_amdgcn_readlane(pcnt, k - 1);
@@ -481,6 +595,8 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
         for (int t = wave; t < nb; t += NW) {
             const int4 mt = sMeta[t];
             if (AA) stage_window_i2(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<double*>(sTr + mt.x), lane);
+            else if (T16) stage_window_16(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<uint16_t*>(sTr + mt.x), lane);
+            else if (P16) stage_window_16p(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<uint32_t*>(sTr + mt.x), lane);
             else if (PAIRS) stage_window(P, lo + mt.w, mt.y, mt.z - mt.y + 1, reinterpret_cast<float2*>(sTr + mt.x), lane);
             else stage_window_f(P, lo + mt.w, mt.y, mt.z - mt.y + 1, sTr + mt.x, lane);
         }
@@ -493,7 +609,10 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
             const int ts = min(t0 + d, nb - 1);
             const float4 sr = sGeo[ts];
             const int4 mt = sMeta[ts];
-            const int lrow = (PAIRS || AA ? mt.x / 2 : mt.x) - mt.y - koff;  // in pairs / doubles / floats
+            // in pairs / doubles / 16-bit samples / floats or packed 16-bit pairs
+            const int lrow = (PAIRS || AA ? mt.x / 2 : T16 ? 2 * mt.x : mt.x) - mt.y - koff;
+            // 16-bit staging: the trace's scale, applied per pair with the weight
+            const float lscl = (S16 && P.scale) ? P.scale[lo + mt.w] : 1.0f;
             const float lwlo = static_cast<float>(mt.y + koff + (AA ? lmax + 2 : 0));
             const float lwhi = static_cast<float>(mt.z - 1 + koff - (AA ? lmax + 1 : 0));
 #pragma unroll
@@ -549,6 +668,7 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                     }
                     const int rb = __builtin_amdgcn_readlane(lrow, tc);
                     const float wlo = uniform_read(lwlo, tc);
+                    const float scl = S16 ? uniform_read(lscl, tc) : 1.0f;
                     // max(hs2, hr2): one v_max (fmaxf would first quiet both inputs)
                     float hm;
                     asm("v_max_f32 %0, %1, %2" : "=v"(hm) : "v"(hs2), "v"(hr2));
@@ -574,8 +694,13 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                                 const int iz1 = min(max(z0 + (k + 1) * kGroup + d, 0), P.nz - 1);
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair_table<TF, true, LAT>(P, Ls, Lr, lc[q], iz0, iz1, hm, sTr + rb, tfo, wlo, whi, R0,
-                                                              R1, acc[q][k], acc[q][k + 1]);
+                                if (S16)
+                                    mig_pair_table16<TF, LAT, S16>(P, Ls, Lr, lc[q], iz0, iz1, hm,
+                                                                   reinterpret_cast<const uint32_t*>(sTr), rb, scl,
+                                                                   tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
+                                else
+                                    mig_pair_table<TF, true, LAT>(P, Ls, Lr, lc[q], iz0, iz1, hm, sTr + rb, tfo, wlo,
+                                                                  whi, R0, R1, acc[q][k], acc[q][k + 1]);
                             }
                         }
                     } else if (AA) {
@@ -613,9 +738,14 @@ __device__ __forceinline__ void migrate_tile(const Params& P, int b, int tile, i
                             if ((any >> k) & 3ull) {
                                 const float R0 = RREG ? T.R[k] : sR[k * kGroup + d];
                                 const float R1 = RREG ? T.R[k + 1] : sR[(k + 1) * kGroup + d];
-                                mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
-                                                             reinterpret_cast<const float2*>(sTr) + rb,
-                                                             tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
+                                if (S16)
+                                    mig_pair16<TF, WK, S16>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
+                                                            reinterpret_cast<const uint32_t*>(sTr) + rb, scl, tfo,
+                                                       wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
+                                else
+                                    mig_pair<TF, WK, true, true>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], hs2, hr2, hm,
+                                                                 reinterpret_cast<const float2*>(sTr) + rb,
+                                                                 tfo, wlo, whi, R0, R1, acc[q][k], acc[q][k + 1]);
                             }
                         }
                     }
@@ -668,11 +798,11 @@ __device__ __forceinline__ void zero_tile(const Params& P, int b, int tile, int 
 // The extended-precision square-root kernels are held to 4 wavefronts per SIMD
 // (128 VGPRs, some spilled) so that two 8-wavefront workgroups share a CU:
 // 2.28 s against 3.29 s at their natural 165 VGPRs on the 3D survey.
-template <int NW, int CWQ, int KS, bool TF, int WK, int TT = TT_DSR, bool PX = false>
+template <int NW, int CWQ, int KS, bool TF, int WK, int TT = TT_DSR, bool PX = false, int S16 = 0>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(PX && TT == TT_DSR && KS <= 8 ? 4 : 1)))
 void migrate_kernel(Params P) {
     extern __shared__ float lds[];
-    migrate_tile<NW, CWQ, KS, TF, WK, true, TT, PX>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
+    migrate_tile<NW, CWQ, KS, TF, WK, true, TT, PX, S16>(P, blockIdx.z, blockIdx.x, blockIdx.y, lds);
 }
 
 // Batched persistent form: work items (problem, bin, column tile, depth
@@ -717,10 +847,41 @@ static hipError_t launch_migrate_dsr(const Params& P, dim3 grid, dim3 block, siz
     return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_DSR, PX>, grid, block, lds, s, P);
 }
 
+// The 16-bit staging kernels (float32 time), per storage type: square-root
+// times per weight and t_first case, the two table kinds per t_first case.
+template <int NW, int CWQ, int KS, int DT>
+static hipError_t launch_migrate_s16_dt(const Params& P, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    if (P.ttab) {
+        if (P.n_gx > 0) {
+            if (P.has_tf)
+                return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_LTABLE, false, DT>, grid, block, lds, s, P);
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_LTABLE, false, DT>, grid, block, lds, s, P);
+        }
+        if (P.has_tf)
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_TABLE, false, DT>, grid, block, lds, s, P);
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_TABLE, false, DT>, grid, block, lds, s, P);
+    }
+    if (P.has_tf) {
+        if (P.weight == W_COSCOS)
+            return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_COSCOS, TT_DSR, false, DT>, grid, block, lds, s, P);
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, true, W_UNIT, TT_DSR, false, DT>, grid, block, lds, s, P);
+    }
+    if (P.weight == W_COSCOS)
+        return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_COSCOS, TT_DSR, false, DT>, grid, block, lds, s, P);
+    return launch_with_lds(migrate_kernel<NW, CWQ, KS, false, W_UNIT, TT_DSR, false, DT>, grid, block, lds, s, P);
+}
+
+template <int NW, int CWQ, int KS>
+static hipError_t launch_migrate_s16(const Params& P, dim3 grid, dim3 block, size_t lds, hipStream_t s) {
+    if (P.dtype == BF16) return launch_migrate_s16_dt<NW, CWQ, KS, BF16>(P, grid, block, lds, s);
+    return launch_migrate_s16_dt<NW, CWQ, KS, F16>(P, grid, block, lds, s);
+}
+
 template <int NW, int CWQ, int KS>
 static hipError_t launch_migrate_shape(const Params& P, hipStream_t s) {
     dim3 grid(P.n_coltiles, P.n_zchunks, P.n_bins), block(NW * 64);
     const size_t lds = lds_bytes(P, KS);
+    if (P.s16) return launch_migrate_s16<NW, CWQ, KS>(P, grid, block, lds, s);  // the host checked the kind
     if (P.ttab && P.n_gx > 0) {  // laterally varying tables: W = 1
         if (P.prec) {
             if (P.has_tf)

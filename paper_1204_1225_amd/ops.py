@@ -380,13 +380,17 @@ def tile_levels(op: int) -> int:
     return int(_lib.load().km_tile_levels(op))
 
 
-def tiles(op: int):
-    """Every valid tile of op: compiled shape + 64 * level."""
+def tiles(op: int, dp: Optional["DeviceProblem"] = None):
+    """Every valid tile of op: compiled shape + 64 * level.  Given a problem,
+    only the tiles that apply to it: the 16-bit staging levels of migrate take
+    16-bit traces with float32 time and no anti-alias filter."""
     out = []
+    s16_ok = dp is None or (dp.dtype != "f32" and dp.prec == "fp32" and dp.aa is None)
     for lv in range(tile_levels(op)):
         for sh in range(tile_count(op)):
             t = sh + 64 * lv
-            if _lib.load().km_tile_describe(op, t, ctypes.byref(KmTileInfo())) == _lib.KM_OK:
+            info = KmTileInfo()
+            if _lib.load().km_tile_describe(op, t, ctypes.byref(info)) == _lib.KM_OK and (s16_ok or not info.lds16):
                 out.append(t)
     return out
 

@@ -42,7 +42,7 @@ def test_exports_every_declared_symbol(lib):
 def test_abi_version_and_limits(lib):
     from paper_1204_1225_amd import _lib
 
-    assert lib.km_abi_version() == _lib.ABI_VERSION == 3
+    assert lib.km_abi_version() == _lib.ABI_VERSION == 4
     assert lib.km_max_samples() >= 20000
     assert lib.km_tile_count(0) >= 2 and lib.km_tile_count(1) >= 2
     assert lib.km_tile_count(7) == 0
@@ -154,17 +154,24 @@ def test_tiles_encode_shape_and_level(lib):
     from paper_1204_1225_amd import _lib
 
     info = _lib.KmTileInfo()
+    assert (lib.km_tile_levels(0), lib.km_tile_levels(1)) == (6, 4)
     for op in (0, 1):
-        assert lib.km_tile_levels(op) == 4
         for sh in range(lib.km_tile_count(op)):
             assert lib.km_tile_describe(op, sh, ctypes.byref(info)) == _lib.KM_OK
-            assert (info.shape, info.level) == (sh, 0)
-    # migrate levels scale the trace block's budget (at most 160 KiB)
+            assert (info.shape, info.level, info.lds16) == (sh, 0, 0)
+    # migrate levels scale the trace block's budget (at most 160 KiB); levels
+    # 4 and 5 stage 16-bit traces with budgets 1 and 2
     assert lib.km_tile_describe(0, 2, ctypes.byref(info)) == _lib.KM_OK
     base = info.lds_budget
     assert lib.km_tile_describe(0, 2 + 64, ctypes.byref(info)) == _lib.KM_OK and info.lds_budget == base // 2
     assert lib.km_tile_describe(0, 2 + 192, ctypes.byref(info)) == _lib.KM_OK and info.lds_budget == 2 * base
-    assert lib.km_tile_describe(0, 2 + 256, ctypes.byref(info)) == _lib.KM_E_INVALID
+    assert info.lds16 == 0
+    assert lib.km_tile_describe(0, 2 + 256, ctypes.byref(info)) == _lib.KM_OK
+    assert (info.lds_budget, info.lds16, info.level) == (base, 1, 4)
+    assert lib.km_tile_describe(0, 2 + 320, ctypes.byref(info)) == _lib.KM_OK
+    assert (info.lds_budget, info.lds16) == (2 * base, 1)
+    assert lib.km_tile_describe(0, 2 + 384, ctypes.byref(info)) == _lib.KM_E_INVALID
+    assert lib.km_tile_describe(1, 3 + 256, ctypes.byref(info)) == _lib.KM_E_INVALID
     # demigrate levels pick the trace quads per workgroup, up to the shape's
     assert lib.km_tile_describe(1, 3 + 64, ctypes.byref(info)) == _lib.KM_OK and info.trace_quads == 1
     assert lib.km_tile_describe(1, 3 + 128, ctypes.byref(info)) == _lib.KM_E_INVALID  # one-quad shape
@@ -403,3 +410,36 @@ def test_injected_launch_failure_is_reported(lib, monkeypatch):
     monkeypatch.setenv("KM_FAULT_INJECT", "other")
     assert lib.kirchhoff_migrate(ctypes.byref(t_bad), ctypes.byref(g2), ctypes.byref(tt2), ctypes.byref(w2), p, 0,
                                  2, None) == _lib.KM_E_INVALID
+
+
+def test_16bit_staging_tiles_need_16bit_float32_time_plain_problems(lib, monkeypatch):
+    # Host validation only (the pointers are never used): migrate levels 4 and
+    # 5 take KM_BF16 / KM_F16 traces with float32 time and no anti-alias
+    # filter; the batched calls refuse them.  With KM_FAULT_INJECT=launch a
+    # valid call reaches its launch (KM_E_HIP) without touching a GPU.
+    from paper_1204_1225_amd import _lib
+
+    p = ctypes.c_void_p(0x1000)
+    for tile in (2 + 256, 0 + 320):
+        t, g, tt, w = _args(_lib)
+        st = lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), p, 0, tile,
+                                   None)
+        assert st == _lib.KM_E_UNSUPPORTED and b"16-bit" in lib.km_last_error()
+        t, g, tt, w = _args(_lib, t__dtype=_lib.KM_BF16, t__scale=p, tt__time_precision=_lib.KM_TIME_EXTENDED)
+        st = lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), p, 0, tile,
+                                   None)
+        assert st == _lib.KM_E_UNSUPPORTED and b"16-bit" in lib.km_last_error()
+        t, g, tt, w = _args(_lib, t__dtype=_lib.KM_F16, t__scale=p)
+        aa = _lib.KmAntialias(dx=10.0, dy=10.0, max_half=2)
+        st = lib.kirchhoff_migrate_aa(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w),
+                                      ctypes.byref(aa), p, 0, tile, None)
+        assert st == _lib.KM_E_UNSUPPORTED and b"16-bit" in lib.km_last_error()
+        pr = (_lib.KmProblem * 1)()
+        pr[0] = _lib.KmProblem(traces=t, grid=g, tt=tt, weight=w, image=p)
+        assert lib.km_batch_migrate_static(pr, 1, tile, None) == _lib.KM_E_UNSUPPORTED
+        assert b"not batched" in lib.km_last_error()
+        monkeypatch.setenv("KM_FAULT_INJECT", "launch")
+        st = lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), ctypes.byref(tt), ctypes.byref(w), p, 0, tile,
+                                   None)
+        assert st == _lib.KM_E_HIP and b"injected" in lib.km_last_error()
+        monkeypatch.delenv("KM_FAULT_INJECT")

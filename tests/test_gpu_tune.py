@@ -41,7 +41,7 @@ def test_every_tile_level_matches_oracle(ops, oracle_lib, prec, tol):
     ref_d = oracle_lib.demigrate(p, m)
     mt = torch.from_numpy(m).cuda()
     worst = 0.0
-    for tile in ops.tiles(0):
+    for tile in ops.tiles(0, dp):
         e = rel_l2(ops.migrate(dp, tile=tile).cpu().numpy(), ref)
         worst = max(worst, e)
         assert e <= tol, tile
@@ -49,8 +49,10 @@ def test_every_tile_level_matches_oracle(ops, oracle_lib, prec, tol):
         e = rel_l2(ops.demigrate(dp, mt, tile=tile).cpu().numpy(), ref_d)
         worst = max(worst, e)
         assert e <= tol, tile
-    print(f"{prec}: {len(ops.tiles(0))} migrate and {len(ops.tiles(1))} demigrate tiles, worst rel L2 {worst:.3e}")
-    assert len(ops.tiles(0)) > ops.tile_count(0) and len(ops.tiles(1)) > ops.tile_count(1)
+    print(f"{prec}: {len(ops.tiles(0, dp))} migrate and {len(ops.tiles(1))} demigrate tiles, "
+          f"worst rel L2 {worst:.3e}")
+    assert len(ops.tiles(0, dp)) > ops.tile_count(0) and len(ops.tiles(1)) > ops.tile_count(1)
+    assert len(ops.tiles(0)) > len(ops.tiles(0, dp))  # the 16-bit staging levels need 16-bit traces
 
 
 @pytest.mark.parametrize("kind", ["plain", "table", "ltable"])
