@@ -94,3 +94,23 @@ def test_tune_pick_persist_reload(ops, oracle_lib, tmp_path, kind):
         assert r.stdout.split()[-2:] == [str(t0), str(t1)]
     finally:
         os.environ.pop("KM_TUNE_CACHE", None)
+
+
+def test_tune_covers_16bit_staging_for_16bit_traces(ops, oracle_lib, tmp_path):
+    # km_tune on bf16 traces with float32 time searches the 16-bit staging
+    # levels too; the tile it records is used by tile = -1 and matches the
+    # oracle on the dequantised samples.
+    os.environ["KM_TUNE_CACHE"] = str(tmp_path / "tune.json")
+    try:
+        p = survey.make_random(65, n_traces=150, n_t=380, nx=17, ny=3, nz=70, n_bins=2, dz=10.0)
+        dp = ops.to_device(p, dtype="bf16")
+        assert len(ops.tiles(0, dp)) == ops.tile_count(0) * ops.tile_levels(0)
+        _, _, deq = survey.quantise(p.data, "bf16")
+        img = torch.empty(dp.image_shape, device="cuda")
+        t0, ms0 = ops.tune(0, dp, img, reps=1)
+        print(f"bf16: tuned migrate tile {t0} ({ms0:.3f} ms), {ops.tile_describe(0, t0)}")
+        assert ops.tune_lookup(0, dp) == t0
+        assert torch.equal(ops.migrate(dp), ops.migrate(dp, tile=t0))
+        assert rel_l2(ops.migrate(dp).cpu().numpy(), oracle_lib.migrate(p, deq)) <= 1e-5
+    finally:
+        os.environ.pop("KM_TUNE_CACHE", None)
