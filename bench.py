@@ -48,9 +48,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "71775327d88fbfb46ba92c5f902df57bb3ee99f18d92ebcf10463c24b60f0c8e",
-    "migrate": 9.1788e10,
-    "demigrate": 3.0074e12,
+    "sources_sha256": "6eb2dd8a81697ee42d6e8e8d8777cadf001d65247119f82a0cb536d08e1f8e66",
+    "migrate": 9.1020e10,
+    "demigrate": 3.0078e12,
 }
 
 
