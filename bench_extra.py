@@ -8,7 +8,8 @@ survey3d_ext: the 3D survey with the extended-precision total time
     the same GPU, and each one's sampled parity against the oracle.
 
 survey3d_bf16 / survey3d_f16: the 3D survey with 16-bit trace storage
-    (per-trace scale), migrate-only throughput next to float32 on the same GPU.
+    (per-trace scale), migrate-only throughput next to float32 on the same GPU,
+    and the time of every tile that keeps the samples as 16-bit values in LDS.
 line2d_vz: the 2D v(z) adjoint pair (61 440 traces x 2000 samples, image
     1024 x 800 in 32 bins): migrate and demigrate throughput and the float32
     dot-product test.
@@ -74,10 +75,19 @@ def _survey16(kind, steps, warmup, dev):
     img = torch.empty(dp.image_shape, device=dev)
     ms32 = _time(lambda: ops.migrate(dp, image=img), steps, warmup)
     ms16 = _time(lambda: ops.migrate(dq, image=img), steps, warmup)
+    # the 16-bit staging tiles (samples kept as 16-bit values in LDS), one timed
+    # call each after one untimed
+    lds16 = {}
+    for t in ops.tiles(0, dq):
+        if ops.tile_describe(0, t)["lds16"]:
+            lds16[t] = _time(lambda: ops.migrate(dq, image=img, tile=t), 1, 1)
+    best = min(lds16, key=lds16.get)
     return {"workload": f"survey3d_{kind}", "metric": "G contributions/s (migrate)", "pairs_in_aperture": n_ap,
             "ms_f32": round(ms32, 3), f"ms_{kind}": round(ms16, 3),
             "gcps_f32": round(n_ap / ms32 / 1e6, 3), f"gcps_{kind}": round(n_ap / ms16 / 1e6, 3),
-            "trace_bytes_f32": int(host.nbytes), f"trace_bytes_{kind}": int(bits.nbytes + sig.nbytes)}
+            "trace_bytes_f32": int(host.nbytes), f"trace_bytes_{kind}": int(bits.nbytes + sig.nbytes),
+            "lds16_tiles_ms": {str(t): round(v, 3) for t, v in lds16.items()},
+            f"ms_{kind}_lds16_best": round(lds16[best], 3), "lds16_best_tile": best}
 
 
 def _line2d_vz(steps, warmup, dev):
