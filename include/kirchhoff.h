@@ -402,7 +402,10 @@ km_status km_tune_ltable(int32_t op, const km_traces* traces, const km_grid* gri
 
 /* The class cache of km_tune.  kind: 0 = square-root times, 1 = table times,
  * 2 = anti-alias filter, 3 = laterally varying tables.  km_tune_lookup returns -1 when nothing is recorded;
- * km_tune_record stores (and persists) a tile with its time. */
+ * km_tune_record stores (and persists) a tile with its time, and returns KM_E_INVALID for a tile out of range
+ * or a 16-bit staging tile (migrate levels 4, 5) for a class of KM_F32 traces, KM_TIME_EXTENDED or kind 2.
+ * Calls with tile = -1 take a recorded tile only if it applies to their class (a cache file may come from
+ * another build); otherwise the library's default. */
 int32_t km_tune_lookup(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,
                        int32_t n_samples);
 km_status km_tune_record(int32_t op, int32_t dtype, int32_t kind, int32_t time_precision, int32_t nz,

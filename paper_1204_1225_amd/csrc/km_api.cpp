@@ -384,7 +384,18 @@ int default_tile(int op, int kind) {
     return kind == KIND_TABLE ? 1 : 3;
 }
 
-// The caller's tile, else the tuned tile of this problem's class, else the default.
+// Whether a tile can run problems of a class: a tile of op, and a 16-bit
+// staging level only for 16-bit traces with float32 time and no anti-alias
+// filter.
+bool tile_applies(int op, int tile, int dtype, int kind, int prec) {
+    int shape = 0, level = 0;
+    if (!decode_tile(op, tile, &shape, &level)) return false;
+    if (op == 0 && kMigrateLds16[level]) return dtype != KM_F32 && prec != KM_TIME_EXTENDED && kind != KIND_AA;
+    return true;
+}
+
+// The caller's tile, else the tuned tile of this problem's class (if it still
+// applies: a cache file may come from another build), else the default.
 km_status pick_tile(int op, int tile, int dtype, int kind, int prec, int nz, int nt, int* out) {
     if (tile >= 0) {
         int shape = 0, level = 0;
@@ -399,7 +410,7 @@ km_status pick_tile(int op, int tile, int dtype, int kind, int prec, int nz, int
         std::lock_guard<std::mutex> lk(g_tune_mu);
         tune_load_locked();
         auto it = g_tune.find(key);
-        if (it != g_tune.end()) {
+        if (it != g_tune.end() && tile_applies(op, it->second.tile, dtype, kind, prec)) {
             *out = it->second.tile;
             return KM_OK;
         }
@@ -813,6 +824,8 @@ km_status km_tune_record(int32_t op, int32_t dtype, int32_t kind, int32_t time_p
     if (kind < KIND_DSR || kind > KIND_LTABLE) return fail(KM_E_INVALID, "km_tune_record: unknown kind %d", kind);
     int shape = 0, level = 0;
     if (!decode_tile(op, tile, &shape, &level)) return fail(KM_E_INVALID, "km_tune_record: tile out of range");
+    if (!tile_applies(op, tile, dtype, kind, time_precision))
+        return fail(KM_E_INVALID, "km_tune_record: tile %d stages 16-bit traces, which this class does not have", tile);
     const TuneKey key = tune_key(op, dtype, kind, time_precision, nz, n_samples);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_load_locked();

@@ -443,3 +443,37 @@ def test_16bit_staging_tiles_need_16bit_float32_time_plain_problems(lib, monkeyp
                                    None)
         assert st == _lib.KM_E_HIP and b"injected" in lib.km_last_error()
         monkeypatch.delenv("KM_FAULT_INJECT")
+
+
+def test_tuned_tiles_must_apply_to_their_class(lib, tmp_path):
+    # km_tune_record refuses a 16-bit staging tile for a class that cannot run
+    # it; a cache file holding one (written by hand here) is ignored by calls
+    # with tile = -1, which take the default and reach their launch (host only:
+    # KM_FAULT_INJECT=launch reports KM_E_HIP instead of launching).
+    import json
+    import subprocess
+    import sys
+
+    from paper_1204_1225_amd import _lib
+
+    assert lib.km_tune_record(0, _lib.KM_F32, 0, 0, 3, 10, 2 + 256, 1.0) == _lib.KM_E_INVALID
+    assert b"16-bit" in lib.km_last_error()
+    assert lib.km_tune_record(0, _lib.KM_BF16, 0, 1, 3, 10, 2 + 256, 1.0) == _lib.KM_E_INVALID
+    assert lib.km_tune_record(0, _lib.KM_BF16, 2, 0, 3, 10, 2 + 256, 1.0) == _lib.KM_E_INVALID
+    code = (f"import ctypes, json, sys; sys.path.insert(0, {ROOT!r})\n"
+            "from paper_1204_1225_amd import _lib\n"
+            "from tests.test_abi import _args\n"
+            "lib = _lib.load()\n"
+            "t, g, tt, w = _args(_lib)\n"
+            "p = ctypes.c_void_p(0x1000)\n"
+            "print(lib.km_tune_lookup(0, 0, 0, 0, 3, 10), lib.kirchhoff_migrate(ctypes.byref(t), ctypes.byref(g), "
+            "ctypes.byref(tt), ctypes.byref(w), p, 0, -1, None), lib.km_last_error().decode())\n")
+    path = tmp_path / "tune.json"
+    path.write_text(json.dumps({"format": "km_tune_cache", "version": 1, "entries": [
+        {"arch": "unknown", "op": 0, "dtype": 0, "kind": 0, "precision": 0, "nz_bucket": 1, "nt_bucket": 1,
+         "tile": 2 + 256, "ms": 1.0}]}))
+    env = dict(os.environ, KM_TUNE_CACHE=str(path), KM_FAULT_INJECT="launch", HIP_VISIBLE_DEVICES="")
+    r = subprocess.run([sys.executable, "-c", code], env=env, capture_output=True, text=True, timeout=120)
+    assert r.returncode == 0, r.stderr
+    looked, status, msg = r.stdout.split(maxsplit=2)
+    assert int(looked) == 2 + 256 and int(status) == _lib.KM_E_HIP and "injected" in msg
