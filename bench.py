@@ -48,9 +48,9 @@ C_TRANS = 3
 # with the SHA-256 of the kernel sources they were taken on, and reported only
 # while the sources still hash the same.
 PROFILED_TRAFFIC = {
-    "sources_sha256": "6eb2dd8a81697ee42d6e8e8d8777cadf001d65247119f82a0cb536d08e1f8e66",
-    "migrate": 9.1020e10,
-    "demigrate": 3.0078e12,
+    "sources_sha256": "e5ea4079e460b916bdb1a95d0865e4d2c6b3804cf54075c33e7ce3a29bbfa1e1",
+    "migrate": 9.0639e10,
+    "demigrate": 3.0069e12,
 }
 
 
