@@ -3,7 +3,9 @@ KM_BF16 / KM_F16 traces staged in LDS as their 16-bit storage, widened and
 scaled per sample read) against the FP64 oracle on the dequantised samples,
 on every compiled shape: square-root times with both weights and t_first != 0,
 curved-ray tables, lateral tables with amplitudes, and sampled points of the
-full 3D survey in bfloat16.  With unit scales they give the float-staging
+full 3D survey in bfloat16; the staged-window edge cases (strided rows, one-
+and two-sample records, 20000-sample records, whole-record fallback, short
+records under a deep image).  With unit scales they give the float-staging
 tiles' bits; a tuned 16-bit staging tile leaves the batched calls working."""
 import dataclasses
 import os
@@ -135,3 +137,49 @@ def test_tuned_s16_tile_leaves_batches_working(ops, oracle_lib, tmp_path):
         assert torch.equal(imgs[0], ops.migrate(dp, tile=2 + 64 * 3))
     finally:
         del os.environ["KM_TUNE_CACHE"]
+
+
+def check_s16(ops, oracle_lib, p, kind, what, tol=1e-5, data=None, scale=None):
+    """Every 16-bit staging tile against the oracle on the dequantised samples."""
+    dp = ops.to_device(p, dtype=kind)
+    _, _, deq = survey.quantise(p.data, kind)
+    ref = oracle_lib.migrate(p, deq)
+    for tile in s16_tiles(ops, dp):
+        img = ops.migrate(dp, tile=tile, data=data, dtype=kind if data is not None else None,
+                          scale=scale).cpu().numpy()
+        e = rel_l2(img, ref)
+        assert e <= tol, (what, kind, tile, e)
+    return ref
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_s16_edges(ops, oracle_lib, kind):
+    # strided 16-bit rows (stride 256 for 200 samples)
+    p = survey.make_random(124, n_traces=80, n_t=200, nx=10, ny=3, nz=50, n_bins=2, dz=10.0)
+    dp = ops.to_device(p, dtype=kind)
+    wide = torch.zeros((p.n_traces, 256), dtype=torch.int16, device="cuda")
+    wide[:, :200] = dp.data
+    check_s16(ops, oracle_lib, p, kind, "strided", data=wide[:, :200], scale=dp.scale)
+    # one- and two-sample records
+    for nt in (1, 2):
+        r = survey.make_random(125 + nt, n_traces=50, n_t=nt, nx=6, ny=1, nz=30, n_bins=1, dz=2.0, spread=0.0)
+        r.data[:] = 1.0
+        check_s16(ops, oracle_lib, r, kind, f"n_t = {nt}")
+    # 20000-sample records: few staged traces per block
+    q = survey.make_random(127, n_traces=12, n_t=20000, nx=8, ny=1, nz=40, n_bins=1, dz=50.0, dt=0.001)
+    check_s16(ops, oracle_lib, q, kind, "long record")
+    check_s16(ops, oracle_lib, survey.with_curved_ray_table(q, dh=25.0), kind, "long record, table")
+
+
+@pytest.mark.parametrize("kind", KINDS)
+def test_s16_staged_window_edges(ops, oracle_lib, kind):
+    # s2 < 0 on some depths: whole-record windows; a short record under a deep
+    # image: most times past the record end
+    p = survey.make_random(128, n_traces=300, n_t=500, nx=24, ny=3, nz=90, n_bins=2, dz=10.0, spread=400.0)
+    s2 = p.s2.copy()
+    s2[30:60] *= -0.01
+    ref = check_s16(ops, oracle_lib, dataclasses.replace(p, s2=s2), kind, "s2 < 0")
+    assert np.count_nonzero(ref[:, :, :, 30:60]) > 0
+    r = survey.make_random(129, n_traces=200, n_t=60, nx=20, ny=2, nz=200, n_bins=3, dz=10.0)
+    ref = check_s16(ops, oracle_lib, r, kind, "short record")
+    assert np.count_nonzero(ref) > 0 and np.all(ref[:, :, :, 150:] == 0)
