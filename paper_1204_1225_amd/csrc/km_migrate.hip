@@ -15,7 +15,9 @@
 // read of the staged (sample, difference) pair, the interpolation, the weight
 // and the lane's aperture mask.  Table times and the anti-alias filter use
 // the same blocks with their own staged forms (plain samples; float64 double
-// running sums, one slot at a time).
+// running sums, one slot at a time).  With 16-bit traces the S16 kernels keep
+// the samples' 16-bit storage in LDS instead (packed pairs; single samples for
+// table times) and widen them on read.
 #include "km_kernels.h"
 
 namespace km {
