@@ -227,3 +227,62 @@ def test_staged_windows_edges(ops, oracle_lib):
     # traces far outside every aperture: the image is exactly zero
     f = dataclasses.replace(s, src=s.src + np.float32(1.0e5), rec=s.rec + np.float32(1.0e5))
     assert np.all(ops.migrate(ops.to_device(f)).cpu().numpy() == 0)
+
+
+def _on_grid(p, step=1.0 / 16):
+    """p with source, receiver and image coordinates rounded to multiples of
+    `step` (so that shifting them by a power of two stays exact in float32)."""
+    def r(a):
+        return (np.round(np.asarray(a, np.float64) / step) * step).astype(np.float32)
+    return dataclasses.replace(p, src=r(p.src), rec=r(p.rec), x=r(p.x), y=r(p.y))
+
+
+def _shifted(p, sx, sy):
+    d = np.array([sx, sy], np.float32)
+    q = dataclasses.replace(p, src=p.src + d, rec=p.rec + d, x=p.x + np.float32(sx), y=p.y + np.float32(sy))
+    if getattr(q, "tgrid", None) is not None:
+        gx0, gy0, gdx, gdy = q.tgrid
+        q = dataclasses.replace(q, tgrid=(gx0 + sx, gy0 + sy, gdx, gdy))
+    return q
+
+
+@pytest.mark.parametrize("kind", ["plain", "table", "ltable", "aa"])
+def test_translation_invariance(ops, kind):
+    # Shifting every coordinate by (1024, -512) m is exact in float32 for
+    # coordinates on a 1/16 m grid; the kernels use only coordinate
+    # differences, so every migrate tile gives the same bits, the pair counts
+    # are equal, and the adjoint agrees up to its atomics' summation order.
+    p = _on_grid(survey.make_random(57, n_traces=160, n_t=400, nx=15, ny=4, nz=70, n_bins=3, dz=10.0,
+                                    t_first=0.02))
+    if kind == "table":
+        p = survey.with_curved_ray_table(p, dh=7.5)
+    if kind == "ltable":
+        p = survey.with_lateral_tables(p, survey.lateral_v0(1500.0, 0.3, -0.2, 1000.0, 2000.0), 0.5, 960.0,
+                                       1970.0, 60.0, 40.0, 3, 3, dh=7.5, amplitude=True)
+    if kind == "aa":
+        p = dataclasses.replace(p, aa=(12.5, 12.5, 6))
+    q = _shifted(p, 1024.0, -512.0)
+    assert np.array_equal(q.src - p.src, np.broadcast_to(np.float32([1024.0, -512.0]), p.src.shape))
+    dp, dq = ops.to_device(p), ops.to_device(q)
+    for tile in range(ops.tile_count(0)):
+        assert torch.equal(ops.migrate(dp, tile=tile), ops.migrate(dq, tile=tile)), (kind, tile)
+    if kind == "plain":
+        assert ops.count(dp) == ops.count(dq)
+    m = torch.from_numpy(survey.bandlimited_image(p, 58)).cuda()
+    for tile in range(ops.tile_count(1)):
+        a = ops.demigrate(dp, m, tile=tile).cpu().numpy()
+        b = ops.demigrate(dq, m, tile=tile).cpu().numpy()
+        assert rel_l2(b, a) <= 1e-6, (kind, tile)
+
+
+def test_bin_partition(ops):
+    # The offset bins partition the traces: the sum over bins of the binned
+    # image is the image of the same traces in one bin (float32 sums in
+    # another order), on every tile.
+    p = survey.make_random(59, n_traces=200, n_t=300, nx=12, ny=3, nz=60, n_bins=4, dz=10.0)
+    one = dataclasses.replace(p, bin=np.zeros_like(p.bin), n_bins=1)
+    dp, do = ops.to_device(p), ops.to_device(one)
+    for tile in range(ops.tile_count(0)):
+        a = ops.migrate(dp, tile=tile).double().sum(0).cpu().numpy()
+        b = ops.migrate(do, tile=tile)[0].double().cpu().numpy()
+        assert rel_l2(a, b) <= 1e-6, tile
