@@ -124,8 +124,18 @@ __device__ __forceinline__ void dem_pair_table_ext(const Params& P, TLegX Ls, TL
 template <bool TF, bool LAT, bool XF, typename Leg>
 __device__ __forceinline__ void dem_pair_table2(const Params& P, Leg Ls, Leg Lr, LCol C, int iz, double* row,
                                                 float wlo, float whi, float x0, float x1, bool act0, bool act1) {
-    const Dbl2 ts = table_time_pair<LAT, XF>(P, Ls.off, static_cast<double>(Ls.f), C, iz);
-    const Dbl2 tr = table_time_pair<LAT, XF>(P, Lr.off, static_cast<double>(Lr.f), C, iz);
+    double w0, w1;
+    if constexpr (XF) {
+        const Dbl2 ts = table_time_pair<LAT>(P, Ls.off, Ls.f, C, iz);
+        const Dbl2 tr = table_time_pair<LAT>(P, Lr.off, Lr.f, C, iz);
+        w0 = (ts.a + tr.a) * P.inv_dt;
+        w1 = (ts.b + tr.b) * P.inv_dt;
+    } else {
+        const TTime2 ts = table_time_pair2<LAT>(P, Ls.off, Ls.f, C, iz);
+        const TTime2 tr = table_time_pair2<LAT>(P, Lr.off, Lr.f, C, iz);
+        w0 = pair_time(P, ts.a, tr.a);
+        w1 = pair_time(P, ts.b, tr.b);
+    }
     float r0 = 1.0f, r1 = 1.0f;
     if (P.tamp) {
         const Flt2 as = table_amp_pair<LAT>(P, Ls.off, static_cast<float>(Ls.f), C, iz);
@@ -133,7 +143,6 @@ __device__ __forceinline__ void dem_pair_table2(const Params& P, Leg Ls, Leg Lr,
         r0 = as.a * ar.a;
         r1 = as.b * ar.b;
     }
-    double w0 = (ts.a + tr.a) * P.inv_dt, w1 = (ts.b + tr.b) * P.inv_dt;
     if (TF) {
         w0 = w0 + P.tf_off_d;
         w1 = w1 + P.tf_off_d;

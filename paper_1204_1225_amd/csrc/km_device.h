@@ -334,14 +334,28 @@ __device__ __forceinline__ double table_time_ext(const Params& P, TLegX L, int i
     return fma(L.f, b - a, a);
 }
 
-// Interpolated one-way time in float64: b - a of two adjacent float32 table
-// values is exact, the interpolation and the sum are float64, so the time
-// keeps the table's own precision (float32 rounding of the time in seconds
-// and again in samples would cost about 1e-5 of a band-limited result).
-__device__ __forceinline__ double table_time(const Params& P, TLeg L, int iz) {
+// Interpolated one-way time as a float32 table value (exact) plus a small
+// float32 increment: b - a of two adjacent table values is exact, and the
+// increment f (b - a), at most one row's difference (milliseconds), rounds to
+// about 1e-10 s.  The pair's time adds the two bases in float64 (exactly) and
+// then the legs' increments (pair_time), so it keeps the table's own precision
+// (float32 rounding of the whole time in seconds and again in samples would
+// cost about 1e-5 of a band-limited result) for a third of the float64 work
+// of a float64 interpolation.
+struct TTime {
+    float base, inc;
+};
+
+__device__ __forceinline__ TTime table_time(const Params& P, TLeg L, int iz) {
     const int vo = (L.off + iz) * 4;
     const float a = table_read(P, vo, 0), b = table_read(P, vo, 4 * P.nz);
-    return fma(static_cast<double>(L.f), static_cast<double>(b - a), static_cast<double>(a));
+    return TTime{a, L.f * (b - a)};
+}
+
+// The pair's total time in samples: (T_s + T_r) / dt, the bases summed exactly.
+__device__ __forceinline__ double pair_time(const Params& P, TTime s, TTime r) {
+    return (static_cast<double>(s.base) + static_cast<double>(r.base) + static_cast<double>(s.inc + r.inc)) *
+           P.inv_dt;
 }
 
 // Laterally varying tables: the image column's place on the node grid, off
@@ -381,21 +395,30 @@ __device__ __forceinline__ LCol lateral_col(const Params& P, float px, float py)
 // One-way time on the laterally varying tables: the interpolation in h of
 // table_time on the four nodes around the column, then in x, then in y, each
 // a + f (b - a) in float64 (equal node tables give table_time exactly).
-__device__ __forceinline__ double ltable_time(const Params& P, TLeg L, LCol C, int iz) {
+// The trilinear time as a base and an increment (as table_time): the base is
+// node (i, j)'s value a00 at row ih, and every other term is taken relative to
+// it in float32.  Neighbouring nodes' times at one depth and row lie within a
+// factor of two of each other, so their differences from a00 are exact; the
+// interpolated increments are small, as in table_time.  Equal nodes give
+// table_time's bits (every difference between nodes is 0).
+__device__ __forceinline__ TTime ltable_lerp(float fh, LCol C, float a00, float b00, float a10, float b10,
+                                             float a01, float b01, float a11, float b11) {
+    const float d00 = fh * (b00 - a00);
+    const float d10 = fmaf(fh, b10 - a10, a10 - a00);
+    const float d01 = fmaf(fh, b01 - a01, a01 - a00);
+    const float d11 = fmaf(fh, b11 - a11, a11 - a00);
+    const float t0 = fmaf(C.fx, d10 - d00, d00), t1 = fmaf(C.fx, d11 - d01, d01);
+    return TTime{a00, fmaf(C.fy, t1 - t0, t0)};
+}
+
+__device__ __forceinline__ TTime ltable_time(const Params& P, TLeg L, LCol C, int iz) {
     const int vo = (C.off + L.off + iz) * 4;
     const int nz = 4 * P.nz, dx = 4 * P.ldx, dy = 4 * P.ldy;  // byte offsets (scalar)
-    const double fh = L.f;
     const float a00 = table_read(P, vo, 0), b00 = table_read(P, vo, nz);
     const float a10 = table_read(P, vo, dx), b10 = table_read(P, vo, dx + nz);
     const float a01 = table_read(P, vo, dy), b01 = table_read(P, vo, dy + nz);
     const float a11 = table_read(P, vo, dx + dy), b11 = table_read(P, vo, dx + dy + nz);
-    const double t00 = fma(fh, static_cast<double>(b00 - a00), static_cast<double>(a00));
-    const double t10 = fma(fh, static_cast<double>(b10 - a10), static_cast<double>(a10));
-    const double t01 = fma(fh, static_cast<double>(b01 - a01), static_cast<double>(a01));
-    const double t11 = fma(fh, static_cast<double>(b11 - a11), static_cast<double>(a11));
-    const double fx = C.fx, fy = C.fy;
-    const double t0 = fma(fx, t10 - t00, t00), t1 = fma(fx, t11 - t01, t01);
-    return fma(fy, t1 - t0, t0);
+    return ltable_lerp(L.f, C, a00, b00, a10, b10, a01, b01, a11, b11);
 }
 
 // ltable_time with an extended leg (the h fraction and the differences in float64).
@@ -443,16 +466,43 @@ __device__ __forceinline__ float table_amp(const Params& P, int off, float fh, L
 // Two adjacent depths iz, iz + 1 of one leg (the adjoint's interleaved slot
 // pairs in full depth chunks, iz + 1 < nz): one 8-byte read per row and node
 // gives both, where table_time / ltable_time read one value per read.  The
-// arithmetic is theirs (XF: that of the extended forms), so each depth's time
-// has the same bits as the single-depth functions give.
+// arithmetic is theirs, so each depth's time has the same bits as the
+// single-depth functions give: table_time_pair2 for float32 legs,
+// table_time_pair for the extended forms (table_time_ext, ltable_time_ext).
 struct Dbl2 {
     double a, b;
 };
 struct Flt2 {
     float a, b;
 };
+struct TTime2 {
+    TTime a, b;
+};
 
-template <bool LAT, bool XF>
+template <bool LAT>
+__device__ __forceinline__ TTime2 table_time_pair2(const Params& P, int off, float fh, LCol C, int iz) {
+    const __amdgpu_buffer_rsrc_t R = raw_buffer(P.ttab, P.ttab_bytes);
+    const int vo = ((LAT ? C.off : 0) + off + iz) * 4;
+    const int nz = 4 * P.nz;
+    auto rows = [&](int so, float2& a, float2& b) {
+        const auto va = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so, 0);       // row ih: iz, iz + 1
+        const auto vb = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so + nz, 0);  // row ih + 1
+        a = make_float2(__uint_as_float(va[0]), __uint_as_float(va[1]));
+        b = make_float2(__uint_as_float(vb[0]), __uint_as_float(vb[1]));
+    };
+    float2 a00, b00;
+    rows(0, a00, b00);
+    if (!LAT) return TTime2{TTime{a00.x, fh * (b00.x - a00.x)}, TTime{a00.y, fh * (b00.y - a00.y)}};
+    const int dx = 4 * P.ldx, dy = 4 * P.ldy;
+    float2 a10, b10, a01, b01, a11, b11;
+    rows(dx, a10, b10);
+    rows(dy, a01, b01);
+    rows(dx + dy, a11, b11);
+    return TTime2{ltable_lerp(fh, C, a00.x, b00.x, a10.x, b10.x, a01.x, b01.x, a11.x, b11.x),
+                  ltable_lerp(fh, C, a00.y, b00.y, a10.y, b10.y, a01.y, b01.y, a11.y, b11.y)};
+}
+
+template <bool LAT>
 __device__ __forceinline__ Dbl2 table_time_pair(const Params& P, int off, double fh, LCol C, int iz) {
     const __amdgpu_buffer_rsrc_t R = raw_buffer(P.ttab, P.ttab_bytes);
     const int vo = ((LAT ? C.off : 0) + off + iz) * 4;
@@ -460,18 +510,9 @@ __device__ __forceinline__ Dbl2 table_time_pair(const Params& P, int off, double
     auto node = [&](int so) {
         const auto a = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so, 0);       // row ih: iz, iz + 1
         const auto b = __builtin_amdgcn_raw_buffer_load_b64(R, vo, so + nz, 0);  // row ih + 1
-        const float a0 = __uint_as_float(a[0]), a1 = __uint_as_float(a[1]);
-        const float b0 = __uint_as_float(b[0]), b1 = __uint_as_float(b[1]);
-        Dbl2 t;
-        if (XF) {
-            const double da0 = a0, da1 = a1, db0 = b0, db1 = b1;
-            t.a = fma(fh, db0 - da0, da0);
-            t.b = fma(fh, db1 - da1, da1);
-        } else {
-            t.a = fma(fh, static_cast<double>(b0 - a0), static_cast<double>(a0));
-            t.b = fma(fh, static_cast<double>(b1 - a1), static_cast<double>(a1));
-        }
-        return t;
+        const double da0 = __uint_as_float(a[0]), da1 = __uint_as_float(a[1]);
+        const double db0 = __uint_as_float(b[0]), db1 = __uint_as_float(b[1]);
+        return Dbl2{fma(fh, db0 - da0, da0), fma(fh, db1 - da1, da1)};
     };
     const Dbl2 t00 = node(0);
     if (!LAT) return t00;
@@ -546,8 +587,8 @@ template <bool TF, bool CLAMP = true, bool LAT = false>
 __device__ __forceinline__ Pair eval_pair_table(const Params& P, TLeg Ls, TLeg Lr, int iz, float tf_off, float wlo,
                                                 float whi, LCol C = LCol{0, 0.0f, 0.0f}) {
     (void)tf_off;
-    double w = (LAT ? ltable_time(P, Ls, C, iz) + ltable_time(P, Lr, C, iz)
-                    : table_time(P, Ls, iz) + table_time(P, Lr, iz)) * P.inv_dt;
+    double w = LAT ? pair_time(P, ltable_time(P, Ls, C, iz), ltable_time(P, Lr, C, iz))
+                   : pair_time(P, table_time(P, Ls, iz), table_time(P, Lr, iz));
     if (TF) w = w + P.tf_off_d;
     if (CLAMP) w = fmin(fmax(w, static_cast<double>(wlo)), static_cast<double>(whi));
     Pair p;
