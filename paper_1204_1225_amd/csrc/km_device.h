@@ -392,15 +392,15 @@ __device__ __forceinline__ LCol lateral_col(const Params& P, float px, float py)
     return C;
 }
 
-// One-way time on the laterally varying tables: the interpolation in h of
-// table_time on the four nodes around the column, then in x, then in y, each
-// a + f (b - a) in float64 (equal node tables give table_time exactly).
-// The trilinear time as a base and an increment (as table_time): the base is
-// node (i, j)'s value a00 at row ih, and every other term is taken relative to
-// it in float32.  Neighbouring nodes' times at one depth and row lie within a
-// factor of two of each other, so their differences from a00 are exact; the
-// interpolated increments are small, as in table_time.  Equal nodes give
-// table_time's bits (every difference between nodes is 0).
+// One-way time on the laterally varying tables: the interpolation in h on the
+// four nodes around the column, then in x, then in y, as a base and an
+// increment (as table_time).  The base is node (i, j)'s value a00 at row ih;
+// every other term is taken relative to it in float32.  Where neighbouring
+// nodes' times at one depth and row lie within a factor of two of each other
+// (any smooth medium) their differences from a00 are exact, otherwise such a
+// difference rounds once in float32; the interpolated increments are small,
+// as in table_time.  Equal nodes give table_time's bits (every difference
+// between nodes is 0).
 __device__ __forceinline__ TTime ltable_lerp(float fh, LCol C, float a00, float b00, float a10, float b10,
                                              float a01, float b01, float a11, float b11) {
     const float d00 = fh * (b00 - a00);
