@@ -362,9 +362,9 @@ km_status km_cig_moveout(const float* image, const km_grid* grid, const float* o
  * extra conversion per sample read): a migrate call with such a tile returns
  * KM_E_UNSUPPORTED for KM_F32 traces, KM_TIME_EXTENDED and the anti-alias
  * filter, and the batched calls refuse it (a tuned one becomes level 0 or 3
- * there); demigrate level 0 takes as many trace quads
- * per workgroup as the shape allows, level L >= 1 takes L quads (L at most the
- * shape's trace_quads). */
+ * there); demigrate level 0 takes as many trace quads per workgroup as the
+ * shape allows, level L >= 1 takes L quads (L at most the shape's
+ * trace_quads). */
 typedef struct km_tile_info {
     int32_t waves;            /* wavefronts (64 lanes) per workgroup */
     int32_t column_groups;    /* groups of 4 image columns per wavefront (migrate) */

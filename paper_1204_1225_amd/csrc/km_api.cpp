@@ -190,9 +190,9 @@ int shape_count(int op) { return op == 0 ? km::migrate_shape_count() : km::demig
 // trace block (traces per block): 1, 0.5, 1.5, 2 times the shape's, and levels
 // 4 and 5 stage 16-bit traces as their 16-bit storage (the S16 kernels) with 1
 // and 2 times the budget: twice the samples per byte of float staging.
-// Demigrate level 0 takes as
-// many trace quads per workgroup as the shape's budget and template allow;
-// level L >= 1 takes L quads (L <= the shape's quads).
+// Demigrate level 0 takes as many trace quads per workgroup as the shape's
+// budget and template allow; level L >= 1 takes L quads (L <= the shape's
+// quads).
 constexpr int kTileLevelStride = 64;
 constexpr int kMigrateLevels = 6;
 constexpr int kDemigrateLevels = 4;
