@@ -84,14 +84,18 @@ def test_s16_tables_every_shape(ops, oracle_lib, kind):
 def test_s16_unit_scales_give_the_float_staging_bits(ops, kind):
     # With scale 1 the widened samples are the staged floats, the scale factor
     # multiplies by 1 and the interpolation is the same FMA: bit for bit.
+    # A NULL scale (no scale array) means 1 on both kinds of tile.
     for p in (problem(CASES[0]), survey.with_curved_ray_table(problem(CASES[2]), dh=7.5)):
         dp = ops.to_device(p, dtype=kind)
+        dn = dp.with_data(dp.data, None, kind)
         dp = dp.with_data(dp.data, torch.ones_like(dp.scale), kind)
         for sh in range(ops.tile_count(0)):
             for lv_f, lv_s in ((0, 4), (3, 5)):
                 a = ops.migrate(dp, tile=sh + 64 * lv_f)
                 b = ops.migrate(dp, tile=sh + 64 * lv_s)
                 assert torch.equal(a, b), (sh, lv_s)
+                assert torch.equal(a, ops.migrate(dn, tile=sh + 64 * lv_f)), (sh, lv_f)
+                assert torch.equal(b, ops.migrate(dn, tile=sh + 64 * lv_s)), (sh, lv_s)
 
 
 def test_s16_survey3d_sampled(ops, oracle_lib):
