@@ -76,9 +76,11 @@ def test_tune_pick_persist_reload(ops, oracle_lib, tmp_path, kind):
         t1, ms1 = ops.tune(1, dp, m, traces_out=out, reps=1)
         print(f"{kind}: tuned migrate tile {t0} ({ms0:.3f} ms), demigrate tile {t1} ({ms1:.3f} ms)")
         assert ops.tune_lookup(0, dp) == t0 and ops.tune_lookup(1, dp) == t1
-        # tile -1 takes the tuned tile: the same bits as passing it
+        # tile -1 takes the tuned tile: the same bits as passing it (the
+        # adjoint's float64 atomics add in no fixed order: to an ulp or so)
         assert torch.equal(ops.migrate(dp), ops.migrate(dp, tile=t0))
-        assert torch.equal(ops.demigrate(dp, m), ops.demigrate(dp, m, tile=t1))
+        a, b = ops.demigrate(dp, m), ops.demigrate(dp, m, tile=t1)
+        assert float((a - b).abs().max()) <= 2.0 ** -22 * float(a.abs().max())
         assert rel_l2(ops.migrate(dp).cpu().numpy(), oracle_lib.migrate(p)) <= 1e-5
         assert rel_l2(ops.demigrate(dp, m).cpu().numpy(), oracle_lib.demigrate(p, m.cpu().numpy())) <= 1e-5
         # a fresh process reads the file and finds the same tiles for the class
