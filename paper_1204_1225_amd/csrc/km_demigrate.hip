@@ -74,6 +74,42 @@ __device__ __forceinline__ void dem_masked(float A0, float B0, float A1, float B
     }
 }
 
+// dem_masked with the taps of the slot pair's two depths (adjacent depths of
+// one lane: their samples i0 <= i1 are usually equal or neighbours) merged by
+// address: the values for i0 .. i0 + 3 are formed in float32 and added with
+// 2 atomics, a third where some lane's i1 = i0 + 1 or i0 + 2, a fourth where
+// some lane's i1 = i0 + 2.  A lane whose i1 - i0 lies outside [0, 2] adds its
+// second depth's taps separately.  A slot outside the aperture contributes 0
+// (and the base is the other slot's sample).
+template <bool TF, int WK>
+__device__ __forceinline__ void dem_merged(float A0, float B0, float A1, float B1, float hs2, float hr2, double* row,
+                                           float tfo, float wlo, float whi, float x0, float x1, bool act0, bool act1) {
+    const Pair p0 = eval_pair<TF, WK, true>(A0, B0, hs2, hr2, tfo, wlo, whi);
+    const Pair p1 = eval_pair<TF, WK, true>(A1, B1, hs2, hr2, tfo, wlo, whi);
+    const float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
+    const float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
+    const float b0 = p0.f * q0, b1 = p1.f * q1;
+    const float t0 = act0 ? q0 - b0 : 0.0f, t1 = act0 ? b0 : 0.0f;
+    const float t2 = act1 ? q1 - b1 : 0.0f, t3 = act1 ? b1 : 0.0f;
+    const int i0 = act0 ? p0.i : p1.i;
+    const int dd = p1.i - i0;
+    const bool near = dd >= 0 && dd <= 2;
+    const float m2 = near ? t2 : 0.0f, m3 = near ? t3 : 0.0f;  // the second depth's merged taps
+    const float v0 = t0 + (dd == 0 ? m2 : 0.0f);
+    const float v1 = t1 + (dd == 0 ? m3 : dd == 1 ? m2 : 0.0f);
+    const float v2 = dd == 1 ? m3 : dd == 2 ? m2 : 0.0f;
+    if (act0 || act1) {
+        atomicAdd(row + i0, static_cast<double>(v0));
+        atomicAdd(row + i0 + 1, static_cast<double>(v1));
+        if (act1 && (dd == 1 || dd == 2)) atomicAdd(row + i0 + 2, static_cast<double>(v2));
+        if (act1 && dd == 2) atomicAdd(row + i0 + 3, static_cast<double>(m3));
+        if (act1 && !near) {
+            atomicAdd(row + p1.i, static_cast<double>(t2));
+            atomicAdd(row + p1.i + 1, static_cast<double>(t3));
+        }
+    }
+}
+
 // dem_masked with the extended-precision time (eval_pair_ext); the two taps
 // are formed in float64 from the float64 fraction.
 template <bool TF, int WK>
@@ -392,7 +428,7 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
 #pragma unroll
             for (int k = 0; k < KS; k += 2) {
                 if (!((any >> k) & 3u)) continue;
-                dem_masked<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo, wlo, whi, x[k],
+                dem_merged<TF, WK>(T.A[k], T.B[k], T.A[k + 1], T.B[k + 1], L.hs2, L.hr2, row, tfo, wlo, whi, x[k],
                                    x[k + 1], L.hmax <= T.R[k], L.hmax <= T.R[k + 1]);
             }
         }
