@@ -54,33 +54,16 @@ __device__ __forceinline__ uint32_t fold_and(uint64_t m) {
     return static_cast<uint32_t>((m & (m >> 16) & (m >> 32) & (m >> 48)) & 0xFFFFull);
 }
 
-// Two slots with a per-lane aperture mask.
-template <bool TF, int WK>
-__device__ __forceinline__ void dem_masked(float A0, float B0, float A1, float B1, float hs2, float hr2, double* row,
-                                           float tfo, float wlo, float whi, float x0, float x1, bool act0, bool act1) {
-    if (act0) {
-        const Pair p0 = eval_pair<TF, WK, true>(A0, B0, hs2, hr2, tfo, wlo, whi);
-        const float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
-        const float b0 = p0.f * q0;
-        atomicAdd(row + p0.i, static_cast<double>(q0 - b0));
-        atomicAdd(row + p0.i + 1, static_cast<double>(b0));
-    }
-    if (act1) {
-        const Pair p1 = eval_pair<TF, WK, true>(A1, B1, hs2, hr2, tfo, wlo, whi);
-        const float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
-        const float b1 = p1.f * q1;
-        atomicAdd(row + p1.i, static_cast<double>(q1 - b1));
-        atomicAdd(row + p1.i + 1, static_cast<double>(b1));
-    }
-}
-
-// dem_masked with the taps of the slot pair's two depths (adjacent depths of
-// one lane: their samples i0 <= i1 are usually equal or neighbours) merged by
-// address: the values for i0 .. i0 + 3 are formed in float32 and added with
-// 2 atomics, a third where some lane's i1 = i0 + 1 or i0 + 2, a fourth where
-// some lane's i1 = i0 + 2.  A lane whose i1 - i0 lies outside [0, 2] adds its
-// second depth's taps separately.  A slot outside the aperture contributes 0
-// (and the base is the other slot's sample).
+// Two slots with a per-lane aperture mask, their taps merged by address.  The
+// two slots of a pair are adjacent depths of one lane, so their samples i0 and
+// i1 are usually equal or neighbours: the values for i0 .. i0 + 3 are summed
+// in float32 first and added with 2 float64 atomics, a third where some lane
+// has i1 = i0 + 1 or i0 + 2, and a fourth where some lane has i1 = i0 + 2
+// (instead of 4 for every pair).  A lane whose i1 - i0 lies outside [0, 2]
+// adds its second slot's taps separately.  A slot outside the aperture
+// contributes nothing (and the base is the other slot's sample).  The table,
+// extended-precision and anti-alias adjoints keep one pair of atomics per
+// slot: with their longer evaluation the merge cost more than it saved.
 template <bool TF, int WK>
 __device__ __forceinline__ void dem_merged(float A0, float B0, float A1, float B1, float hs2, float hr2, double* row,
                                            float tfo, float wlo, float whi, float x0, float x1, bool act0, bool act1) {
@@ -110,7 +93,7 @@ __device__ __forceinline__ void dem_merged(float A0, float B0, float A1, float B
     }
 }
 
-// dem_masked with the extended-precision time (eval_pair_ext); the two taps
+// Two slots with the extended-precision time (eval_pair_ext); the two taps
 // are formed in float64 from the float64 fraction.
 template <bool TF, int WK>
 __device__ __forceinline__ void dem_masked_ext(float A0, float B0, float A1, float B1, double Hs, double Hr,
@@ -211,7 +194,7 @@ __device__ __forceinline__ void dem_pair_table2(const Params& P, Leg Ls, Leg Lr,
     }
 }
 
-// dem_masked with table traveltimes (W = A_s A_r with amplitude tables, else
+// Two slots with table traveltimes (W = A_s A_r with amplitude tables, else
 // 1); iz0, iz1 are the lane's depths of the two slots, clamped into the table.  LAT: laterally varying tables, C
 // the column on the node grid.
 template <bool TF, bool MASKED, bool LAT>
