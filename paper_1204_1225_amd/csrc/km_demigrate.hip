@@ -69,26 +69,28 @@ __device__ __forceinline__ void dem_merged(float A0, float B0, float A1, float B
                                            float tfo, float wlo, float whi, float x0, float x1, bool act0, bool act1) {
     const Pair p0 = eval_pair<TF, WK, true>(A0, B0, hs2, hr2, tfo, wlo, whi);
     const Pair p1 = eval_pair<TF, WK, true>(A1, B1, hs2, hr2, tfo, wlo, whi);
-    const float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
-    const float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
+    float q0 = (WK == W_COSCOS) ? x0 * p0.r : x0;
+    float q1 = (WK == W_COSCOS) ? x1 * p1.r : x1;
+    q0 = act0 ? q0 : 0.0f;  // a slot outside the aperture: both taps 0
+    q1 = act1 ? q1 : 0.0f;
     const float b0 = p0.f * q0, b1 = p1.f * q1;
-    const float t0 = act0 ? q0 - b0 : 0.0f, t1 = act0 ? b0 : 0.0f;
-    const float t2 = act1 ? q1 - b1 : 0.0f, t3 = act1 ? b1 : 0.0f;
+    const float t0 = q0 - b0, t2 = q1 - b1;
     const int i0 = act0 ? p0.i : p1.i;
     const int dd = p1.i - i0;
-    const bool near = dd >= 0 && dd <= 2;
-    const float m2 = near ? t2 : 0.0f, m3 = near ? t3 : 0.0f;  // the second depth's merged taps
-    const float v0 = t0 + (dd == 0 ? m2 : 0.0f);
-    const float v1 = t1 + (dd == 0 ? m3 : dd == 1 ? m2 : 0.0f);
-    const float v2 = dd == 1 ? m3 : dd == 2 ? m2 : 0.0f;
+    const bool e0 = dd == 0, e1 = dd == 1, e2 = dd == 2;  // none: the second slot's taps go separately
+    const float v0 = t0 + (e0 ? t2 : 0.0f);
+    const float v1 = b0 + (e0 ? b1 : e1 ? t2 : 0.0f);
+    const float v2 = e1 ? b1 : t2;  // at i0 + 2 (e1 or e2)
     if (act0 || act1) {
         atomicAdd(row + i0, static_cast<double>(v0));
         atomicAdd(row + i0 + 1, static_cast<double>(v1));
-        if (act1 && (dd == 1 || dd == 2)) atomicAdd(row + i0 + 2, static_cast<double>(v2));
-        if (act1 && dd == 2) atomicAdd(row + i0 + 3, static_cast<double>(m3));
-        if (act1 && !near) {
-            atomicAdd(row + p1.i, static_cast<double>(t2));
-            atomicAdd(row + p1.i + 1, static_cast<double>(t3));
+        if (act1) {
+            if (e1 || e2) atomicAdd(row + i0 + 2, static_cast<double>(v2));
+            if (e2) atomicAdd(row + i0 + 3, static_cast<double>(b1));
+            if (!(e0 || e1 || e2)) {
+                atomicAdd(row + p1.i, static_cast<double>(t2));
+                atomicAdd(row + p1.i + 1, static_cast<double>(b1));
+            }
         }
     }
 }
