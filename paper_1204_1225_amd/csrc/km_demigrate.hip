@@ -503,11 +503,11 @@ __device__ __forceinline__ void demigrate_segment(const Params& P, int b, int t0
 }
 
 // The 4-slot square-root kernels are held to 6 wavefronts per SIMD (80 VGPRs;
-// no spills in the float32 kernel, about 20 registers spilled in the
-// extended-precision one, which ran 2.38 s against 2.56 s at its natural 108 on
-// the 3D survey): with 8-wavefront one-quad workgroups that is three workgroups
-// per CU, as many as their LDS rows allow.  The other kernels need more
-// registers.
+// the float32 kernel spills 3 registers in its set-up, outside the column
+// loop; the extended-precision one about 20, and ran 2.38 s against 2.56 s at
+// its natural 108 on the 3D survey): with 8-wavefront one-quad workgroups that
+// is three workgroups per CU, as many as their LDS rows allow.  The other
+// kernels need more registers.
 template <int NW, int KS, int NQ, bool TF, int WK, int TT = TT_DSR, bool PX = false>
 __global__ __launch_bounds__(NW * 64) __attribute__((amdgpu_waves_per_eu(KS <= 4 && TT == TT_DSR ? 6 : 1)))
 void demigrate_kernel(Params P) {
