@@ -56,12 +56,12 @@ __device__ __forceinline__ uint32_t fold_and(uint64_t m) {
 
 // Two slots with a per-lane aperture mask, their taps merged by address.  The
 // two slots of a pair are adjacent depths of one lane, so their samples i0 and
-// i1 are usually equal or neighbours: the values for i0 .. i0 + 3 are summed
-// in float32 first and added with 2 float64 atomics, a third where some lane
-// has i1 = i0 + 1 or i0 + 2, and a fourth where some lane has i1 = i0 + 2
-// (instead of 4 for every pair).  A lane whose i1 - i0 lies outside [0, 2]
-// adds its second slot's taps separately.  A slot outside the aperture
-// contributes nothing (and the base is the other slot's sample).  The table,
+// i1 are usually equal or neighbours: the second slot's taps that land on i0
+// or i0 + 1 are summed (in float32) into the first slot's, which go out as 2
+// float64 atomics; its tap at i1 + 1 needs a third atomic where some lane has
+// i1 != i0, its tap at i1 a fourth where some lane has i1 > i0 + 1 (instead
+// of 4 atomics for every pair).  A slot outside the aperture contributes
+// nothing (its value is zeroed; its clamped sample is still a valid base).  The table,
 // extended-precision and anti-alias adjoints keep one pair of atomics per
 // slot: with their longer evaluation the merge cost more than it saved.
 template <bool TF, int WK>
@@ -75,22 +75,15 @@ __device__ __forceinline__ void dem_merged(float A0, float B0, float A1, float B
     q1 = act1 ? q1 : 0.0f;
     const float b0 = p0.f * q0, b1 = p1.f * q1;
     const float t0 = q0 - b0, t2 = q1 - b1;
-    const int i0 = act0 ? p0.i : p1.i;
-    const int dd = p1.i - i0;
-    const bool e0 = dd == 0, e1 = dd == 1, e2 = dd == 2;  // none: the second slot's taps go separately
-    const float v0 = t0 + (e0 ? t2 : 0.0f);
-    const float v1 = b0 + (e0 ? b1 : e1 ? t2 : 0.0f);
-    const float v2 = e1 ? b1 : t2;  // at i0 + 2 (e1 or e2)
+    const bool e0 = p1.i == p0.i, e1 = p1.i == p0.i + 1;
+    const float v0 = t0 + (e0 ? t2 : 0.0f);                // at i0
+    const float v1 = b0 + (e0 ? b1 : e1 ? t2 : 0.0f);      // at i0 + 1
     if (act0 || act1) {
-        atomicAdd(row + i0, static_cast<double>(v0));
-        atomicAdd(row + i0 + 1, static_cast<double>(v1));
-        if (act1) {
-            if (e1 || e2) atomicAdd(row + i0 + 2, static_cast<double>(v2));
-            if (e2) atomicAdd(row + i0 + 3, static_cast<double>(b1));
-            if (!(e0 || e1 || e2)) {
-                atomicAdd(row + p1.i, static_cast<double>(t2));
-                atomicAdd(row + p1.i + 1, static_cast<double>(b1));
-            }
+        atomicAdd(row + p0.i, static_cast<double>(v0));
+        atomicAdd(row + p0.i + 1, static_cast<double>(v1));
+        if (act1 && !e0) {
+            atomicAdd(row + p1.i + 1, static_cast<double>(b1));       // i0 + 2 when i1 = i0 + 1
+            if (!e1) atomicAdd(row + p1.i, static_cast<double>(t2));  // i0 + 2 when i1 = i0 + 2
         }
     }
 }
