@@ -372,7 +372,14 @@ def model_scatterers(problem: Problem, scat: np.ndarray, f_peak: float = 25.0,
         ok = (idx >= 0) & (idx < nt)
         rows = torch.arange(j0, j1, device=dev, dtype=torch.int64)[:, None, None] * nt
         flat = (rows + idx)[ok]
-        out.index_add_(0, flat, val[ok].to(torch.float32))
+        # overlapping wavelets: the deterministic (sorted) scatter keeps the
+        # float32 sums, and so the samples, the same from run to run on a GPU
+        was = torch.are_deterministic_algorithms_enabled()
+        torch.use_deterministic_algorithms(True)
+        try:
+            out.index_add_(0, flat, val[ok].to(torch.float32))
+        finally:
+            torch.use_deterministic_algorithms(was)
     return out.view(n, nt)
 
 
