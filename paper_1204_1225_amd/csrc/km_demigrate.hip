@@ -334,7 +334,8 @@ __device__ __forceinline__ void sweep_columns(const Params& P, const float* img,
         const float* x = c.x;
 #pragma unroll
         for (int q = 0; q < NQ; ++q) {
-            if (q >= nq) break;
+            // a segment holds at least one trace, so quad 0 always exists
+            if (q > 0 && q >= nq) break;
             const Legs L = legs(px, py, G[q]);
             // lanes d >= KS hold rhi = -inf and rlo = +inf; kMask drops their bits
             const uint32_t any = fold_or(__builtin_amdgcn_ballot_w64(L.hmax <= T.rhi)) & kMask;
